@@ -1,0 +1,165 @@
+"""Benchmark of the FSB hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload: one school of N = 2^24 fish (x, y uniform in the 200x200 pond,
+weights in [1, 2], seed 0), advanced by per-iteration fsb_step launches (two
+streaming kernels per iteration).  A "step" is one FSB iteration over the
+whole school: swim, objective, max |diff|, feeding and barycentre sums.
+`value` is fish-updates/s = N * K / wall time of K iterations, with the
+school resident in HBM.  Prints ONE JSON line on stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per fish of each plain kernel (float32 columns).
+BYTES_PER_FISH = {
+    "swim_eval": 12 + 16,  # reads x, y, cur; writes x, y, prev, cur
+    "feed_bary": 20 + 4,   # reads prev, cur, w, x, y; writes w
+}
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2507_20173_amd", "csrc", "fsb_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plain_n16777216.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for name in ("fsb_kernels.hip", "fsb_device.hpp", "fsb_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2507_20173_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, n_fish: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    if it was taken from the current kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except OSError:
+        return None
+    if t.get("source_digest") != source_digest() or t.get("n_fish") != n_fish:
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def plain_run(n: int, steps: int, warmup: int):
+    import torch
+
+    import paper_2507_20173_amd as fsb
+
+    cfg = fsb.FsbConfig(n_fish=n, seed=0, history_len=1)
+    sch = fsb.School(cfg)
+    sch.run(warmup)
+    sch.sync()
+    fsb.fsb_profile_enable(sch.h, True)
+    fsb.fsb_kernel_times(sch.h)  # reset counters
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sch.run(steps)
+    sch.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    counts, ms = fsb.fsb_kernel_times(sch.h)
+    xy, sums = sch.barycentre()
+    sch.close()
+    kernels = {}
+    for name, kind in (("swim_eval", fsb.FSB_KERNEL_SWIM_EVAL),
+                       ("feed_bary", fsb.FSB_KERNEL_FEED_BARY)):
+        c = int(counts[kind])
+        avg_s = ms[kind] / 1e3 / max(c, 1)
+        nbytes = BYTES_PER_FISH[name] * n
+        kernels[name] = {"launches": c, "avg_us": avg_s * 1e6,
+                         "algorithmic_bytes_per_launch": nbytes,
+                         "achieved_GBs": nbytes / avg_s / 1e9}
+    return wall, kernels, xy
+
+
+def cpu_baseline(n: int, budget_s: float = 12.0, max_steps: int = 40):
+    """The oracle as it stands, on this host's cores, on a bounded prefix of
+    the same workload."""
+    from oracle.oracle import Config, default
+
+    O = default()
+    cfg = Config(numFish=n, seed=0)
+    school = O.init(cfg)
+    done, t0 = 0, time.perf_counter()
+    while done < max_steps and time.perf_counter() - t0 < budget_s:
+        O.step(cfg, school, done)
+        done += 1
+    el = time.perf_counter() - t0
+    return {"value": n * done / el, "unit": "fish-updates/s", "cores": O.max_threads(),
+            "kind": "oracle",
+            "sample": f"first {done} iterations of the same school (N={n}, seed 0), binary32 "
+                      f"oracle with binary64 reference sums, {el:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n-fish", type=int, default=1 << 24)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        log(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+            "the school would shard across GPUs with one small all-gather per iteration, "
+            "which is not built.")
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        log("bench.py needs a GPU")
+        return 1
+    n = args.n_fish
+    wall, kernels, xy = plain_run(n, args.steps, args.warmup)
+    value = n * args.steps / wall
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"])
+    dk = kernels[dom]
+    traffic = measured_traffic(dom, n)
+    line = {
+        "metric": "fish-updates/sec (N x steps/s) on 1 MI355X + % of HBM peak; fused vs plain",
+        "value": value,
+        "unit": "fish-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "plain FSB, one school: N=2^24 fish, 1000 iterations, "
+                               "per-iteration fsb_step launches (swim pass + feed pass)",
+                   "n_fish": n, "iterations": args.steps, "seed": 0, "mode": "plain"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk["achieved_GBs"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": dk["achieved_GBs"] / HBM_PEAK_GBS, "traffic": traffic},
+        "kernels": kernels,
+        "hbm_frac_whole_step": (sum(BYTES_PER_FISH.values()) * n * args.steps / wall / 1e9)
+        / HBM_PEAK_GBS,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(n)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,212 @@
+/*
+ * fsb.h -- C ABI of libfsb, the MI355X (gfx950) Fish School Behaviour step.
+ *
+ * The method (arXiv 2507.20173, "High-Performance Parallel Optimization of
+ * the Fish School Behaviour on the Setonix Platform Using OpenMP"):
+ *   - each fish carries {x, y, weight, prevObjective, currentObjective}
+ *     (Sec. 2.1.1); here they are five float32 structure-of-arrays columns
+ *     x[], y[], w[], prev[], cur[];
+ *   - the pond is 200x200 (Sec. 2.1.2), read as [-H, H]^2 centred at the
+ *     origin, H = 100;
+ *   - positions and weights start random; the objective is the Euclidean
+ *     distance from the pond centre (Sec. 2.1.1);
+ *   - every iteration each fish swims a random step and is re-evaluated
+ *     (Sec. 2.1.2), then eat() takes diff = prevObjective - currentObjective
+ *     and its school-wide maximum (the Reduction Construct, Sec. 2.3.2,
+ *     Experiment 3), which normalises the weight update;
+ *   - the school's weighted barycentre (sum w*x / sum w, sum w*y / sum w).
+ * Readings where the paper is silent (swim rule, feeding formula, weight
+ * limits, random generator):
+ *   iteration t, fish i:
+ *     (a, b)  = two words of Philox4x32-10 (Salmon et al., SC'11) with key =
+ *               seed and counter = (pair lo, pair hi, t, 0), pair = i >> 1;
+ *               fish i takes words 2(i&1) and 2(i&1)+1
+ *     v(r)    = (r >> 8) * 2^-23 - 1, exact, in [-1, 1)
+ *     x       = min(max(x + S*v(a), -H), H);  y likewise with v(b)
+ *     prev    = cur;  cur = sqrtf(x*x + y*y)
+ *     diff    = prev - cur;   M = max over the school of |diff|
+ *     w       = min(max(w + diff / M, w_min), w_max)   if M > 0, else w kept
+ *     sums    = (sum w, sum w*x, sum w*y) over the post-feed state
+ *   every float operation is binary32 round-to-nearest-even, rounded on its
+ *   own (no fused multiply-add), with correctly rounded sqrtf and division
+ *   and no flush to zero: per-fish state is bit-exact and reproducible.
+ *   Initial state: counter (pair, 0, 1) gives x = H*v(a), y = H*v(b);
+ *   counter (pair, 1, 1) gives w = lo + (hi - lo) * u(a), u(r) = (r >> 8) *
+ *   2^-24; cur = prev = sqrtf(x*x + y*y).
+ *
+ * Conventions for every entry point:
+ *   - Device pointers are caller-owned (allocated by the caller, e.g. with
+ *     PyTorch); the library never allocates, frees or retains device memory
+ *     beyond the handle's lifetime.  Arrays are 16-byte aligned, hold at
+ *     least n_fish floats and do not overlap.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All work is enqueued on it; calls are asynchronous unless documented
+ *     as synchronising.
+ *   - Every call returns FSB_OK (0) or a negative FSB_ERR_* code; arguments
+ *     are checked on the host before anything is enqueued, so an invalid
+ *     call has no effect.  fsb_last_error() returns a message for the last
+ *     failure on the calling thread.  No C++ exception crosses the ABI.
+ *   - A handle is used by one host thread at a time.
+ */
+#ifndef FSB_H
+#define FSB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FSB_ABI_VERSION 1
+
+/* Return codes. */
+#define FSB_OK 0
+#define FSB_ERR_INVALID_ARG (-1) /* bad pointer, size, alignment or value */
+#define FSB_ERR_HIP (-2)         /* the HIP runtime reported an error      */
+#define FSB_ERR_UNSUPPORTED (-3) /* e.g. persistent grid cannot be resident */
+#define FSB_ERR_STATE (-4)       /* call not valid in the handle's state   */
+#define FSB_ERR_DEVICE (-5)      /* a kernel reported a failure (barrier timeout) */
+
+/* fsb_config.reduce_mode: how the barycentre sums are reduced. */
+#define FSB_REDUCE_COMPENSATED 0u /* per-lane compensated (TwoSum) float32, binary64 cross-block combine, fixed order */
+#define FSB_REDUCE_NAIVE_F32 1u   /* float32 block trees + float32 atomicAdd (accuracy baseline) */
+
+/* fsb_run modes. */
+#define FSB_RUN_PLAIN 0u /* one fsb_step (two kernels) per iteration */
+#define FSB_RUN_FUSED 1u /* one persistent launch with a grid barrier per iteration */
+
+typedef struct fsb_config {
+    uint64_t n_fish;      /* fish in the school, >= 1 */
+    uint64_t seed;        /* Philox key */
+    float pond_half;      /* H > 0: the pond is [-H, H]^2 (Sec. 2.1.2: 200x200 -> 100) */
+    float swim_step;      /* S >= 0: per-axis displacement in [-S, S); 0 = zero swim */
+    float w_init_lo;      /* initial weights in [lo, hi], lo <= hi */
+    float w_init_hi;
+    float w_min;          /* weight limits applied by feeding, w_min <= w_max */
+    float w_max;
+    uint32_t reduce_mode; /* FSB_REDUCE_* */
+    uint32_t history_len; /* per-iteration records kept, >= 1 (a ring) */
+} fsb_config;
+
+/* The school's state: five float32 columns of n_fish (caller-owned device
+ * memory).  For a batch of schools the columns are packed school after
+ * school (see fsb_batch_init). */
+typedef struct fsb_state {
+    float *x;
+    float *y;
+    float *w;
+    float *prev;
+    float *cur;
+} fsb_state;
+
+/* What one iteration reduced, as kept in the workspace ring. */
+typedef struct fsb_record {
+    double sum_w;     /* sum of post-feed weights */
+    double sum_wx;    /* sum of w*x */
+    double sum_wy;    /* sum of w*y */
+    float max_delta;  /* M = max |prev - cur| (exact) */
+    uint32_t step_lo; /* low 32 bits of the iteration index it belongs to */
+} fsb_record;
+
+typedef struct fsb_school fsb_school; /* opaque host-side handle */
+
+/* ---- errors ------------------------------------------------------------ */
+
+/* Static text for a return code. */
+const char *fsb_strerror(int code);
+/* Message of the last failing call on this thread ("" if none). */
+const char *fsb_last_error(void);
+int fsb_abi_version(void);
+
+/* ---- one school -------------------------------------------------------- */
+
+/* Bytes of device workspace a school with this config needs (256-byte
+ * aligned start).  Pure host arithmetic.  Returns FSB_ERR_INVALID_ARG for a
+ * bad config. */
+int fsb_workspace_bytes(const fsb_config *cfg, size_t *out_bytes);
+
+/* Initialisation (Sec. 2.1.1: random position and weight; objective = the
+ * distance from the pond centre): writes all five columns from the init
+ * draws, clears the workspace's control words, and returns a handle at
+ * iteration t = 0.  `workspace` is caller-owned device memory of at least
+ * fsb_workspace_bytes, 256-byte aligned, used by this handle only.  The
+ * handle copies `cfg` and the pointers; the memory must outlive it.
+ * Asynchronous. */
+int fsb_init(const fsb_config *cfg, fsb_state state, void *workspace,
+             size_t workspace_bytes, void *stream, fsb_school **out);
+
+/* Wrap existing state (resume from a checkpoint, or a hand-made school) at
+ * iteration `t`, without writing the columns.  cur should equal
+ * sqrtf(x*x + y*y) and prev the objective before the last swim, as after
+ * fsb_step.  Clears the control words.  Asynchronous. */
+int fsb_attach(const fsb_config *cfg, fsb_state state, void *workspace,
+               size_t workspace_bytes, void *stream, uint64_t t,
+               fsb_school **out);
+
+/* One iteration t (swim, objective, diff, school max, feeding, barycentre
+ * sums; Sec. 2.1.2 and eat() of Sec. 2.3.2) as two kernels on the stream;
+ * the record goes to slot t mod history_len; t advances.  Asynchronous.
+ * FSB_ERR_INVALID_ARG once t reaches 2^32 (the counter word is 32 bits). */
+int fsb_step(fsb_school *h);
+
+/* n_steps iterations.  FSB_RUN_PLAIN issues fsb_step n_steps times;
+ * FSB_RUN_FUSED runs them in persistent launches with a grid barrier per
+ * iteration.  Both give bit-identical columns and maxima (the sums agree to
+ * rounding; each mode is deterministic).  Asynchronous; FSB_ERR_UNSUPPORTED
+ * if the fused grid cannot be co-resident. */
+int fsb_run(fsb_school *h, uint64_t n_steps, uint32_t mode);
+
+/* Test hook: one iteration with the displacements dx[n_fish], dy[n_fish]
+ * (device float32) used in place of the Philox draws.  t advances.
+ * Asynchronous. */
+int fsb_step_displaced(fsb_school *h, const float *dx, const float *dy);
+
+/* Barycentre of the last completed iteration: out_xy = (sum w*x / sum w,
+ * sum w*y / sum w) in binary64; out_sums3 (nullable) = the three sums.
+ * Synchronises the stream.  FSB_ERR_STATE before the first iteration;
+ * FSB_ERR_DEVICE if a kernel reported a failure. */
+int fsb_barycentre(fsb_school *h, double out_xy[2], double *out_sums3);
+
+/* M = max |diff| of the last completed iteration.  Synchronises. */
+int fsb_max_delta(fsb_school *h, float *out_max);
+
+/* Records of iterations [first, first + count): each must still be in the
+ * ring (t - history_len <= first, first + count <= t).  Synchronises. */
+int fsb_history(fsb_school *h, uint64_t first, uint64_t count,
+                fsb_record *out);
+
+/* Wait for the handle's work; reports asynchronous HIP or kernel errors. */
+int fsb_sync(fsb_school *h);
+
+/* Current iteration index (the next iteration fsb_step will run). */
+int fsb_step_index(const fsb_school *h, uint64_t *out_t);
+
+/* Move the iteration index (resume); clears the pending maximum slot.
+ * Asynchronous. */
+int fsb_set_step_index(fsb_school *h, uint64_t t);
+
+/* Free the handle (host memory only; the caller frees device memory after
+ * the stream's work is done). */
+int fsb_destroy(fsb_school *h);
+
+/* ---- instrumentation --------------------------------------------------- */
+
+/* Kernel timing: when enabled, every kernel the handle launches is
+ * bracketed by HIP events on its stream.  fsb_kernel_times synchronises and
+ * returns, per kernel kind (FSB_KERNEL_*), the number of launches and their
+ * summed duration in milliseconds since the previous read (reading resets
+ * the counts). */
+#define FSB_KERNEL_SWIM_EVAL 0 /* plain pass 1: swim, objective, max |diff| */
+#define FSB_KERNEL_FEED_BARY 1 /* plain pass 2: feeding, barycentre sums */
+#define FSB_KERNEL_FUSED 2     /* persistent multi-iteration kernel */
+#define FSB_KERNEL_INIT 3
+#define FSB_KERNEL_KINDS 4
+int fsb_profile_enable(fsb_school *h, int enable);
+int fsb_kernel_times(fsb_school *h, uint64_t counts[FSB_KERNEL_KINDS],
+                     double ms[FSB_KERNEL_KINDS]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

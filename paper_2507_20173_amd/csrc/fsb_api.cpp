@@ -1,0 +1,454 @@
+// fsb_api.cpp -- the C ABI of libfsb (declared in include/fsb.h): argument
+// checks, handles, launch sequencing, result read-back, kernel timing.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "fsb.h"
+#include "fsb_internal.hpp"
+
+using namespace fsb;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+    return FSB_ERR_HIP;
+}
+
+#define FSB_HIP_TRY(expr, what)                 \
+    do {                                        \
+        hipError_t e_ = (expr);                 \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+constexpr uint64_t kMaxFish = 1ull << 40;
+constexpr uint32_t kMaxHistory = 1u << 24;
+constexpr uint64_t kStepLimit = 1ull << 32;  // iteration index fills one counter word
+
+int check_config(const fsb_config* c, bool need_fish) {
+    if (!c) return fail(FSB_ERR_INVALID_ARG, "config is NULL");
+    if (need_fish && c->n_fish == 0) return fail(FSB_ERR_INVALID_ARG, "n_fish must be >= 1");
+    if (c->n_fish > kMaxFish) return fail(FSB_ERR_INVALID_ARG, "n_fish exceeds 2^40");
+    if (!(std::isfinite(c->pond_half) && c->pond_half > 0.0f))
+        return fail(FSB_ERR_INVALID_ARG, "pond_half must be finite and > 0");
+    if (!(std::isfinite(c->swim_step) && c->swim_step >= 0.0f))
+        return fail(FSB_ERR_INVALID_ARG, "swim_step must be finite and >= 0");
+    if (!(std::isfinite(c->w_init_lo) && std::isfinite(c->w_init_hi) && c->w_init_lo <= c->w_init_hi))
+        return fail(FSB_ERR_INVALID_ARG, "need finite w_init_lo <= w_init_hi");
+    if (!(std::isfinite(c->w_min) && std::isfinite(c->w_max) && c->w_min <= c->w_max))
+        return fail(FSB_ERR_INVALID_ARG, "need finite w_min <= w_max");
+    if (c->reduce_mode != FSB_REDUCE_COMPENSATED && c->reduce_mode != FSB_REDUCE_NAIVE_F32)
+        return fail(FSB_ERR_INVALID_ARG, "unknown reduce_mode");
+    if (c->history_len == 0 || c->history_len > kMaxHistory)
+        return fail(FSB_ERR_INVALID_ARG, "history_len must be in [1, 2^24]");
+    return FSB_OK;
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int check_columns(const fsb_state& s, uint64_t n) {
+    const float* cols[5] = {s.x, s.y, s.w, s.prev, s.cur};
+    const char* names[5] = {"x", "y", "w", "prev", "cur"};
+    for (int i = 0; i < 5; ++i) {
+        if (!cols[i]) return fail(FSB_ERR_INVALID_ARG, std::string("column ") + names[i] + " is NULL");
+        if (!aligned(cols[i], 16))
+            return fail(FSB_ERR_INVALID_ARG, std::string("column ") + names[i] + " is not 16-byte aligned");
+    }
+    const uintptr_t bytes = (uintptr_t)n * sizeof(float);
+    for (int i = 0; i < 5; ++i)
+        for (int j = i + 1; j < 5; ++j) {
+            const uintptr_t a = reinterpret_cast<uintptr_t>(cols[i]);
+            const uintptr_t b = reinterpret_cast<uintptr_t>(cols[j]);
+            if (a < b + bytes && b < a + bytes)
+                return fail(FSB_ERR_INVALID_ARG, std::string("columns ") + names[i] + " and " +
+                                                     names[j] + " overlap");
+        }
+    return FSB_OK;
+}
+
+int check_workspace(void* ws, size_t bytes, size_t need) {
+    if (!ws) return fail(FSB_ERR_INVALID_ARG, "workspace is NULL");
+    if (!aligned(ws, kAlign)) return fail(FSB_ERR_INVALID_ARG, "workspace is not 256-byte aligned");
+    if (bytes < need)
+        return fail(FSB_ERR_INVALID_ARG, "workspace too small: " + std::to_string(bytes) + " < " +
+                                             std::to_string(need) + " bytes");
+    return FSB_OK;
+}
+
+// Pairs of HIP events bracketing launches of one kernel kind.
+struct Timer {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+    size_t used = 0;
+    ~Timer() {
+        for (auto& p : pool) {
+            (void)hipEventDestroy(p.first);
+            (void)hipEventDestroy(p.second);
+        }
+    }
+    hipError_t next(std::pair<hipEvent_t, hipEvent_t>** out) {
+        if (used == pool.size()) {
+            std::pair<hipEvent_t, hipEvent_t> p{nullptr, nullptr};
+            hipError_t e = hipEventCreate(&p.first);
+            if (e != hipSuccess) return e;
+            e = hipEventCreate(&p.second);
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(p.first);
+                return e;
+            }
+            pool.push_back(p);
+        }
+        *out = &pool[used++];
+        return hipSuccess;
+    }
+    hipError_t total(double* ms) {
+        double sum = 0.0;
+        for (size_t i = 0; i < used; ++i) {
+            float v = 0.0f;
+            hipError_t e = hipEventElapsedTime(&v, pool[i].first, pool[i].second);
+            if (e != hipSuccess) return e;
+            sum += v;
+        }
+        *ms = sum;
+        return hipSuccess;
+    }
+};
+
+}  // namespace
+
+struct fsb_school {
+    fsb_config cfg;
+    fsb_state st;
+    void* ws;
+    size_t ws_bytes;
+    hipStream_t stream;
+    Layout L;
+    SchoolArgs args;
+    uint64_t t;            // next iteration
+    uint64_t first_valid;  // first iteration whose record this handle wrote
+    bool has_result;       // an iteration completed since init/attach/set
+    bool pending;          // last feed pass's partials not yet combined
+    uint32_t pending_t;
+    uint32_t pending_grid;
+    bool profile;
+    Timer timers[FSB_KERNEL_KINDS];
+};
+
+namespace {
+
+// Launch `fn` bracketed by the kind's events when profiling is on.
+template <class F>
+int timed(fsb_school* h, int kind, const char* what, F&& fn) {
+    std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
+    if (h->profile) {
+        FSB_HIP_TRY(h->timers[kind].next(&ev), "hipEventCreate");
+        FSB_HIP_TRY(hipEventRecord(ev->first, h->stream), "hipEventRecord");
+    }
+    FSB_HIP_TRY(fn(), what);
+    if (ev) FSB_HIP_TRY(hipEventRecord(ev->second, h->stream), "hipEventRecord");
+    return FSB_OK;
+}
+
+SchoolArgs make_args(const fsb_config& c, const fsb_state& st, void* ws, const Layout& L) {
+    SchoolArgs a{};
+    char* base = static_cast<char*>(ws);
+    a.x = st.x;
+    a.y = st.y;
+    a.w = st.w;
+    a.prev = st.prev;
+    a.cur = st.cur;
+    a.n = c.n_fish;
+    a.k0 = (uint32_t)c.seed;
+    a.k1 = (uint32_t)(c.seed >> 32);
+    a.H = c.pond_half;
+    a.S = c.swim_step;
+    a.wmin = c.w_min;
+    a.wmax = c.w_max;
+    a.ctrl = reinterpret_cast<Ctrl*>(base + L.ctrl);
+    a.hist = reinterpret_cast<fsb_record*>(base + L.hist);
+    a.hist_len = c.history_len;
+    a.blockmax = reinterpret_cast<uint32_t*>(base + L.blockmax);
+    a.partials = reinterpret_cast<double*>(base + L.partials);
+    return a;
+}
+
+int new_school(const fsb_config* cfg, fsb_state state, void* ws, size_t ws_bytes, void* stream,
+               uint64_t t, fsb_school** out) {
+    int rc = check_config(cfg, true);
+    if (rc) return rc;
+    if (!out) return fail(FSB_ERR_INVALID_ARG, "out is NULL");
+    rc = check_columns(state, cfg->n_fish);
+    if (rc) return rc;
+    const Layout L = school_layout(cfg->history_len);
+    rc = check_workspace(ws, ws_bytes, L.total);
+    if (rc) return rc;
+    if (t >= kStepLimit) return fail(FSB_ERR_INVALID_ARG, "iteration index must be < 2^32");
+    fsb_school* h = new (std::nothrow) fsb_school();
+    if (!h) return fail(FSB_ERR_INVALID_ARG, "out of host memory");
+    h->cfg = *cfg;
+    h->st = state;
+    h->ws = ws;
+    h->ws_bytes = ws_bytes;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->L = L;
+    h->args = make_args(*cfg, state, ws, L);
+    h->t = t;
+    h->first_valid = t;
+    h->has_result = false;
+    h->pending = false;
+    h->profile = false;
+    hipError_t e = launch_reset(h->args, h->stream);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "reset launch");
+    }
+    *out = h;
+    return FSB_OK;
+}
+
+// Write the pending record (iteration pending_t) with a one-block launch.
+int finish_pending(fsb_school* h) {
+    if (!h->pending) return FSB_OK;
+    const uint32_t naive = h->cfg.reduce_mode == FSB_REDUCE_NAIVE_F32;
+    FSB_HIP_TRY(launch_combine(h->args, h->pending_t, h->pending_grid, naive, h->stream),
+                "combine launch");
+    h->pending = false;
+    return FSB_OK;
+}
+
+int check_device_error(fsb_school* h) {
+    uint32_t err = 0;
+    FSB_HIP_TRY(hipMemcpyDtoHAsync(&err, reinterpret_cast<hipDeviceptr_t>(&h->args.ctrl->error),
+                                   sizeof(err), h->stream),
+                "hipMemcpyDtoHAsync");
+    FSB_HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    if (err & kErrBarrierTimeout)
+        return fail(FSB_ERR_DEVICE, "a persistent kernel's grid barrier timed out");
+    if (err) return fail(FSB_ERR_DEVICE, "kernel error flags " + std::to_string(err));
+    return FSB_OK;
+}
+
+int do_step(fsb_school* h, const float* dx, const float* dy) {
+    if (h->t >= kStepLimit) return fail(FSB_ERR_INVALID_ARG, "iteration index reached 2^32");
+    StepArgs s{};
+    s.t = (uint32_t)h->t;
+    s.swim_grid = plain_grid(h->cfg.n_fish);
+    s.combine = h->pending ? 1u : 0u;
+    s.prev_t = h->pending_t;
+    s.prev_grid = h->pending_grid;
+    s.naive = h->cfg.reduce_mode == FSB_REDUCE_NAIVE_F32;
+    s.dx = dx;
+    s.dy = dy;
+    int rc = timed(h, FSB_KERNEL_SWIM_EVAL, "swim pass launch",
+                   [&] { return launch_swim_eval(h->args, s, h->stream); });
+    if (rc) return rc;
+    h->pending = false;
+    const uint32_t feed_grid = plain_grid(h->cfg.n_fish);
+    rc = timed(h, FSB_KERNEL_FEED_BARY, "feed pass launch",
+               [&] { return launch_feed_bary(h->args, s, feed_grid, h->stream); });
+    if (rc) return rc;
+    h->pending = true;
+    h->pending_t = (uint32_t)h->t;
+    h->pending_grid = feed_grid;
+    h->t += 1;
+    h->has_result = true;
+    return FSB_OK;
+}
+
+int read_record(fsb_school* h, uint64_t step, fsb_record* r) {
+    const fsb_record* src = h->args.hist + (step % h->cfg.history_len);
+    FSB_HIP_TRY(hipMemcpyDtoHAsync(r, reinterpret_cast<hipDeviceptr_t>(const_cast<fsb_record*>(src)),
+                                   sizeof(*r), h->stream),
+                "hipMemcpyDtoHAsync");
+    return FSB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fsb_strerror(int code) {
+    switch (code) {
+        case FSB_OK: return "ok";
+        case FSB_ERR_INVALID_ARG: return "invalid argument";
+        case FSB_ERR_HIP: return "HIP runtime error";
+        case FSB_ERR_UNSUPPORTED: return "unsupported configuration";
+        case FSB_ERR_STATE: return "call not valid in the current state";
+        case FSB_ERR_DEVICE: return "a kernel reported a failure";
+        default: return "unknown error code";
+    }
+}
+
+const char* fsb_last_error(void) { return g_last_error.c_str(); }
+
+int fsb_abi_version(void) { return FSB_ABI_VERSION; }
+
+int fsb_workspace_bytes(const fsb_config* cfg, size_t* out_bytes) {
+    int rc = check_config(cfg, false);
+    if (rc) return rc;
+    if (!out_bytes) return fail(FSB_ERR_INVALID_ARG, "out_bytes is NULL");
+    *out_bytes = school_layout(cfg->history_len).total;
+    return FSB_OK;
+}
+
+int fsb_init(const fsb_config* cfg, fsb_state state, void* workspace, size_t workspace_bytes,
+             void* stream, fsb_school** out) {
+    fsb_school* h = nullptr;
+    int rc = new_school(cfg, state, workspace, workspace_bytes, stream, 0, &h);
+    if (rc) return rc;
+    rc = timed(h, FSB_KERNEL_INIT, "init launch", [&] {
+        return launch_init(h->args, cfg->w_init_lo, cfg->w_init_hi, h->stream);
+    });
+    if (rc) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return FSB_OK;
+}
+
+int fsb_attach(const fsb_config* cfg, fsb_state state, void* workspace, size_t workspace_bytes,
+               void* stream, uint64_t t, fsb_school** out) {
+    return new_school(cfg, state, workspace, workspace_bytes, stream, t, out);
+}
+
+int fsb_step(fsb_school* h) {
+    if (!h) return fail(FSB_ERR_INVALID_ARG, "handle is NULL");
+    return do_step(h, nullptr, nullptr);
+}
+
+int fsb_step_displaced(fsb_school* h, const float* dx, const float* dy) {
+    if (!h) return fail(FSB_ERR_INVALID_ARG, "handle is NULL");
+    if (!dx || !dy) return fail(FSB_ERR_INVALID_ARG, "displacement arrays must not be NULL");
+    if (!aligned(dx, 16) || !aligned(dy, 16))
+        return fail(FSB_ERR_INVALID_ARG, "displacement arrays must be 16-byte aligned");
+    return do_step(h, dx, dy);
+}
+
+int fsb_run(fsb_school* h, uint64_t n_steps, uint32_t mode) {
+    if (!h) return fail(FSB_ERR_INVALID_ARG, "handle is NULL");
+    if (mode != FSB_RUN_PLAIN && mode != FSB_RUN_FUSED) return fail(FSB_ERR_INVALID_ARG, "unknown run mode");
+    if (n_steps > kStepLimit - h->t) return fail(FSB_ERR_INVALID_ARG, "iteration index would pass 2^32");
+    if (mode == FSB_RUN_FUSED) return fail(FSB_ERR_UNSUPPORTED, "fused mode not available");
+    for (uint64_t k = 0; k < n_steps; ++k) {
+        int rc = do_step(h, nullptr, nullptr);
+        if (rc) return rc;
+    }
+    return FSB_OK;
+}
+
+int fsb_barycentre(fsb_school* h, double out_xy[2], double* out_sums3) {
+    if (!h || !out_xy) return fail(FSB_ERR_INVALID_ARG, "NULL argument");
+    if (!h->has_result) return fail(FSB_ERR_STATE, "no iteration has completed");
+    int rc = finish_pending(h);
+    if (rc) return rc;
+    fsb_record r;
+    rc = read_record(h, h->t - 1, &r);
+    if (rc) return rc;
+    rc = check_device_error(h);
+    if (rc) return rc;
+    out_xy[0] = r.sum_wx / r.sum_w;
+    out_xy[1] = r.sum_wy / r.sum_w;
+    if (out_sums3) {
+        out_sums3[0] = r.sum_w;
+        out_sums3[1] = r.sum_wx;
+        out_sums3[2] = r.sum_wy;
+    }
+    return FSB_OK;
+}
+
+int fsb_max_delta(fsb_school* h, float* out_max) {
+    if (!h || !out_max) return fail(FSB_ERR_INVALID_ARG, "NULL argument");
+    if (!h->has_result) return fail(FSB_ERR_STATE, "no iteration has completed");
+    int rc = finish_pending(h);
+    if (rc) return rc;
+    fsb_record r;
+    rc = read_record(h, h->t - 1, &r);
+    if (rc) return rc;
+    rc = check_device_error(h);
+    if (rc) return rc;
+    *out_max = r.max_delta;
+    return FSB_OK;
+}
+
+int fsb_history(fsb_school* h, uint64_t first, uint64_t count, fsb_record* out) {
+    if (!h || (!out && count)) return fail(FSB_ERR_INVALID_ARG, "NULL argument");
+    const uint64_t lo = h->t > h->cfg.history_len ? h->t - h->cfg.history_len : 0;
+    const uint64_t oldest = lo > h->first_valid ? lo : h->first_valid;
+    if (first < oldest || first > h->t || count > h->t - first)
+        return fail(FSB_ERR_INVALID_ARG, "requested iterations are not in the record ring");
+    int rc = finish_pending(h);
+    if (rc) return rc;
+    for (uint64_t k = 0; k < count; ++k) {
+        rc = read_record(h, first + k, out + k);
+        if (rc) return rc;
+    }
+    rc = check_device_error(h);
+    if (rc) return rc;
+    for (uint64_t k = 0; k < count; ++k)
+        if (out[k].step_lo != (uint32_t)(first + k))
+            return fail(FSB_ERR_STATE, "record ring slot holds another iteration");
+    return FSB_OK;
+}
+
+int fsb_sync(fsb_school* h) {
+    if (!h) return fail(FSB_ERR_INVALID_ARG, "handle is NULL");
+    int rc = finish_pending(h);
+    if (rc) return rc;
+    return check_device_error(h);
+}
+
+int fsb_step_index(const fsb_school* h, uint64_t* out_t) {
+    if (!h || !out_t) return fail(FSB_ERR_INVALID_ARG, "NULL argument");
+    *out_t = h->t;
+    return FSB_OK;
+}
+
+int fsb_set_step_index(fsb_school* h, uint64_t t) {
+    if (!h) return fail(FSB_ERR_INVALID_ARG, "handle is NULL");
+    if (t >= kStepLimit) return fail(FSB_ERR_INVALID_ARG, "iteration index must be < 2^32");
+    int rc = finish_pending(h);
+    if (rc) return rc;
+    h->t = t;
+    h->first_valid = t;
+    h->has_result = false;
+    return FSB_OK;
+}
+
+int fsb_destroy(fsb_school* h) {
+    if (!h) return fail(FSB_ERR_INVALID_ARG, "handle is NULL");
+    delete h;
+    return FSB_OK;
+}
+
+int fsb_profile_enable(fsb_school* h, int enable) {
+    if (!h) return fail(FSB_ERR_INVALID_ARG, "handle is NULL");
+    h->profile = enable != 0;
+    return FSB_OK;
+}
+
+int fsb_kernel_times(fsb_school* h, uint64_t counts[FSB_KERNEL_KINDS], double ms[FSB_KERNEL_KINDS]) {
+    if (!h || !counts || !ms) return fail(FSB_ERR_INVALID_ARG, "NULL argument");
+    FSB_HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    for (int k = 0; k < FSB_KERNEL_KINDS; ++k) {
+        counts[k] = h->timers[k].used;
+        FSB_HIP_TRY(h->timers[k].total(&ms[k]), "hipEventElapsedTime");
+        h->timers[k].used = 0;
+    }
+    return FSB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,162 @@
+// fsb_device.hpp -- device building blocks of the FSB kernels (gfx950, wave64).
+//
+// The per-fish arithmetic must be bit-exact and reproducible: every float op
+// is binary32 round-to-nearest-even, rounded on its own.  The library is
+// compiled with -ffp-contract=off (no a*b+c fusion),
+// -fhip-fp32-correctly-rounded-divide-sqrt and without denormal flushing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fsb {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Counter (c0..c3), key
+// (k0, k1).  A round forms the two 64-bit products A*c0 and B*c2 and
+// rebuilds the counter as (hi(B*c2)^c1^k0, lo(B*c2), hi(A*c0)^c3^k1,
+// lo(A*c0)); the key moves on by the two Weyl constants after each round.
+// The key is uniform across a launch, so its schedule lives in SGPRs.
+// ---------------------------------------------------------------------------
+struct Words {
+    uint32_t r0, r1, r2, r3;
+};
+
+__device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                               uint32_t c3, uint32_t k0, uint32_t k1) {
+    constexpr uint32_t A = 0xD2511F53u, B = 0xCD9E8D57u;
+    constexpr uint32_t WA = 0x9E3779B9u, WB = 0xBB67AE85u;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t loA = A * c0, hiA = __umulhi(A, c0);
+        const uint32_t loB = B * c2, hiB = __umulhi(B, c2);
+        c0 = hiB ^ c1 ^ k0;
+        c1 = loB;
+        c2 = hiA ^ c3 ^ k1;
+        c3 = loA;
+        k0 += WA;
+        k1 += WB;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// Counter word 3: the random stream's domain.
+constexpr uint32_t kDomainSwim = 0u;
+constexpr uint32_t kDomainInit = 1u;
+
+// Both words of one pair-call, for pair index p, sub-stream s, domain d.
+__device__ __forceinline__ Words pair_words(uint64_t p, uint32_t s, uint32_t d,
+                                            uint32_t k0, uint32_t k1) {
+    return philox4x32_10((uint32_t)p, (uint32_t)(p >> 32), s, d, k0, k1);
+}
+
+// v(r) = (r >> 8) * 2^-23 - 1, formed as the signed integer
+// (r >> 8) - 2^23 scaled by 2^-23: both steps are exact in binary32.
+__device__ __forceinline__ float signed_unit(uint32_t r) {
+    return (float)((int32_t)(r >> 8) - (1 << 23)) * 0x1p-23f;
+}
+
+// u(r) = (r >> 8) * 2^-24, exact.
+__device__ __forceinline__ float unit(uint32_t r) {
+    return (float)(r >> 8) * 0x1p-24f;
+}
+
+__device__ __forceinline__ float clamp_to(float v, float lo, float hi) {
+    return fminf(fmaxf(v, lo), hi);
+}
+
+// Euclidean distance from the pond centre; each op rounded on its own.
+__device__ __forceinline__ float distance(float x, float y) {
+    const float xx = x * x;
+    const float yy = y * y;
+    return sqrtf(xx + yy);
+}
+
+// One fish's swim: move by (dx, dy) inside [-H, H]^2 and re-evaluate.  Returns
+// the new objective; x, y are updated in place.
+__device__ __forceinline__ float swim(float& x, float& y, float dx, float dy, float H) {
+    x = clamp_to(x + dx, -H, H);
+    y = clamp_to(y + dy, -H, H);
+    return distance(x, y);
+}
+
+// Feeding: w + diff / M, kept inside [wmin, wmax]; M == 0 leaves w alone.
+__device__ __forceinline__ float feed(float w, float diff, float M, float wmin, float wmax) {
+    return M > 0.0f ? clamp_to(w + diff / M, wmin, wmax) : w;
+}
+
+// Non-negative floats order like their bit patterns.
+__device__ __forceinline__ uint32_t mag_bits(float d) {
+    return __float_as_uint(fabsf(d));
+}
+
+// ---------------------------------------------------------------------------
+// Compensated float32 accumulation: (s, e) with the true sum ~ s + e.  Each
+// term goes through Knuth's TwoSum, which is exact whatever the relative
+// magnitudes (plain Kahan is not when a term exceeds the running sum, as in
+// the signed sums of w*x over a school centred at the origin).
+// ---------------------------------------------------------------------------
+struct CSum {
+    float s, e;
+};
+
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& err) {
+    s = a + b;
+    const float bv = s - a;
+    const float av = s - bv;
+    err = (a - av) + (b - bv);
+}
+
+__device__ __forceinline__ void csum_add(CSum& c, float v) {
+    float s, err;
+    two_sum(c.s, v, s, err);
+    c.s = s;
+    c.e += err;
+}
+
+__device__ __forceinline__ CSum csum_merge(CSum a, CSum b) {
+    float s, err;
+    two_sum(a.s, b.s, s, err);
+    return {s, (a.e + b.e) + err};
+}
+
+__device__ __forceinline__ double csum_value(CSum c) {
+    return (double)c.s + (double)c.e;
+}
+
+// ---------------------------------------------------------------------------
+// Wave64 reductions (butterfly over lanes; every lane ends with the result).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1)
+        v = max(v, (uint32_t)__shfl_xor((int)v, off, kWave));
+    return v;
+}
+
+__device__ __forceinline__ CSum wave_csum(CSum c) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        CSum o{__shfl_xor(c.s, off, kWave), __shfl_xor(c.e, off, kWave)};
+        c = csum_merge(c, o);
+    }
+    return c;
+}
+
+__device__ __forceinline__ float wave_sum_f32(float v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+}  // namespace fsb

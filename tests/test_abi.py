@@ -1,0 +1,135 @@
+"""The C ABI library loads on the CPU, exports every entry point the public
+header declares, and rejects bad arguments on the host before any HIP call.
+Every call here carries at least one invalid argument, so no kernel is ever
+launched (these tests also run safely where a GPU is present)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2507_20173_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fsb.h")
+
+DECL = re.compile(r"^\s*(?:const\s+)?\w+\s*\*?\s*(fsb_\w+)\s*\(", re.M)
+
+
+def declared():
+    with open(HEADER) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(DECL.findall(text)))
+
+
+def test_header_declares_entry_points():
+    names = declared()
+    for must in ("fsb_init", "fsb_step", "fsb_run", "fsb_barycentre"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.lib()
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, f"declared but not exported: {missing}"
+
+
+def test_binding_covers_every_declared_symbol():
+    assert set(declared()) <= set(_lib.PROTOTYPES)
+
+
+def test_abi_version_and_strerror():
+    lib = _lib.lib()
+    assert lib.fsb_abi_version() == 1
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.fsb_strerror(code)
+    assert lib.fsb_strerror(-99) == b"unknown error code"
+
+
+def cfg(**kw):
+    base = dict(n_fish=1000, seed=0, pond_half=100.0, swim_step=0.1, w_init_lo=1.0,
+                w_init_hi=2.0, w_min=1.0, w_max=4.0, reduce_mode=0, history_len=1)
+    base.update(kw)
+    return _lib.fsb_config(*base.values())
+
+
+def ws_bytes(c):
+    out = ctypes.c_size_t()
+    rc = _lib.lib().fsb_workspace_bytes(ctypes.byref(c), ctypes.byref(out))
+    return rc, out.value
+
+
+def test_workspace_bytes_pure_host():
+    rc, b1 = ws_bytes(cfg(history_len=1))
+    assert rc == 0 and b1 % 256 == 0 and b1 > 0
+    rc, b2 = ws_bytes(cfg(history_len=1000))
+    assert rc == 0 and b2 >= b1 + 999 * ctypes.sizeof(_lib.fsb_record) - 256
+
+
+@pytest.mark.parametrize("bad", [
+    dict(pond_half=0.0), dict(pond_half=float("nan")), dict(pond_half=-1.0),
+    dict(swim_step=-0.1), dict(swim_step=float("inf")),
+    dict(w_init_lo=2.0, w_init_hi=1.0), dict(w_min=5.0, w_max=4.0),
+    dict(w_max=float("nan")), dict(reduce_mode=7), dict(history_len=0),
+    dict(n_fish=(1 << 40) + 1)])
+def test_bad_config_rejected(bad):
+    rc, _ = ws_bytes(cfg(**bad))
+    assert rc == _lib.FSB_ERR_INVALID_ARG
+    assert _lib.lib().fsb_last_error()
+
+
+FAKE = 1 << 40  # an aligned address that is never dereferenced
+
+
+def cols(**over):
+    base = dict(x=FAKE, y=FAKE + (1 << 20), w=FAKE + (2 << 20), prev=FAKE + (3 << 20),
+                cur=FAKE + (4 << 20))
+    base.update(over)
+    return _lib.fsb_state(*base.values())
+
+
+def init(c, st, ws, nbytes):
+    h = ctypes.c_void_p()
+    return _lib.lib().fsb_init(ctypes.byref(c), st, ws, nbytes, None, ctypes.byref(h))
+
+
+@pytest.mark.parametrize("case", ["n0", "null_col", "misaligned_col", "overlap",
+                                  "null_ws", "misaligned_ws", "small_ws"])
+def test_init_rejects_before_any_hip_call(case):
+    c = cfg()
+    _, need = ws_bytes(c)
+    st, ws, nbytes = cols(), FAKE + (8 << 20), need
+    if case == "n0":
+        c = cfg(n_fish=0)
+    elif case == "null_col":
+        st = cols(w=0)
+    elif case == "misaligned_col":
+        st = cols(prev=FAKE + (3 << 20) + 4)
+    elif case == "overlap":
+        st = cols(y=FAKE + 400)
+    elif case == "null_ws":
+        ws = 0
+    elif case == "misaligned_ws":
+        ws = FAKE + (8 << 20) + 64
+    elif case == "small_ws":
+        nbytes = need - 1
+    assert init(c, st, ws, nbytes) == _lib.FSB_ERR_INVALID_ARG
+    assert _lib.lib().fsb_last_error()
+
+
+def test_null_handles_rejected():
+    L = _lib.lib()
+    assert L.fsb_step(None) == _lib.FSB_ERR_INVALID_ARG
+    assert L.fsb_run(None, 1, 0) == _lib.FSB_ERR_INVALID_ARG
+    assert L.fsb_sync(None) == _lib.FSB_ERR_INVALID_ARG
+    assert L.fsb_destroy(None) == _lib.FSB_ERR_INVALID_ARG
+    xy = (ctypes.c_double * 2)()
+    assert L.fsb_barycentre(None, xy, None) == _lib.FSB_ERR_INVALID_ARG
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "LIBRARY", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError, match="no fallback"):
+        _lib.lib()

@@ -1,0 +1,50 @@
+"""Our own gfx950 assembly keeps the binary32 contract: the only fused
+multiply-adds in any kernel are those inside the correctly rounded sqrtf
+(two residual checks per v_sqrt_f32) and division (five per
+v_div_fixup_f32) expansions, and no packed-FP32 instruction is emitted."""
+import re
+
+import pytest
+
+from paper_2507_20173_amd import build as fsb_build
+
+
+@pytest.fixture(scope="module")
+def kernels():
+    path = fsb_build.assembly("fsb_kernels.hip")
+    text = open(path).read()
+    bodies, name = {}, None
+    for line in text.splitlines():
+        m = re.match(r"^(_Z\w+):", line)
+        if m:
+            name = m.group(1)
+            bodies[name] = []
+        elif name:
+            bodies[name].append(line)
+            if line.strip().startswith(".Lfunc_end"):
+                name = None
+    return {k: "\n".join(v) for k, v in bodies.items()}
+
+
+def count(body, pattern):
+    return len(re.findall(pattern, body))
+
+
+def test_kernels_found(kernels):
+    names = " ".join(kernels)
+    for k in ("init_kernel", "swim_eval_kernel", "feed_bary_kernel", "combine_kernel"):
+        assert k in names
+
+
+def test_no_contraction_outside_sqrt_and_div(kernels):
+    for name, body in kernels.items():
+        fma = count(body, r"\bv_(fma|fmac|mac|mad)_f32|\bv_fma_mix")
+        sqrt = count(body, r"\bv_sqrt_f32")
+        div = count(body, r"\bv_div_fixup_f32")
+        assert fma == 2 * sqrt + 5 * div, (
+            f"{name}: {fma} fused ops vs {sqrt} sqrt and {div} div expansions")
+
+
+def test_no_packed_fp32(kernels):
+    for name, body in kernels.items():
+        assert count(body, r"\bv_pk_(add|mul|fma)_f32") == 0, name

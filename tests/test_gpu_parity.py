@@ -1,0 +1,285 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Per-fish columns and the school max are compared bit for bit; the three
+barycentre sums within 1e-6 of the oracle's binary64 reference (relative to
+sum w, and to sum |w*x|, sum |w*y| for the signed sums)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle_pins
+import paper_2507_20173_amd as fsb
+from oracle.oracle import FISH, default
+from parity_util import (FIELD_OF, assert_columns_equal, assert_sums_close, columns_of,
+                         oracle_config)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def O():
+    return default()
+
+
+def announce(msg):
+    print(f"[parity] {msg}", flush=True)
+
+
+# Sizes span one tile, several tiles, several grid-stride rounds and ragged
+# tails (n % 4 = 1, 2, 3), plus the degenerate single fish.
+SIZES = [1, 2, 3, 4, 5, 7, 63, 64, 65, 1000, 4097, 65539, 262147, 1 << 21, (1 << 22) + 3]
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_init_matches_oracle(torch_cuda, O, n):
+    announce(f"init n={n}")
+    cfg = fsb.FsbConfig(n_fish=n, seed=0x5EED0000 + n)
+    sch = fsb.School(cfg)
+    got = sch.state()
+    want = O.init(oracle_config(cfg))
+    assert_columns_equal(got, want, f"init n={n}")
+    sch.close()
+
+
+@pytest.mark.parametrize("n,steps", [(1, 6), (3, 6), (5, 6), (65, 6), (1000, 6), (4097, 5),
+                                     (65539, 4), ((1 << 21) + 1, 3), ((1 << 23) + 6, 2)])
+def test_steps_match_oracle(torch_cuda, O, n, steps):
+    announce(f"steps n={n} steps={steps}")
+    cfg = fsb.FsbConfig(n_fish=n, seed=1234567 + n, history_len=steps)
+    ocfg = oracle_config(cfg)
+    school = O.init(ocfg)
+    sch = fsb.School(cfg)
+    for t in range(steps):
+        m, s, a = O.step(ocfg, school, t)
+        sch.step()
+        assert sch.max_delta() == m, f"n={n} t={t}: M {sch.max_delta()} != {m}"
+        _, sums = sch.barycentre()
+        assert_sums_close(sums, s, a, what=f"n={n} t={t}")
+        assert_columns_equal(sch.state(), school, f"n={n} t={t}")
+    sch.close()
+
+
+def test_cfg1_full_run(torch_cuda, O):
+    """N = 10,000 fish, 100 iterations, seed 0: every iteration's record and
+    the final columns against the oracle."""
+    announce("cfg1 N=10000 T=100")
+    cfg = fsb.FsbConfig(n_fish=10_000, seed=0, history_len=100)
+    ocfg = oracle_config(cfg)
+    school = O.init(ocfg)
+    m, s, a = O.run(ocfg, school, 0, 100)
+    sch = fsb.School(cfg)
+    sch.run(100)
+    hist = sch.history(0, 100)
+    assert np.array_equal(hist["max_delta"], m), "per-iteration maxima differ"
+    assert np.array_equal(hist["step_lo"], np.arange(100))
+    got = np.stack([hist["sum_w"], hist["sum_wx"], hist["sum_wy"]], 1)
+    assert_sums_close(got, s, a, what="cfg1 history")
+    assert_columns_equal(sch.state(), school, "cfg1 final")
+    sch.close()
+
+
+def test_cfg2_full_size_prefix(torch_cuda, O):
+    """N = 2^24 (the benchmarked school), in the benchmark's launch shape:
+    every fish bit-exact and the sums in tolerance over the first iterations."""
+    n, steps = 1 << 24, 3
+    announce(f"cfg2 N={n} prefix {steps}")
+    cfg = fsb.FsbConfig(n_fish=n, seed=0, history_len=steps)
+    ocfg = oracle_config(cfg)
+    school = O.init(ocfg)
+    m, s, a = O.run(ocfg, school, 0, steps)
+    sch = fsb.School(cfg)
+    sch.run(steps)
+    hist = sch.history(0, steps)
+    assert np.array_equal(hist["max_delta"], m)
+    got = np.stack([hist["sum_w"], hist["sum_wx"], hist["sum_wy"]], 1)
+    assert_sums_close(got, s, a, what="cfg2 prefix")
+    assert_columns_equal(sch.state(), school, "cfg2 prefix")
+    sch.close()
+
+
+def test_cfg2_full_length_sampled(torch_cuda, O):
+    """N = 2^24, 1000 iterations (the full benchmark run): swimming does not
+    depend on weights or other fish, so the oracle follows sampled fish one
+    by one; weights and maxima are checked through invariants."""
+    n, steps = 1 << 24, 1000
+    announce(f"cfg2 N={n} T={steps} sampled")
+    cfg = fsb.FsbConfig(n_fish=n, seed=0, history_len=steps)
+    ocfg = oracle_config(cfg)
+    sch = fsb.School(cfg)
+    start = {k: v.cpu().numpy() for k, v in sch.cols.items()}
+    sch.run(steps)
+    got = sch.state()
+    rng = np.random.default_rng(99)
+    sample = np.unique(np.concatenate([[0, 1, 2, 3, n - 4, n - 3, n - 2, n - 1],
+                                       rng.integers(0, n, 56)]))
+    for i in sample:
+        rec = np.zeros(1, FISH)
+        for k, f in FIELD_OF.items():
+            rec[f] = start[k][i]
+        f = O.follow_fish(ocfg, int(i), 0, steps, rec[0])
+        for k in ("x", "y", "prev", "cur"):
+            assert got[k][i] == f[FIELD_OF[k]], f"fish {i} {k}"
+    hist = sch.history(0, steps)
+    assert (hist["max_delta"] > 0).all()
+    assert (hist["max_delta"] <= cfg.swim_step * math.sqrt(2) + 1e-4).all()
+    w = got["w"]
+    assert (w >= cfg.w_min).all() and (w <= cfg.w_max).all()
+    diff = got["prev"] - got["cur"]
+    assert np.abs(diff).max() == hist["max_delta"][-1]
+    assert np.array_equal(got["cur"], np.sqrt(got["x"] * got["x"] + got["y"] * got["y"]))
+    # The recorded sums are the sums of the columns the kernels left behind
+    # (a property at any size; numpy's binary64 pairwise sums as reference).
+    wd = w.astype(np.float64)
+    ref = [wd.sum(), (wd * got["x"]).sum(), (wd * got["y"]).sum()]
+    den = [wd.sum(), np.abs(wd * got["x"]).sum(), np.abs(wd * got["y"]).sum()]
+    assert_sums_close([hist["sum_w"][-1], hist["sum_wx"][-1], hist["sum_wy"][-1]], ref, den,
+                      what="cfg2 last iteration")
+    sch.close()
+
+
+def _golden_school(torch_cuda, name):
+    fx = oracle_pins.load_golden(name)
+    c = fx["config"]
+    n = len(fx["before"])
+    cfg = fsb.FsbConfig(n_fish=n, pond_half=c["pondHalf"], swim_step=c["swimStep"],
+                        w_min=c["weightMin"], w_max=c["weightMax"])
+    before = oracle_pins.golden_school(fx, "before")
+    sch = fsb.School(cfg, state=columns_of(before))
+    d = np.array(fx["displacement"], np.float32)
+    dx = torch_cuda.tensor(d[:, 0].copy(), device="cuda")
+    dy = torch_cuda.tensor(d[:, 1].copy(), device="cuda")
+    return fx, sch, dx, dy
+
+
+@pytest.mark.parametrize("name", ["worked_example_4fish.json", "worked_example_division.json"])
+def test_worked_examples(torch_cuda, name):
+    announce(f"golden {name}")
+    fx, sch, dx, dy = _golden_school(torch_cuda, name)
+    sch.step_displaced(dx, dy)
+    assert sch.max_delta() == np.float32(fx["maxDiff"])
+    xy, sums = sch.barycentre()
+    # Columns and the max are exact; the sums are held to the reduction gate
+    # (the kernels form w*x as a rounded binary32 product: 3 * 9087659 * 2^-22
+    # needs 25 bits, so the second example's sum w*x is not exact in binary32).
+    absums = [sum(abs(f["weight"]) for f in fx["after"])] + [
+        sum(abs(f["weight"] * f[k]) for f in fx["after"]) for k in ("x", "y")]
+    assert_sums_close(sums, fx["sums"], absums, what=name)
+    assert abs(xy[0] - fx["barycentre"][0]) <= 1e-6 * abs(fx["barycentre"][0])
+    assert abs(xy[1] - fx["barycentre"][1]) <= 1e-6 * abs(fx["barycentre"][1])
+    if name == "worked_example_4fish.json":  # every product and sum exact
+        assert list(sums) == fx["sums"] and list(xy) == fx["barycentre"]
+    assert_columns_equal(sch.state(), oracle_pins.golden_school(fx, "after"), name)
+    sch.close()
+
+
+def test_zero_swim(torch_cuda):
+    announce("zero swim")
+    cfg = fsb.FsbConfig(n_fish=10_003, seed=3, swim_step=0.0, history_len=4)
+    sch = fsb.School(cfg)
+    before = sch.state()
+    sch.run(4)
+    hist = sch.history(0, 4)
+    assert (hist["max_delta"] == 0).all()
+    after = sch.state()
+    for k in before:
+        assert np.array_equal(before[k], after[k]), k
+
+
+def test_uniform_weights_barycentre_is_mean(torch_cuda):
+    announce("uniform weights")
+    c = 1.5
+    cfg = fsb.FsbConfig(n_fish=100_003, seed=11, w_init_lo=c, w_init_hi=c, w_min=c, w_max=c)
+    sch = fsb.School(cfg)
+    for t in range(3):
+        sch.step()
+        xy, sums = sch.barycentre()
+        st = sch.state()
+        assert (st["w"] == np.float32(c)).all()
+        x = st["x"].astype(np.float64)
+        y = st["y"].astype(np.float64)
+        assert abs(sums[0] - c * cfg.n_fish) <= 1e-12 * c * cfg.n_fish
+        assert abs(xy[0] - x.mean()) <= 1e-6 * np.abs(x).mean()
+        assert abs(xy[1] - y.mean()) <= 1e-6 * np.abs(y).mean()
+
+
+def test_symmetric_school_sums_exactly_zero(torch_cuda):
+    """Mirror pairs on a coarse dyadic grid: every product and partial sum
+    is exact in binary32, so the GPU's sums are exactly 0 in any order."""
+    announce("symmetric school")
+    school = oracle_pins.symmetric_dyadic_school(2048, 5)
+    cfg = fsb.FsbConfig(n_fish=school.size, swim_step=0.0)
+    sch = fsb.School(cfg, state=columns_of(school))
+    sch.step()
+    xy, sums = sch.barycentre()
+    assert sums[1] == 0.0 and sums[2] == 0.0
+    assert sums[0] == math.fsum(school["weight"].astype(np.float64))
+
+
+def test_composition_and_resume(torch_cuda, O):
+    """run(3) + run(4) == run(7) == 7 x step; a school attached from a
+    checkpoint at t = 3 continues bit-exactly."""
+    announce("composition/resume")
+    cfg = fsb.FsbConfig(n_fish=5003, seed=77, history_len=8)
+    a = fsb.School(cfg)
+    a.run(3)
+    ckpt = a.state()
+    a.run(4)
+    b = fsb.School(cfg)
+    for _ in range(7):
+        b.step()
+    sa, sb = a.state(), b.state()
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+    c = fsb.School(cfg, state=ckpt, t=3)
+    c.run(4)
+    sc = c.state()
+    for k in sa:
+        assert np.array_equal(sa[k], sc[k]), k
+    assert np.array_equal(a.history(3, 4)["max_delta"], c.history(3, 4)["max_delta"])
+    school = O.init(oracle_config(cfg))
+    O.run(oracle_config(cfg), school, 0, 7)
+    assert_columns_equal(sa, school, "composition")
+
+
+def test_naive_mode_same_state_looser_sums(torch_cuda, O):
+    """The float32-atomics baseline changes only how the sums are reduced."""
+    announce("naive reduction")
+    n = 200_003
+    cfg = fsb.FsbConfig(n_fish=n, seed=8, reduce_mode=fsb.FSB_REDUCE_NAIVE_F32, history_len=3)
+    ocfg = oracle_config(cfg)
+    school = O.init(ocfg)
+    m, s, a = O.run(ocfg, school, 0, 3)
+    sch = fsb.School(cfg)
+    sch.run(3)
+    hist = sch.history(0, 3)
+    assert np.array_equal(hist["max_delta"], m)
+    got = np.stack([hist["sum_w"], hist["sum_wx"], hist["sum_wy"]], 1)
+    assert_sums_close(got, s, a, tol=1e-3, what="naive")
+    assert_columns_equal(sch.state(), school, "naive")
+
+
+def test_history_ring_and_errors(torch_cuda):
+    announce("history ring / errors")
+    cfg = fsb.FsbConfig(n_fish=1000, seed=1, history_len=4)
+    sch = fsb.School(cfg)
+    with pytest.raises(fsb.FsbError) as e:
+        sch.barycentre()
+    assert e.value.code == fsb._lib.FSB_ERR_STATE
+    sch.run(10)
+    h = sch.history(6, 4)
+    assert list(h["step_lo"]) == [6, 7, 8, 9]
+    with pytest.raises(fsb.FsbError):
+        sch.history(5, 2)
+    with pytest.raises(fsb.FsbError):
+        sch.history(8, 3)
+    assert sch.t == 10
