@@ -89,7 +89,56 @@ def plain_run(n: int, steps: int, warmup: int):
     return wall, kernels, xy
 
 
-def cpu_baseline(n: int, budget_s: float = 12.0, max_steps: int = 40):
+def run_form(n: int, steps: int, mode: int, warmup: int = 2):
+    """Wall time of `steps` iterations of one school in the given mode, plus
+    the kernels' event-timed durations."""
+    import torch
+
+    import paper_2507_20173_amd as fsb
+
+    cfg = fsb.FsbConfig(n_fish=n, seed=0, history_len=1)
+    sch = fsb.School(cfg)
+    sch.run(warmup, mode)
+    sch.sync()
+    fsb.fsb_profile_enable(sch.h, True)
+    fsb.fsb_kernel_times(sch.h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sch.run(steps, mode)
+    sch.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    counts, ms = fsb.fsb_kernel_times(sch.h)
+    sch.close()
+    del sch
+    torch.cuda.empty_cache()
+    return wall, counts, ms
+
+
+def fused_vs_plain(n: int, steps: int, label: str):
+    """The persistent form against per-iteration launches on the same school."""
+    import paper_2507_20173_amd as fsb
+
+    wf, cf, mf = run_form(n, steps, fsb.FSB_RUN_FUSED)
+    wp, cp, mp = run_form(n, steps, fsb.FSB_RUN_PLAIN)
+    fused_kernel_s = mf[fsb.FSB_KERNEL_FUSED] / 1e3
+    # one launch: prologue 24 B + (steps - 1) sweeps of 32 B + last sweep 24 B
+    fused_bytes = n * (24 + 32 * (steps - 1) + 24)
+    return {
+        "workload": label, "n_fish": n, "iterations": steps,
+        "fused": {"value": n * steps / wf, "ms_per_step": wf / steps * 1e3,
+                  "launches": int(cf[fsb.FSB_KERNEL_FUSED]),
+                  "algorithmic_bytes_per_fish_step": 32,
+                  "kernel_achieved_GBs": fused_bytes / fused_kernel_s / 1e9,
+                  "kernel_hbm_frac": fused_bytes / fused_kernel_s / 1e9 / HBM_PEAK_GBS},
+        "plain": {"value": n * steps / wp, "ms_per_step": wp / steps * 1e3,
+                  "algorithmic_bytes_per_fish_step": 52,
+                  "hbm_frac": 52 * n * steps / wp / 1e9 / HBM_PEAK_GBS},
+        "fused_speedup": wp / wf,
+    }
+
+
+def cpu_baseline(n: int, budget_s: float = 12.0, max_steps: int = 400):
     """The oracle as it stands, on this host's cores, on a bounded prefix of
     the same workload."""
     from oracle.oracle import Config, default
@@ -115,6 +164,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n-fish", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain-only", action="store_true", help="skip the fused/batched forms")
+    ap.add_argument("--fused-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         log(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -155,6 +206,14 @@ def main() -> int:
         "hbm_frac_whole_step": (sum(BYTES_PER_FISH.values()) * n * args.steps / wall / 1e9)
         / HBM_PEAK_GBS,
     }
+    if not args.plain_only:
+        line["forms"] = {
+            "fused_cfg4": fused_vs_plain(1 << 26, args.fused_steps,
+                                         "persistent form: N=2^26 fish, 2000 iterations in one "
+                                         "cooperative launch vs per-iteration launches"),
+            "fused_cfg2": fused_vs_plain(n, args.steps, "persistent form on the headline school "
+                                                        "(N=2^24, 1000 iterations)"),
+        }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(line), flush=True)

@@ -144,6 +144,7 @@ struct fsb_school {
     uint32_t pending_t;
     uint32_t pending_grid;
     bool profile;
+    uint32_t resident[2];  // co-resident grid of the persistent kernel (per reduce mode; 0 = unknown)
     Timer timers[FSB_KERNEL_KINDS];
 };
 
@@ -182,6 +183,7 @@ SchoolArgs make_args(const fsb_config& c, const fsb_state& st, void* ws, const L
     a.hist_len = c.history_len;
     a.blockmax = reinterpret_cast<uint32_t*>(base + L.blockmax);
     a.partials = reinterpret_cast<double*>(base + L.partials);
+    a.sync = reinterpret_cast<uint32_t*>(base + L.sync);
     return a;
 }
 
@@ -268,6 +270,44 @@ int do_step(fsb_school* h, const float* dx, const float* dy) {
     return FSB_OK;
 }
 
+// n_steps iterations in one persistent launch (cooperative, so the grid is
+// guaranteed co-resident or the launch fails).
+int run_fused(fsb_school* h, uint64_t n_steps) {
+    if (n_steps == 0) return FSB_OK;
+    const uint32_t naive = h->cfg.reduce_mode == FSB_REDUCE_NAIVE_F32;
+    if (h->resident[naive] == 0)
+        FSB_HIP_TRY(fused_resident_grid(naive, &h->resident[naive]), "occupancy query");
+    if (h->resident[naive] == 0)
+        return fail(FSB_ERR_UNSUPPORTED, "the persistent kernel cannot be resident on this device");
+    int rc = finish_pending(h);
+    if (rc) return rc;
+    const uint32_t grid = fused_grid(h->cfg.n_fish, h->resident[naive]);
+    FusedArgs f{};
+    f.t0 = (uint32_t)h->t;
+    f.steps = (uint32_t)n_steps;
+    f.naive = naive;
+    fused_groups(grid, &f.group_size, &f.groups);
+    // Non-temporal streaming once the four live columns outgrow the 256 MB
+    // last-level cache (below that, keeping lines cached is faster).
+    f.streaming = h->cfg.n_fish * 16ull > (256ull << 20);
+    std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
+    if (h->profile) {
+        FSB_HIP_TRY(h->timers[FSB_KERNEL_FUSED].next(&ev), "hipEventCreate");
+        FSB_HIP_TRY(hipEventRecord(ev->first, h->stream), "hipEventRecord");
+    }
+    hipError_t e = launch_fused(h->args, f, grid, h->stream);
+    if (e == hipErrorCooperativeLaunchTooLarge)
+        return fail(FSB_ERR_UNSUPPORTED, "persistent grid cannot be co-resident");
+    if (e != hipSuccess) return hip_fail(e, "persistent kernel launch");
+    if (ev) FSB_HIP_TRY(hipEventRecord(ev->second, h->stream), "hipEventRecord");
+    h->pending = true;
+    h->pending_t = (uint32_t)(h->t + n_steps - 1);
+    h->pending_grid = grid;
+    h->t += n_steps;
+    h->has_result = true;
+    return FSB_OK;
+}
+
 int read_record(fsb_school* h, uint64_t step, fsb_record* r) {
     const fsb_record* src = h->args.hist + (step % h->cfg.history_len);
     FSB_HIP_TRY(hipMemcpyDtoHAsync(r, reinterpret_cast<hipDeviceptr_t>(const_cast<fsb_record*>(src)),
@@ -342,7 +382,7 @@ int fsb_run(fsb_school* h, uint64_t n_steps, uint32_t mode) {
     if (!h) return fail(FSB_ERR_INVALID_ARG, "handle is NULL");
     if (mode != FSB_RUN_PLAIN && mode != FSB_RUN_FUSED) return fail(FSB_ERR_INVALID_ARG, "unknown run mode");
     if (n_steps > kStepLimit - h->t) return fail(FSB_ERR_INVALID_ARG, "iteration index would pass 2^32");
-    if (mode == FSB_RUN_FUSED) return fail(FSB_ERR_UNSUPPORTED, "fused mode not available");
+    if (mode == FSB_RUN_FUSED) return run_fused(h, n_steps);
     for (uint64_t k = 0; k < n_steps; ++k) {
         int rc = do_step(h, nullptr, nullptr);
         if (rc) return rc;

@@ -4,29 +4,35 @@
 //   swim pass  (reads x, y, cur; writes x, y, prev, cur; 28 B/fish)
 //     draws, swim + pond clamp, objective, |diff|; each block stores its max
 //     |diff| bit pattern (non-negative floats order like their bits, so the
-//     max is exact and independent of order).  Block 0 first finishes the
-//     previous iteration's record from the feed pass's block partials.
+//     max is exact and independent of order).  Block 0 first writes the
+//     pending record of the previous iteration from its block partials.
 //   feed pass  (reads prev, cur, w, x, y; writes w; 24 B/fish)
 //     every block reduces the swim pass's block maxima to M, feeds, and
 //     accumulates sum w, sum w*x, sum w*y per lane in compensated float32,
-//     merges lanes with TwoSum and waves in binary64; one binary64 partial
+//     merges lanes with TwoSum and waves in binary64: one binary64 partial
 //     per block.
-// The record of iteration t is written by the next swim pass's block 0 (or by
-// a one-block combine launch when the host asks for it), in a fixed order, so
-// every sum is deterministic.  No atomics and no fences are needed: the
-// stream orders the passes.
-// Each thread handles groups of four consecutive fish (one float4 per
-// column), i.e. two Philox calls (fish pairs 2g and 2g+1).  Fish beyond the
-// last full group (n % 4 of them) are handled one by one by the last block.
+// Persistent iteration (one cooperative launch for many iterations, one grid
+// barrier per iteration; 32 B/fish per iteration):
+//   prologue   swim t0 from (x, y, cur), keep (x, y, prev), block max -> M_t0
+//   sweep s    read (x, y, w, prev); cur = |p| recomputed; feed with M_s;
+//              partial sums of s; then swim s+1 and its max -> M_{s+1};
+//              write (x, y, w, prev); grid barrier.  The last sweep writes
+//              (w, cur) instead, leaving the five columns complete.
+//   The record of s is written after the barrier by block s % grid.
+// Records are combined in a fixed order, so every sum is deterministic for a
+// given launch shape.  Each thread handles groups of four consecutive fish
+// (one float4 per column): two Philox calls, for fish pairs 2g and 2g+1.
+// The n % 4 fish past the last full group are handled one by one by the last
+// block.  A thread keeps the same fish in every sweep of a launch.
 #include "fsb_device.hpp"
 #include "fsb_internal.hpp"
 
 namespace fsb {
 
 constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / kWave;
 constexpr uint32_t kPlainGridCap = 2048;  // 8 blocks of 4 waves per CU x 256 CUs
 constexpr int kUnroll = 2;                // groups in flight per thread
+constexpr uint32_t kBarrierSpinLimit = 1u << 22;
 
 __device__ __forceinline__ float4 ld4(const float* p, uint64_t g) {
     return reinterpret_cast<const float4*>(p)[g];
@@ -38,8 +44,105 @@ __device__ __forceinline__ float& lane_of(float4& v, int k) {
     return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w;
 }
 
+__device__ __forceinline__ double* partial_slot(const SchoolArgs& a, uint32_t t, int k) {
+    return a.partials + ((size_t)(t & 1u) * 3 + k) * kMaxGrid;
+}
+
+// Swim displacements of the four fish of group g at iteration t.
+__device__ __forceinline__ void group_draws(const SchoolArgs& a, uint64_t g, uint32_t t,
+                                            float dx[4], float dy[4]) {
+    const float S = a.S;
+    const Words p0 = pair_words(2 * g, t, kDomainSwim, a.k0, a.k1);
+    const Words p1 = pair_words(2 * g + 1, t, kDomainSwim, a.k0, a.k1);
+    dx[0] = S * signed_unit(p0.r0); dy[0] = S * signed_unit(p0.r1);
+    dx[1] = S * signed_unit(p0.r2); dy[1] = S * signed_unit(p0.r3);
+    dx[2] = S * signed_unit(p1.r0); dy[2] = S * signed_unit(p1.r1);
+    dx[3] = S * signed_unit(p1.r2); dy[3] = S * signed_unit(p1.r3);
+}
+
+// Swim displacement of one fish i at iteration t.
+__device__ __forceinline__ void fish_draw(const SchoolArgs& a, uint64_t i, uint32_t t, float& dx,
+                                          float& dy) {
+    const Words p = pair_words(i >> 1, t, kDomainSwim, a.k0, a.k1);
+    const bool odd = i & 1;
+    dx = a.S * signed_unit(odd ? p.r2 : p.r0);
+    dy = a.S * signed_unit(odd ? p.r3 : p.r1);
+}
+
+// Per-lane sums of the barycentre: compensated (TwoSum) or plain float32.
+template <bool kNaive>
+struct LaneSums {
+    CSum c[3] = {{0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}};
+    float f[3] = {0.0f, 0.0f, 0.0f};
+    __device__ __forceinline__ void add(float w, float x, float y) {
+        const float wx = w * x;
+        const float wy = w * y;
+        if constexpr (kNaive) {
+            f[0] += w;
+            f[1] += wx;
+            f[2] += wy;
+        } else {
+            csum_add(c[0], w);
+            csum_add(c[1], wx);
+            csum_add(c[2], wy);
+        }
+    }
+};
+
+// Block-wide reduction of the lane sums: binary64 partial of this block for
+// iteration t (compensated mode) or float32 atomics into slot t & 1 (naive).
+template <bool kNaive, int BLOCK = kBlock>
+__device__ __forceinline__ void block_sums(const SchoolArgs& a, LaneSums<kNaive>& ls, uint32_t t) {
+    constexpr int W = BLOCK / kWave;
+    __shared__ CSum wave_cs[3][W];
+    __shared__ float wave_fs[3][W];
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    if constexpr (kNaive) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float v = wave_sum_f32(ls.f[k]);
+            if (lane == 0) wave_fs[k][wid] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int k = 0; k < 3; ++k) {
+                float v = wave_fs[k][0];
+                for (int w = 1; w < W; ++w) v += wave_fs[k][w];
+                atomicAdd(&a.ctrl->naive_acc[t & 1u][k], v);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const CSum v = wave_csum(ls.c[k]);
+            if (lane == 0) wave_cs[k][wid] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int k = 0; k < 3; ++k) {
+                double v = 0.0;
+                for (int w = 0; w < W; ++w) v += csum_value(wave_cs[k][w]);
+                partial_slot(a, t, k)[blockIdx.x] = v;
+            }
+        }
+    }
+}
+
+// Block max of per-thread maxima (every thread gets it).
+template <int BLOCK = kBlock>
+__device__ __forceinline__ uint32_t block_max(uint32_t v) {
+    constexpr int W = BLOCK / kWave;
+    __shared__ uint32_t wave_best[W];
+    v = wave_max_u32(v);
+    if (threadIdx.x % kWave == 0) wave_best[threadIdx.x / kWave] = v;
+    __syncthreads();
+    uint32_t m = wave_best[0];
+    for (int w = 1; w < W; ++w) m = max(m, wave_best[w]);
+    return m;
+}
+
 // ---------------------------------------------------------------------------
-// Control-word reset (a kernel rather than a memset, so it is graph-safe).
+// Control-word resets (kernels rather than memsets, so they are graph-safe).
 // ---------------------------------------------------------------------------
 __global__ void reset_kernel(Ctrl* ctrl) {
     uint32_t* p = reinterpret_cast<uint32_t*>(ctrl);
@@ -102,50 +205,39 @@ __global__ __launch_bounds__(kBlock) void init_kernel(InitArgs ia) {
 }
 
 // ---------------------------------------------------------------------------
-// Record of iteration t from the feed pass's block partials (one block).
+// Record of iteration t from its block partials (one whole block calls this).
 // ---------------------------------------------------------------------------
-__device__ void combine_block(const SchoolArgs& a, uint32_t t, uint32_t grid, uint32_t naive) {
-    __shared__ double part[3][kWaves];
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+template <int BLOCK = kBlock>
+__device__ void combine_block(const SchoolArgs& a, uint32_t t, uint32_t grid, uint32_t naive,
+                              uint32_t max_bits) {
+    constexpr int W = BLOCK / kWave;
+    __shared__ double part[3][W];
     if (!naive) {
-        const double* p = a.partials;  // phase 0
-        for (uint32_t b = threadIdx.x; b < grid; b += kBlock) {
-            acc0 += p[b];
-            acc1 += p[kMaxGrid + b];
-            acc2 += p[2 * kMaxGrid + b];
-        }
-        acc0 = wave_sum_f64(acc0);
-        acc1 = wave_sum_f64(acc1);
-        acc2 = wave_sum_f64(acc2);
-        const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-        if (lane == 0) {
-            part[0][wid] = acc0;
-            part[1][wid] = acc1;
-            part[2][wid] = acc2;
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (uint32_t b = threadIdx.x; b < grid; b += BLOCK)
+            for (int k = 0; k < 3; ++k) acc[k] += partial_slot(a, t, k)[b];
+        for (int k = 0; k < 3; ++k) {
+            acc[k] = wave_sum_f64(acc[k]);
+            if (threadIdx.x % kWave == 0) part[k][threadIdx.x / kWave] = acc[k];
         }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         fsb_record r;
-        if (!naive) {
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-            for (int w = 0; w < kWaves; ++w) {
-                s0 += part[0][w];
-                s1 += part[1][w];
-                s2 += part[2][w];
+        double s[3];
+        for (int k = 0; k < 3; ++k) {
+            if (!naive) {
+                s[k] = 0.0;
+                for (int w = 0; w < W; ++w) s[k] += part[k][w];
+            } else {
+                s[k] = (double)a.ctrl->naive_acc[t & 1u][k];
+                a.ctrl->naive_acc[t & 1u][k] = 0.0f;
             }
-            r.sum_w = s0;
-            r.sum_wx = s1;
-            r.sum_wy = s2;
-        } else {
-            r.sum_w = (double)a.ctrl->naive_acc[0];
-            r.sum_wx = (double)a.ctrl->naive_acc[1];
-            r.sum_wy = (double)a.ctrl->naive_acc[2];
-            a.ctrl->naive_acc[0] = 0.0f;
-            a.ctrl->naive_acc[1] = 0.0f;
-            a.ctrl->naive_acc[2] = 0.0f;
         }
-        r.max_delta = __uint_as_float(a.ctrl->last_max);
+        r.sum_w = s[0];
+        r.sum_wx = s[1];
+        r.sum_wy = s[2];
+        r.max_delta = __uint_as_float(max_bits);
         r.step_lo = t;
         a.hist[t % a.hist_len] = r;
     }
@@ -154,18 +246,18 @@ __device__ void combine_block(const SchoolArgs& a, uint32_t t, uint32_t grid, ui
 
 __global__ __launch_bounds__(kBlock) void combine_kernel(SchoolArgs a, uint32_t t, uint32_t grid,
                                                          uint32_t naive) {
-    combine_block(a, t, grid, naive);
+    combine_block(a, t, grid, naive, a.ctrl->last_max);
 }
 
 // ---------------------------------------------------------------------------
-// Swim pass.
+// Plain swim pass.
 // ---------------------------------------------------------------------------
 template <bool kInject>
 __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArgs s) {
-    __shared__ uint32_t wave_best[kWaves];
-    if (s.combine && blockIdx.x == 0) combine_block(a, s.prev_t, s.prev_grid, s.naive);
+    if (s.combine && blockIdx.x == 0)
+        combine_block(a, s.prev_t, s.prev_grid, s.naive, a.ctrl->last_max);
 
-    const float H = a.H, S = a.S;
+    const float H = a.H;
     const uint64_t n4 = a.n >> 2;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     uint32_t best = 0u;
@@ -191,12 +283,7 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
                 dx[0] = DX.x; dx[1] = DX.y; dx[2] = DX.z; dx[3] = DX.w;
                 dy[0] = DY.x; dy[1] = DY.y; dy[2] = DY.z; dy[3] = DY.w;
             } else {
-                const Words p0 = pair_words(2 * g, s.t, kDomainSwim, a.k0, a.k1);
-                const Words p1 = pair_words(2 * g + 1, s.t, kDomainSwim, a.k0, a.k1);
-                dx[0] = S * signed_unit(p0.r0); dy[0] = S * signed_unit(p0.r1);
-                dx[1] = S * signed_unit(p0.r2); dy[1] = S * signed_unit(p0.r3);
-                dx[2] = S * signed_unit(p1.r0); dy[2] = S * signed_unit(p1.r1);
-                dx[3] = S * signed_unit(p1.r2); dy[3] = S * signed_unit(p1.r3);
+                group_draws(a, g, s.t, dx, dy);
             }
             float4 nx = X[u], ny = Y[u], nc;
 #pragma unroll
@@ -218,10 +305,7 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
                 dx = s.dx[i];
                 dy = s.dy[i];
             } else {
-                const Words p = pair_words(i >> 1, s.t, kDomainSwim, a.k0, a.k1);
-                const bool odd = i & 1;
-                dx = S * signed_unit(odd ? p.r2 : p.r0);
-                dy = S * signed_unit(odd ? p.r3 : p.r1);
+                fish_draw(a, i, s.t, dx, dy);
             }
             float x = a.x[i], y = a.y[i];
             const float c = a.cur[i];
@@ -233,55 +317,29 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
             a.cur[i] = nc;
         }
     }
-    best = wave_max_u32(best);
-    if (threadIdx.x % kWave == 0) wave_best[threadIdx.x / kWave] = best;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t m = wave_best[0];
-        for (int w = 1; w < kWaves; ++w) m = max(m, wave_best[w]);
-        a.blockmax[blockIdx.x] = m;
-    }
+    const uint32_t m = block_max(best);
+    if (threadIdx.x == 0) a.blockmax[blockIdx.x] = m;
 }
 
 // ---------------------------------------------------------------------------
-// Feed pass.
+// Plain feed pass.
 // ---------------------------------------------------------------------------
-template <bool kNaive>
-__device__ __forceinline__ void accumulate(CSum* cs, float* fs, float w, float x, float y) {
-    const float wx = w * x;
-    const float wy = w * y;
-    if constexpr (kNaive) {
-        fs[0] += w;
-        fs[1] += wx;
-        fs[2] += wy;
-    } else {
-        csum_add(cs[0], w);
-        csum_add(cs[1], wx);
-        csum_add(cs[2], wy);
-    }
-}
-
 template <bool kNaive>
 __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArgs s) {
-    __shared__ uint32_t wave_best[kWaves];
-    __shared__ CSum wave_cs[3][kWaves];
-    __shared__ float wave_fs[3][kWaves];
-    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-
+    __shared__ uint32_t M_bits;
     // M = max over the swim pass's block maxima.
     uint32_t mb = 0u;
     for (uint32_t b = threadIdx.x; b < s.swim_grid; b += kBlock) mb = max(mb, a.blockmax[b]);
-    mb = wave_max_u32(mb);
-    if (lane == 0) wave_best[wid] = mb;
+    mb = block_max(mb);
+    if (threadIdx.x == 0) {
+        M_bits = mb;
+        if (blockIdx.x == 0) a.ctrl->last_max = mb;
+    }
     __syncthreads();
-    mb = wave_best[0];
-    for (int w = 1; w < kWaves; ++w) mb = max(mb, wave_best[w]);
-    const float M = __uint_as_float(mb);
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->last_max = mb;
+    const float M = __uint_as_float(M_bits);
 
     const float wmin = a.wmin, wmax = a.wmax;
-    CSum cs[3] = {{0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}};
-    float fs[3] = {0.0f, 0.0f, 0.0f};
+    LaneSums<kNaive> ls;
     const uint64_t n4 = a.n >> 2;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t g0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g0 < n4;
@@ -307,7 +365,7 @@ __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArg
             for (int k = 0; k < 4; ++k) {
                 const float diff = lane_of(P[u], k) - lane_of(C[u], k);
                 lane_of(nw, k) = feed(lane_of(W[u], k), diff, M, wmin, wmax);
-                accumulate<kNaive>(cs, fs, lane_of(nw, k), lane_of(X[u], k), lane_of(Y[u], k));
+                ls.add(lane_of(nw, k), lane_of(X[u], k), lane_of(Y[u], k));
             }
             st4(a.w, g, nw);
         }
@@ -318,40 +376,250 @@ __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArg
             const float diff = a.prev[i] - a.cur[i];
             const float nw = feed(a.w[i], diff, M, wmin, wmax);
             a.w[i] = nw;
-            accumulate<kNaive>(cs, fs, nw, a.x[i], a.y[i]);
+            ls.add(nw, a.x[i], a.y[i]);
         }
+    }
+    block_sums<kNaive>(a, ls, s.t);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent kernel: two-level grid barrier that also reduces the max.
+//
+// Thread 0 of each block folds the block's max into its group's max word and
+// arrives on the group counter (agent-scope acquire-release: the block's
+// partial sums and max are published).  The last arrival of a group resets
+// the group words, folds the group max into the root max and arrives on the
+// root counter; the last root arrival publishes M (slot s & 1), resets the
+// root words and advances the phase word the other blocks wait on.  Same-
+// address atomics, which serialise, number at most one group per address.
+// Waits are bounded: on timeout, or when another block has flagged an error,
+// every block leaves the kernel and the host reports FSB_ERR_DEVICE.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t arrive(uint32_t* p) {
+    return __hip_atomic_fetch_add(p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void max_agent(uint32_t* p, uint32_t v) {
+    __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Returns false if the launch must be abandoned.  `m` is this block's max;
+// on return *M_sh holds the grid max, published in slot `parity`.
+__device__ __forceinline__ bool barrier_max(const SchoolArgs& a, const FusedArgs& f, uint32_t m,
+                                           uint32_t parity, uint32_t& phase, uint32_t* M_sh) {
+    __shared__ int ok_sh;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t* sync = a.sync;
+        int ok = 1;
+        const uint32_t target = phase + 1u;
+        const uint32_t g = blockIdx.x / f.group_size;
+        const uint32_t members = min(f.group_size, gridDim.x - g * f.group_size);
+        uint32_t* grp = sync + kSyncGroups + g * kLineWords;
+        max_agent(grp + 1, m);
+        bool released = false;
+        if (arrive(grp) == members - 1u) {
+            const uint32_t gm = ld_agent(grp + 1);
+            st_agent(grp + 1, 0u);
+            st_agent(grp, 0u);
+            max_agent(sync + kSyncRootMax, gm);
+            if (arrive(sync + kSyncRootCount) == f.groups - 1u) {
+                const uint32_t M = ld_agent(sync + kSyncRootMax);
+                st_agent(sync + kSyncRootMax, 0u);
+                st_agent(sync + kSyncMaxPub + parity, M);
+                st_agent(sync + kSyncRootCount, 0u);
+                __hip_atomic_store(sync + kSyncPhase, target, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                released = true;
+            }
+        }
+        if (!released) {
+            uint32_t spins = 0;
+            while (ld_agent(sync + kSyncPhase) != target) {
+                if ((spins & 255u) == 0u && ld_agent(&a.ctrl->error)) {
+                    ok = 0;
+                    break;
+                }
+                if (++spins > kBarrierSpinLimit) {
+                    __hip_atomic_fetch_or(&a.ctrl->error, kErrBarrierTimeout, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        *M_sh = ld_agent(sync + kSyncMaxPub + parity);
+        phase = target;
+        ok_sh = ok;
+    }
+    __syncthreads();
+    return ok_sh != 0;
+}
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <bool kNT>
+__device__ __forceinline__ float4 ldv(const float* p, uint64_t g) {
+    if constexpr (kNT) {
+        const v4f v = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p) + g);
+        return make_float4(v.x, v.y, v.z, v.w);
+    } else {
+        return ld4(p, g);
+    }
+}
+template <bool kNT>
+__device__ __forceinline__ void stv(float* p, uint64_t g, float4 v) {
+    if constexpr (kNT) {
+        const v4f w = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(w, reinterpret_cast<v4f*>(p) + g);
+    } else {
+        st4(p, g, v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent multi-iteration kernel (1024 threads: one block per CU, so the
+// barrier has few participants).
+// ---------------------------------------------------------------------------
+constexpr int kFusedBlock = 1024;
+
+template <bool kNaive, bool kNT>
+__global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedArgs f) {
+    constexpr int B = kFusedBlock;
+    __shared__ uint32_t M_sh;
+    const float H = a.H, wmin = a.wmin, wmax = a.wmax;
+    const uint32_t grid = gridDim.x;
+    const uint64_t n4 = a.n >> 2;
+    const uint64_t stride = (uint64_t)grid * B;
+    const uint64_t gbase = (uint64_t)blockIdx.x * B + threadIdx.x;
+    const uint64_t tail_i = 4 * n4 + threadIdx.x;
+    const bool has_tail = blockIdx.x == grid - 1 && tail_i < a.n;
+    uint32_t phase = 0;
+    if (threadIdx.x == 0) phase = ld_agent(a.sync + kSyncPhase);
+
+    // Prologue: swim t0, keep (x, y, prev), M_t0.
+    {
+        uint32_t best = 0u;
+        for (uint64_t g = gbase; g < n4; g += stride) {
+            float4 X = ldv<kNT>(a.x, g), Y = ldv<kNT>(a.y, g), C = ldv<kNT>(a.cur, g);
+            float dx[4], dy[4];
+            group_draws(a, g, f.t0, dx, dy);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float nc = swim(lane_of(X, q), lane_of(Y, q), dx[q], dy[q], H);
+                best = max(best, mag_bits(lane_of(C, q) - nc));
+            }
+            stv<kNT>(a.x, g, X);
+            stv<kNT>(a.y, g, Y);
+            stv<kNT>(a.prev, g, C);
+        }
+        if (has_tail) {
+            float dx, dy;
+            fish_draw(a, tail_i, f.t0, dx, dy);
+            float x = a.x[tail_i], y = a.y[tail_i];
+            const float c = a.cur[tail_i];
+            const float nc = swim(x, y, dx, dy, H);
+            best = max(best, mag_bits(c - nc));
+            a.x[tail_i] = x;
+            a.y[tail_i] = y;
+            a.prev[tail_i] = c;
+        }
+        const uint32_t m = block_max<B>(best);
+        if (!barrier_max(a, f, m, f.t0 & 1u, phase, &M_sh)) return;
     }
 
-    if constexpr (kNaive) {
-        // Plain float32 trees, then float32 atomics across blocks.
+    for (uint32_t k = 0; k < f.steps; ++k) {
+        const uint32_t s = f.t0 + k;
+        const bool last = k + 1 == f.steps;
+        const float M = __uint_as_float(M_sh);
+        // Record of the previous iteration, by a rotating block.
+        if (k > 0 && blockIdx.x == (s - 1u) % grid)
+            combine_block<B>(a, s - 1u, grid, f.naive, ld_agent(a.sync + kSyncMaxPub + ((s - 1u) & 1u)));
+
+        LaneSums<kNaive> ls;
+        uint32_t best = 0u;
+        for (uint64_t g0 = gbase; g0 < n4; g0 += kUnroll * stride) {
+            float4 X[kUnroll], Y[kUnroll], W[kUnroll], P[kUnroll];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            fs[k] = wave_sum_f32(fs[k]);
-            if (lane == 0) wave_fs[k][wid] = fs[k];
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int k = 0; k < 3; ++k) {
-                float v = wave_fs[k][0];
-                for (int w = 1; w < kWaves; ++w) v += wave_fs[k][w];
-                atomicAdd(&a.ctrl->naive_acc[k], v);
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint64_t g = g0 + u * stride;
+                if (g < n4) {
+                    X[u] = ldv<kNT>(a.x, g);
+                    Y[u] = ldv<kNT>(a.y, g);
+                    W[u] = ldv<kNT>(a.w, g);
+                    P[u] = ldv<kNT>(a.prev, g);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint64_t g = g0 + u * stride;
+                if (g >= n4) break;
+                float4 C;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    lane_of(C, q) = distance(lane_of(X[u], q), lane_of(Y[u], q));
+                    const float diff = lane_of(P[u], q) - lane_of(C, q);
+                    lane_of(W[u], q) = feed(lane_of(W[u], q), diff, M, wmin, wmax);
+                    ls.add(lane_of(W[u], q), lane_of(X[u], q), lane_of(Y[u], q));
+                }
+                stv<kNT>(a.w, g, W[u]);
+                if (last) {
+                    stv<kNT>(a.cur, g, C);
+                } else {
+                    float dx[4], dy[4];
+                    group_draws(a, g, s + 1u, dx, dy);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const float nc =
+                            swim(lane_of(X[u], q), lane_of(Y[u], q), dx[q], dy[q], H);
+                        best = max(best, mag_bits(lane_of(C, q) - nc));
+                    }
+                    stv<kNT>(a.x, g, X[u]);
+                    stv<kNT>(a.y, g, Y[u]);
+                    stv<kNT>(a.prev, g, C);
+                }
             }
         }
-    } else {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            cs[k] = wave_csum(cs[k]);
-            if (lane == 0) wave_cs[k][wid] = cs[k];
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int k = 0; k < 3; ++k) {
-                double v = 0.0;
-                for (int w = 0; w < kWaves; ++w) v += csum_value(wave_cs[k][w]);
-                a.partials[k * kMaxGrid + blockIdx.x] = v;
+        if (has_tail) {
+            float x = a.x[tail_i], y = a.y[tail_i];
+            const float c = distance(x, y);
+            const float nw = feed(a.w[tail_i], a.prev[tail_i] - c, M, wmin, wmax);
+            a.w[tail_i] = nw;
+            ls.add(nw, x, y);
+            if (last) {
+                a.cur[tail_i] = c;
+            } else {
+                float dx, dy;
+                fish_draw(a, tail_i, s + 1u, dx, dy);
+                const float nc = swim(x, y, dx, dy, H);
+                best = max(best, mag_bits(c - nc));
+                a.x[tail_i] = x;
+                a.y[tail_i] = y;
+                a.prev[tail_i] = c;
             }
+        }
+        block_sums<kNaive, B>(a, ls, s);
+        if (last) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->last_max = M_sh;
+        } else {
+            const uint32_t m = block_max<B>(best);
+            if (!barrier_max(a, f, m, (s + 1u) & 1u, phase, &M_sh)) return;
         }
     }
+}
+
+// Clears the barrier's counters and maxima before a persistent launch (the
+// phase word only ever advances).
+__global__ void reset_sync_kernel(uint32_t* sync) {
+    for (uint32_t i = threadIdx.x; i < kSyncWords; i += blockDim.x)
+        if (i != kSyncPhase) sync[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -397,6 +665,63 @@ hipError_t launch_combine(const SchoolArgs& a, uint32_t t, uint32_t grid, uint32
                           hipStream_t stream) {
     hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(kBlock), 0, stream, a, t, grid, naive);
     return hipGetLastError();
+}
+
+template <bool kNaive, bool kNT>
+const void* fused_fn() {
+    return reinterpret_cast<const void*>(fused_kernel<kNaive, kNT>);
+}
+
+const void* pick_fused(uint32_t naive, uint32_t streaming) {
+    if (naive) return streaming ? fused_fn<true, true>() : fused_fn<true, false>();
+    return streaming ? fused_fn<false, true>() : fused_fn<false, false>();
+}
+
+hipError_t fused_resident_grid(uint32_t naive, uint32_t* out_grid) {
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    int per_cu = 1 << 30;
+    for (uint32_t nt = 0; nt < 2; ++nt) {  // both variants must fit
+        int b = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, pick_fused(naive, nt), kFusedBlock, 0);
+        if (e != hipSuccess) return e;
+        per_cu = b < per_cu ? b : per_cu;
+    }
+    uint64_t g = (uint64_t)cus * (uint64_t)(per_cu > 0 ? per_cu : 0);
+    if (g > kMaxGroups * 16ull) g = kMaxGroups * 16ull;
+    if (g > kMaxGrid) g = kMaxGrid;
+    *out_grid = (uint32_t)g;
+    return hipSuccess;
+}
+
+uint32_t fused_grid(uint64_t n, uint32_t resident) {
+    const uint64_t groups = n >> 2;
+    uint64_t g = (groups + kFusedBlock - 1) / kFusedBlock;
+    if (g < 1) g = 1;
+    if (g > resident) g = resident;
+    return (uint32_t)g;
+}
+
+void fused_groups(uint32_t grid, uint32_t* group_size, uint32_t* groups) {
+    uint32_t gs = 16;
+    while ((grid + gs - 1) / gs > kMaxGroups) gs *= 2;
+    *group_size = gs;
+    *groups = (grid + gs - 1) / gs;
+}
+
+hipError_t launch_fused(const SchoolArgs& a, const FusedArgs& f, uint32_t grid,
+                        hipStream_t stream) {
+    hipLaunchKernelGGL(reset_sync_kernel, dim3(1), dim3(256), 0, stream, a.sync);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    SchoolArgs sa = a;
+    FusedArgs fa = f;
+    void* args[] = {&sa, &fa};
+    return hipLaunchCooperativeKernel(pick_fused(f.naive, f.streaming), dim3(grid),
+                                      dim3(kFusedBlock), args, 0, stream);
 }
 
 }  // namespace fsb

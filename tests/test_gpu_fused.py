@@ -1,0 +1,126 @@
+"""Persistent (fused) mode: one cooperative launch per fsb_run, a grid
+barrier per iteration.  Columns and maxima must equal the oracle's (and the
+plain path's) bit for bit; sums within the 1e-6 gate."""
+import numpy as np
+import pytest
+
+import paper_2507_20173_amd as fsb
+from oracle.oracle import default
+from parity_util import assert_columns_equal, assert_sums_close, oracle_config
+
+pytestmark = pytest.mark.gpu
+FUSED, PLAIN = fsb.FSB_RUN_FUSED, fsb.FSB_RUN_PLAIN
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def O():
+    return default()
+
+
+def announce(msg):
+    print(f"[fused] {msg}", flush=True)
+
+
+def history_sums(h):
+    return np.stack([h["sum_w"], h["sum_wx"], h["sum_wy"]], 1)
+
+
+@pytest.mark.parametrize("n,steps", [(1, 5), (2, 3), (3, 1), (5, 7), (64, 4), (1001, 6),
+                                     (4097, 5), (65539, 4), ((1 << 20) + 3, 3),
+                                     ((1 << 23) + 6, 2)])
+def test_fused_matches_oracle(torch_cuda, O, n, steps):
+    announce(f"n={n} steps={steps}")
+    cfg = fsb.FsbConfig(n_fish=n, seed=4242 + n, history_len=steps)
+    ocfg = oracle_config(cfg)
+    school = O.init(ocfg)
+    m, s, a = O.run(ocfg, school, 0, steps)
+    sch = fsb.School(cfg)
+    sch.run(steps, FUSED)
+    h = sch.history(0, steps)
+    assert np.array_equal(h["step_lo"], np.arange(steps))
+    assert np.array_equal(h["max_delta"], m), f"maxima {h['max_delta']} vs {m}"
+    assert_sums_close(history_sums(h), s, a, what=f"fused n={n}")
+    assert_columns_equal(sch.state(), school, f"fused n={n}")
+    sch.close()
+
+
+def test_fused_plain_interleaved(torch_cuda, O):
+    """plain 2 + fused 3 + plain 1 + fused 1 + fused 4 == oracle 11."""
+    announce("interleaved")
+    n = 30_011
+    cfg = fsb.FsbConfig(n_fish=n, seed=5, history_len=11)
+    ocfg = oracle_config(cfg)
+    school = O.init(ocfg)
+    m, s, a = O.run(ocfg, school, 0, 11)
+    sch = fsb.School(cfg)
+    for k, mode in ((2, PLAIN), (3, FUSED), (1, PLAIN), (1, FUSED), (4, FUSED)):
+        sch.run(k, mode)
+    h = sch.history(0, 11)
+    assert np.array_equal(h["max_delta"], m)
+    assert_sums_close(history_sums(h), s, a, what="interleaved")
+    assert_columns_equal(sch.state(), school, "interleaved")
+
+
+def test_fused_naive_reduction(torch_cuda, O):
+    announce("naive")
+    n = 100_003
+    cfg = fsb.FsbConfig(n_fish=n, seed=6, reduce_mode=fsb.FSB_REDUCE_NAIVE_F32, history_len=4)
+    ocfg = oracle_config(cfg)
+    school = O.init(ocfg)
+    m, s, a = O.run(ocfg, school, 0, 4)
+    sch = fsb.School(cfg)
+    sch.run(4, FUSED)
+    h = sch.history(0, 4)
+    assert np.array_equal(h["max_delta"], m)
+    assert_sums_close(history_sums(h), s, a, tol=1e-3, what="fused naive")
+    assert_columns_equal(sch.state(), school, "fused naive")
+
+
+def test_fused_zero_swim(torch_cuda):
+    announce("zero swim")
+    cfg = fsb.FsbConfig(n_fish=7777, seed=3, swim_step=0.0, history_len=5)
+    sch = fsb.School(cfg)
+    before = sch.state()
+    sch.run(5, FUSED)
+    assert (sch.history(0, 5)["max_delta"] == 0).all()
+    after = sch.state()
+    for k in before:
+        assert np.array_equal(before[k], after[k]), k
+
+
+def test_fused_is_deterministic(torch_cuda):
+    """Same launch shape, same sums to the last bit."""
+    announce("determinism")
+    cfg = fsb.FsbConfig(n_fish=(1 << 20) + 1, seed=9, history_len=6)
+    runs = []
+    for _ in range(2):
+        sch = fsb.School(cfg)
+        sch.run(6, FUSED)
+        runs.append(sch.history(0, 6).tobytes())
+        sch.close()
+    assert runs[0] == runs[1]
+
+
+def test_cfg4_full_size_prefix(torch_cuda, O):
+    """N = 2^26 (the persistent-form workload) for the first iterations,
+    every fish bit-exact."""
+    n, steps = 1 << 26, 2
+    announce(f"cfg4 N={n} prefix {steps}")
+    cfg = fsb.FsbConfig(n_fish=n, seed=0, history_len=steps)
+    ocfg = oracle_config(cfg)
+    school = O.init(ocfg)
+    m, s, a = O.run(ocfg, school, 0, steps)
+    sch = fsb.School(cfg)
+    sch.run(steps, FUSED)
+    h = sch.history(0, steps)
+    assert np.array_equal(h["max_delta"], m)
+    assert_sums_close(history_sums(h), s, a, what="cfg4 prefix")
+    assert_columns_equal(sch.state(), school, "cfg4 prefix")
+    sch.close()
