@@ -138,6 +138,64 @@ def fused_vs_plain(n: int, steps: int, label: str):
     }
 
 
+def precision_form(n: int, steps: int, oracle_steps: int):
+    """Compensated (default) vs naive float32-atomic barycentre sums on one
+    school: throughput of each, and the error of each recorded iteration
+    against the oracle's binary64 sums (first `oracle_steps` iterations) and
+    against numpy's binary64 sums of the final columns (last iteration)."""
+    import numpy as np
+    import torch
+
+    import paper_2507_20173_amd as fsb
+    from oracle.oracle import Config, default
+
+    out = {"workload": f"precision form: N=2^{n.bit_length() - 1} fish, {steps} iterations, "
+                       "per-iteration launches; compensated float32 lane sums + binary64 block "
+                       "combine vs float32 trees + float32 atomicAdd",
+           "n_fish": n, "iterations": steps}
+    recs = {}
+    for name, mode in (("compensated", fsb.FSB_REDUCE_COMPENSATED),
+                       ("naive_f32_atomics", fsb.FSB_REDUCE_NAIVE_F32)):
+        cfg = fsb.FsbConfig(n_fish=n, seed=0, reduce_mode=mode, history_len=steps)
+        sch = fsb.School(cfg)
+        sch.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sch.run(steps)
+        sch.sync()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        hist = sch.history(0, steps)
+        final = sch.state()
+        sch.close()
+        del sch
+        torch.cuda.empty_cache()
+        w = final["w"].astype(np.float64)
+        ref = np.array([w.sum(), (w * final["x"]).sum(), (w * final["y"]).sum()])
+        den = np.array([w.sum(), np.abs(w * final["x"]).sum(), np.abs(w * final["y"]).sum()])
+        got = np.array([hist["sum_w"][-1], hist["sum_wx"][-1], hist["sum_wy"][-1]])
+        recs[name] = hist
+        out[name] = {"value": n * steps / wall, "ms_per_step": wall / steps * 1e3,
+                     "last_iteration_error_vs_columns": (np.abs(got - ref) / den).tolist()}
+    O = default()
+    ocfg = Config(numFish=n, seed=0)
+    school = O.init(ocfg)
+    per_step = {k: [] for k in recs}
+    for t in range(oracle_steps):
+        m, s_ref, a_ref = O.step(ocfg, school, t)
+        for k, hist in recs.items():
+            got = np.array([hist["sum_w"][t], hist["sum_wx"][t], hist["sum_wy"][t]])
+            per_step[k].append({"iteration": t, "max_exact": bool(hist["max_delta"][t] == m),
+                                "error": (np.abs(got - s_ref) / a_ref).tolist()})
+    del school
+    for k in recs:
+        out[k]["error_vs_oracle"] = per_step[k]
+        out[k]["max_error_vs_oracle"] = max(max(e["error"]) for e in per_step[k])
+    out["error_definition"] = ("|got - ref| / sum|terms| per sum (sum w, sum w*x, sum w*y); "
+                               "ref = oracle binary64 Neumaier sums of exact products")
+    return out
+
+
 def cpu_baseline(n: int, budget_s: float = 12.0, max_steps: int = 400):
     """The oracle as it stands, on this host's cores, on a bounded prefix of
     the same workload."""
@@ -166,6 +224,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-only", action="store_true", help="skip the fused/batched forms")
     ap.add_argument("--fused-steps", type=int, default=2000)
+    ap.add_argument("--precision-steps", type=int, default=200)
+    ap.add_argument("--precision-oracle-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         log(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -214,6 +274,9 @@ def main() -> int:
             "fused_cfg2": fused_vs_plain(n, args.steps, "persistent form on the headline school "
                                                         "(N=2^24, 1000 iterations)"),
         }
+    if not args.plain_only:
+        line["forms"]["precision_cfg3"] = precision_form(1 << 27, args.precision_steps,
+                                                         args.precision_oracle_steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(line), flush=True)

@@ -1,0 +1,45 @@
+"""Precision form at full size (N = 2^27): the compensated reduction stays
+within the 1e-6 gate of the oracle's binary64 sums; the naive float32-atomic
+baseline changes only the sums, never the columns or the max."""
+import numpy as np
+import pytest
+
+import paper_2507_20173_amd as fsb
+from oracle.oracle import default
+from parity_util import assert_columns_equal, oracle_config, sum_errors
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    return torch
+
+
+def test_cfg3_full_size_compensated_vs_naive(torch_cuda):
+    n, steps = 1 << 27, 2
+    print(f"[precision] N={n} steps={steps}", flush=True)
+    O = default()
+    ocfg = oracle_config(fsb.FsbConfig(n_fish=n, seed=0))
+    school = O.init(ocfg)
+    m, s, a = O.run(ocfg, school, 0, steps)
+    errs = {}
+    for mode in (fsb.FSB_REDUCE_COMPENSATED, fsb.FSB_REDUCE_NAIVE_F32):
+        sch = fsb.School(fsb.FsbConfig(n_fish=n, seed=0, reduce_mode=mode, history_len=steps))
+        sch.run(steps)
+        h = sch.history(0, steps)
+        assert np.array_equal(h["max_delta"], m)
+        got = np.stack([h["sum_w"], h["sum_wx"], h["sum_wy"]], 1)
+        errs[mode] = sum_errors(got, s, a)
+        if mode == fsb.FSB_REDUCE_COMPENSATED:
+            assert_columns_equal(sch.state(), school, "cfg3")
+        sch.close()
+        del sch
+        torch_cuda.cuda.empty_cache()
+    comp, naive = errs[fsb.FSB_REDUCE_COMPENSATED], errs[fsb.FSB_REDUCE_NAIVE_F32]
+    print(f"[precision] compensated max error {comp.max():.3e}, naive {naive.max():.3e}",
+          flush=True)
+    assert (comp <= 1e-6).all()
+    assert comp.max() < naive.max()
