@@ -110,6 +110,16 @@ typedef struct fsb_record {
 } fsb_record;
 
 typedef struct fsb_school fsb_school; /* opaque host-side handle */
+typedef struct fsb_batch fsb_batch;   /* opaque host-side handle */
+
+/* Launch shape of the persistent batched kernel. */
+typedef struct fsb_tuning {
+    uint32_t block_size;       /* threads per block: 256 or 1024 */
+    uint32_t fish_per_thread;  /* fish per lane per tile: 4, 8 or 16 (a tile is one
+                                  wavefront's share of one school: 64 x this many fish) */
+    uint32_t steps_per_launch; /* iterations per persistent launch, >= 1 */
+    uint32_t blocks_per_cu;    /* resident blocks per compute unit to use (0 = all that fit) */
+} fsb_tuning;
 
 /* ---- errors ------------------------------------------------------------ */
 
@@ -190,6 +200,67 @@ int fsb_set_step_index(fsb_school *h, uint64_t t);
  * the stream's work is done). */
 int fsb_destroy(fsb_school *h);
 
+/* ---- batch of independent schools ------------------------------------- */
+
+/* Many independent schools advanced together (the same iteration on every
+ * school): school s holds fish [starts[s], starts[s] + sizes[s]) of packed
+ * float32 columns of length packed_len (caller-owned device memory, the
+ * same five columns as one school).  starts[s] is a multiple of 4 (each
+ * school 16-byte aligned), starts are increasing and schools do not
+ * overlap; gaps are allowed and never touched.  School s draws from its own
+ * Philox key seeds[s] with the same counter layout as a single school, so
+ * school s evolves exactly as a single school of sizes[s] fish with seed
+ * seeds[s] would.  All host arrays are read during the call only. */
+
+/* Workspace bytes for such a batch (pure host arithmetic).  common supplies
+ * H, S, the weight ranges, reduce_mode and history_len; its n_fish and seed
+ * are ignored. */
+int fsb_batch_workspace_bytes(const fsb_config *common, uint32_t n_schools,
+                              const uint64_t *starts, const uint64_t *sizes,
+                              size_t *out_bytes);
+
+/* Initialise every school (Sec. 2.1.1 draws, per-school key) and return a
+ * handle at iteration 0 with the default tuning (1024 threads, 8 fish per
+ * lane, 100 iterations per launch).  Uploads the school tables (synchronous
+ * copies), then enqueues the init kernel on `stream`. */
+int fsb_batch_init(const fsb_config *common, uint32_t n_schools,
+                   const uint64_t *starts, const uint64_t *sizes,
+                   const uint64_t *seeds, fsb_state packed, uint64_t packed_len,
+                   void *workspace, size_t workspace_bytes, void *stream,
+                   fsb_batch **out);
+
+/* n_steps iterations of every school: persistent launches of
+ * steps_per_launch iterations (one grid barrier per iteration), each launch
+ * a replay of a captured HIP graph.  tuning NULL keeps the handle's tuning;
+ * otherwise it becomes the handle's tuning.  Per-fish state and maxima do
+ * not depend on the tuning (sums agree to rounding).  Asynchronous. */
+int fsb_batch_run(fsb_batch *b, uint64_t n_steps, const fsb_tuning *tuning);
+
+/* Results of the last completed iteration, per school: out_xy[2*n_schools]
+ * barycentres (nullable), out_sums[3*n_schools] (sum w, sum w*x, sum w*y;
+ * nullable), out_max[n_schools] (M; nullable).  Synchronises.
+ * FSB_ERR_STATE before the first iteration. */
+int fsb_batch_results(fsb_batch *b, double *out_xy, double *out_sums,
+                      float *out_max);
+
+/* Records of iteration `step` for every school (out[n_schools]); the
+ * iteration must still be in the history ring.  Synchronises. */
+int fsb_batch_history(fsb_batch *b, uint64_t step, fsb_record *out);
+
+/* Time candidate tunings (256 or 1024 threads x 4, 8 or 16 fish per lane,
+ * then iterations per launch), each on probe_steps real iterations (the
+ * schools advance), keep the fastest as the handle's tuning and copy it to
+ * *out.  If the environment variable FSB_AUTOTUNE_CACHE names a file, a
+ * tuning recorded there for this device and batch shape is reused without
+ * probing, and new results are appended.  Synchronises. */
+int fsb_autotune(fsb_batch *b, uint64_t probe_steps, fsb_tuning *out);
+
+int fsb_batch_get_tuning(const fsb_batch *b, fsb_tuning *out);
+int fsb_batch_step_index(const fsb_batch *b, uint64_t *out_t);
+/* Wait for the handle's work; reports asynchronous HIP or kernel errors. */
+int fsb_batch_sync(fsb_batch *b);
+int fsb_batch_destroy(fsb_batch *b);
+
 /* ---- instrumentation --------------------------------------------------- */
 
 /* Kernel timing: when enabled, every kernel the handle launches is
@@ -205,6 +276,9 @@ int fsb_destroy(fsb_school *h);
 int fsb_profile_enable(fsb_school *h, int enable);
 int fsb_kernel_times(fsb_school *h, uint64_t counts[FSB_KERNEL_KINDS],
                      double ms[FSB_KERNEL_KINDS]);
+/* The same for a batch: launches of the persistent batched kernel. */
+int fsb_batch_profile_enable(fsb_batch *b, int enable);
+int fsb_batch_kernel_times(fsb_batch *b, uint64_t *count, double *ms);
 
 #ifdef __cplusplus
 }

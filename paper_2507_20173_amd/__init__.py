@@ -152,7 +152,98 @@ def fsb_kernel_times(h) -> tuple[np.ndarray, np.ndarray]:
     return np.array(counts[:], np.uint64), np.array(ms[:])
 
 
-# ---- convenience owner --------------------------------------------------------
+# ---- batch entry points ---------------------------------------------------------
+
+def _u64_array(v) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(v, dtype=np.uint64))
+
+
+def fsb_batch_workspace_bytes(common: FsbConfig, starts, sizes) -> int:
+    st, sz = _u64_array(starts), _u64_array(sizes)
+    out = ctypes.c_size_t()
+    c = common.c()
+    check(lib().fsb_batch_workspace_bytes(ctypes.byref(c), sz.size, st.ctypes.data,
+                                          sz.ctypes.data, ctypes.byref(out)))
+    return out.value
+
+
+def fsb_batch_init(common: FsbConfig, starts, sizes, seeds, cols: dict, workspace,
+                   stream=None) -> ctypes.c_void_p:
+    st, sz, sd = _u64_array(starts), _u64_array(sizes), _u64_array(seeds)
+    h = ctypes.c_void_p()
+    c = common.c()
+    check(lib().fsb_batch_init(ctypes.byref(c), sz.size, st.ctypes.data, sz.ctypes.data,
+                               sd.ctypes.data, state_struct(cols), cols["x"].numel(),
+                               _ptr(workspace), workspace.numel() * workspace.element_size(),
+                               _stream_handle(stream), ctypes.byref(h)))
+    return h
+
+
+def tuning(block_size=1024, fish_per_thread=8, steps_per_launch=100, blocks_per_cu=0):
+    return _lib.fsb_tuning(block_size, fish_per_thread, steps_per_launch, blocks_per_cu)
+
+
+def tuning_dict(t: _lib.fsb_tuning) -> dict:
+    return {k: getattr(t, k) for k, _ in _lib.fsb_tuning._fields_}
+
+
+def fsb_batch_run(b, n_steps: int, tune: _lib.fsb_tuning | None = None) -> None:
+    check(lib().fsb_batch_run(b, n_steps, ctypes.byref(tune) if tune is not None else None))
+
+
+def fsb_batch_results(b, n_schools: int):
+    xy = np.zeros((n_schools, 2), np.float64)
+    sums = np.zeros((n_schools, 3), np.float64)
+    mx = np.zeros(n_schools, np.float32)
+    check(lib().fsb_batch_results(b, xy.ctypes.data_as(_lib._DP), sums.ctypes.data_as(_lib._DP),
+                                  mx.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return xy, sums, mx
+
+
+def fsb_batch_history(b, step: int, n_schools: int) -> np.ndarray:
+    out = np.zeros(n_schools, RECORD)
+    check(lib().fsb_batch_history(b, step, out.ctypes.data_as(ctypes.POINTER(_lib.fsb_record))))
+    return out
+
+
+def fsb_autotune(b, probe_steps: int) -> _lib.fsb_tuning:
+    t = _lib.fsb_tuning()
+    check(lib().fsb_autotune(b, probe_steps, ctypes.byref(t)))
+    return t
+
+
+def fsb_batch_get_tuning(b) -> _lib.fsb_tuning:
+    t = _lib.fsb_tuning()
+    check(lib().fsb_batch_get_tuning(b, ctypes.byref(t)))
+    return t
+
+
+def fsb_batch_step_index(b) -> int:
+    t = ctypes.c_uint64()
+    check(lib().fsb_batch_step_index(b, ctypes.byref(t)))
+    return t.value
+
+
+def fsb_batch_sync(b) -> None:
+    check(lib().fsb_batch_sync(b))
+
+
+def fsb_batch_destroy(b) -> None:
+    check(lib().fsb_batch_destroy(b))
+
+
+def fsb_batch_profile_enable(b, enable: bool = True) -> None:
+    check(lib().fsb_batch_profile_enable(b, 1 if enable else 0))
+
+
+def fsb_batch_kernel_times(b) -> tuple[int, float]:
+    n = ctypes.c_uint64()
+    ms = ctypes.c_double()
+    check(lib().fsb_batch_kernel_times(b, ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+# ---- convenience owners ---------------------------------------------------------
 
 def alloc_columns(n: int, device="cuda"):
     import torch
@@ -212,6 +303,70 @@ class School:
     def close(self):
         if getattr(self, "h", None) is not None:
             fsb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent schools of the given sizes and seeds, packed back to back
+    (each start rounded up to a multiple of 4 fish) in five columns
+    allocated with PyTorch, plus the workspace."""
+
+    def __init__(self, common: FsbConfig, sizes, seeds, starts=None, stream=None,
+                 device="cuda"):
+        import torch
+
+        from .workloads import packed_starts
+        self.sizes = _u64_array(sizes)
+        self.seeds = _u64_array(seeds)
+        self.starts = _u64_array(packed_starts(self.sizes) if starts is None else starts)
+        self.n = int(self.sizes.size)
+        self.common = common
+        length = int(self.starts[-1] + self.sizes[-1])
+        length = (length + 3) // 4 * 4
+        self.cols = alloc_columns(length, device)
+        self.workspace = torch.empty(fsb_batch_workspace_bytes(common, self.starts, self.sizes),
+                                     dtype=torch.uint8, device=device)
+        self.h = fsb_batch_init(common, self.starts, self.sizes, self.seeds, self.cols,
+                                self.workspace, stream)
+
+    def run(self, n_steps: int, tune=None):
+        fsb_batch_run(self.h, n_steps, tune)
+
+    def results(self):
+        return fsb_batch_results(self.h, self.n)
+
+    def history(self, step: int):
+        return fsb_batch_history(self.h, step, self.n)
+
+    def autotune(self, probe_steps: int):
+        return fsb_autotune(self.h, probe_steps)
+
+    @property
+    def tuning(self):
+        return fsb_batch_get_tuning(self.h)
+
+    @property
+    def t(self) -> int:
+        return fsb_batch_step_index(self.h)
+
+    def sync(self):
+        fsb_batch_sync(self.h)
+
+    def school_state(self, s: int) -> dict:
+        """Columns of school s copied to host numpy arrays (synchronises)."""
+        self.sync()
+        a, n = int(self.starts[s]), int(self.sizes[s])
+        return {k: v[a:a + n].cpu().numpy() for k, v in self.cols.items()}
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            fsb_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

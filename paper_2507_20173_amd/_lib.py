@@ -49,6 +49,11 @@ class fsb_record(ctypes.Structure):
                 ("step_lo", ctypes.c_uint32)]
 
 
+class fsb_tuning(ctypes.Structure):
+    _fields_ = [("block_size", ctypes.c_uint32), ("fish_per_thread", ctypes.c_uint32),
+                ("steps_per_launch", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32)]
+
+
 class FsbError(RuntimeError):
     def __init__(self, code: int, message: str):
         super().__init__(f"{message} [code {code}]")
@@ -81,6 +86,20 @@ PROTOTYPES = {
     "fsb_destroy": (_I, [_P]),
     "fsb_profile_enable": (_I, [_P, _I]),
     "fsb_kernel_times": (_I, [_P, ctypes.POINTER(_U64), _DP]),
+    "fsb_batch_workspace_bytes": (_I, [ctypes.POINTER(fsb_config), _U32, _P, _P,
+                                       ctypes.POINTER(ctypes.c_size_t)]),
+    "fsb_batch_init": (_I, [ctypes.POINTER(fsb_config), _U32, _P, _P, _P, fsb_state, _U64, _P,
+                            ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+    "fsb_batch_run": (_I, [_P, _U64, ctypes.POINTER(fsb_tuning)]),
+    "fsb_batch_results": (_I, [_P, _DP, _DP, ctypes.POINTER(ctypes.c_float)]),
+    "fsb_batch_history": (_I, [_P, _U64, ctypes.POINTER(fsb_record)]),
+    "fsb_autotune": (_I, [_P, _U64, ctypes.POINTER(fsb_tuning)]),
+    "fsb_batch_get_tuning": (_I, [_P, ctypes.POINTER(fsb_tuning)]),
+    "fsb_batch_step_index": (_I, [_P, ctypes.POINTER(_U64)]),
+    "fsb_batch_sync": (_I, [_P]),
+    "fsb_batch_destroy": (_I, [_P]),
+    "fsb_batch_profile_enable": (_I, [_P, _I]),
+    "fsb_batch_kernel_times": (_I, [_P, ctypes.POINTER(_U64), _DP]),
 }
 
 _lib: ctypes.CDLL | None = None

@@ -11,123 +11,10 @@
 #include <vector>
 
 #include "fsb.h"
+#include "fsb_host.hpp"
 #include "fsb_internal.hpp"
 
 using namespace fsb;
-
-namespace {
-
-thread_local std::string g_last_error;
-
-int fail(int code, const std::string& msg) {
-    g_last_error = msg;
-    return code;
-}
-
-int hip_fail(hipError_t e, const char* what) {
-    g_last_error = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
-    return FSB_ERR_HIP;
-}
-
-#define FSB_HIP_TRY(expr, what)                 \
-    do {                                        \
-        hipError_t e_ = (expr);                 \
-        if (e_ != hipSuccess) return hip_fail(e_, what); \
-    } while (0)
-
-constexpr uint64_t kMaxFish = 1ull << 40;
-constexpr uint32_t kMaxHistory = 1u << 24;
-constexpr uint64_t kStepLimit = 1ull << 32;  // iteration index fills one counter word
-
-int check_config(const fsb_config* c, bool need_fish) {
-    if (!c) return fail(FSB_ERR_INVALID_ARG, "config is NULL");
-    if (need_fish && c->n_fish == 0) return fail(FSB_ERR_INVALID_ARG, "n_fish must be >= 1");
-    if (c->n_fish > kMaxFish) return fail(FSB_ERR_INVALID_ARG, "n_fish exceeds 2^40");
-    if (!(std::isfinite(c->pond_half) && c->pond_half > 0.0f))
-        return fail(FSB_ERR_INVALID_ARG, "pond_half must be finite and > 0");
-    if (!(std::isfinite(c->swim_step) && c->swim_step >= 0.0f))
-        return fail(FSB_ERR_INVALID_ARG, "swim_step must be finite and >= 0");
-    if (!(std::isfinite(c->w_init_lo) && std::isfinite(c->w_init_hi) && c->w_init_lo <= c->w_init_hi))
-        return fail(FSB_ERR_INVALID_ARG, "need finite w_init_lo <= w_init_hi");
-    if (!(std::isfinite(c->w_min) && std::isfinite(c->w_max) && c->w_min <= c->w_max))
-        return fail(FSB_ERR_INVALID_ARG, "need finite w_min <= w_max");
-    if (c->reduce_mode != FSB_REDUCE_COMPENSATED && c->reduce_mode != FSB_REDUCE_NAIVE_F32)
-        return fail(FSB_ERR_INVALID_ARG, "unknown reduce_mode");
-    if (c->history_len == 0 || c->history_len > kMaxHistory)
-        return fail(FSB_ERR_INVALID_ARG, "history_len must be in [1, 2^24]");
-    return FSB_OK;
-}
-
-bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
-
-int check_columns(const fsb_state& s, uint64_t n) {
-    const float* cols[5] = {s.x, s.y, s.w, s.prev, s.cur};
-    const char* names[5] = {"x", "y", "w", "prev", "cur"};
-    for (int i = 0; i < 5; ++i) {
-        if (!cols[i]) return fail(FSB_ERR_INVALID_ARG, std::string("column ") + names[i] + " is NULL");
-        if (!aligned(cols[i], 16))
-            return fail(FSB_ERR_INVALID_ARG, std::string("column ") + names[i] + " is not 16-byte aligned");
-    }
-    const uintptr_t bytes = (uintptr_t)n * sizeof(float);
-    for (int i = 0; i < 5; ++i)
-        for (int j = i + 1; j < 5; ++j) {
-            const uintptr_t a = reinterpret_cast<uintptr_t>(cols[i]);
-            const uintptr_t b = reinterpret_cast<uintptr_t>(cols[j]);
-            if (a < b + bytes && b < a + bytes)
-                return fail(FSB_ERR_INVALID_ARG, std::string("columns ") + names[i] + " and " +
-                                                     names[j] + " overlap");
-        }
-    return FSB_OK;
-}
-
-int check_workspace(void* ws, size_t bytes, size_t need) {
-    if (!ws) return fail(FSB_ERR_INVALID_ARG, "workspace is NULL");
-    if (!aligned(ws, kAlign)) return fail(FSB_ERR_INVALID_ARG, "workspace is not 256-byte aligned");
-    if (bytes < need)
-        return fail(FSB_ERR_INVALID_ARG, "workspace too small: " + std::to_string(bytes) + " < " +
-                                             std::to_string(need) + " bytes");
-    return FSB_OK;
-}
-
-// Pairs of HIP events bracketing launches of one kernel kind.
-struct Timer {
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
-    size_t used = 0;
-    ~Timer() {
-        for (auto& p : pool) {
-            (void)hipEventDestroy(p.first);
-            (void)hipEventDestroy(p.second);
-        }
-    }
-    hipError_t next(std::pair<hipEvent_t, hipEvent_t>** out) {
-        if (used == pool.size()) {
-            std::pair<hipEvent_t, hipEvent_t> p{nullptr, nullptr};
-            hipError_t e = hipEventCreate(&p.first);
-            if (e != hipSuccess) return e;
-            e = hipEventCreate(&p.second);
-            if (e != hipSuccess) {
-                (void)hipEventDestroy(p.first);
-                return e;
-            }
-            pool.push_back(p);
-        }
-        *out = &pool[used++];
-        return hipSuccess;
-    }
-    hipError_t total(double* ms) {
-        double sum = 0.0;
-        for (size_t i = 0; i < used; ++i) {
-            float v = 0.0f;
-            hipError_t e = hipEventElapsedTime(&v, pool[i].first, pool[i].second);
-            if (e != hipSuccess) return e;
-            sum += v;
-        }
-        *ms = sum;
-        return hipSuccess;
-    }
-};
-
-}  // namespace
 
 struct fsb_school {
     fsb_config cfg;
@@ -332,7 +219,7 @@ const char* fsb_strerror(int code) {
     }
 }
 
-const char* fsb_last_error(void) { return g_last_error.c_str(); }
+const char* fsb_last_error(void) { return last_error().c_str(); }
 
 int fsb_abi_version(void) { return FSB_ABI_VERSION; }
 

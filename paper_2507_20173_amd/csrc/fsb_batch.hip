@@ -1,0 +1,370 @@
+// fsb_batch.hip -- many independent schools of uneven size advanced together
+// by one persistent launch of several iterations.
+//
+// Work is cut into tiles: a tile is one wavefront's share of one school
+// (64 lanes x fish_per_lane fish, the last tile of a school ragged).  Tile tl
+// belongs to wavefront tl mod (waves in the grid) for every sweep, so each
+// fish stays with one lane.  Per iteration every tile
+//   - reads its school's M_s (slot s % 3 of the per-school max ring),
+//   - feeds, accumulates compensated lane sums, swims the next iteration,
+//   - reduces over the wave (butterflies, no LDS): lane 0 stores the tile's
+//     binary64 partials and folds the tile max into its school's next slot
+//     with one device-scope atomic max.
+// The grid barrier (shared with the single-school persistent kernel) then
+// separates iterations.  After it, one wavefront per school folds that
+// school's tile partials in tile order (deterministic) into the school's
+// record and clears the used max slot.  Same 32 B/fish per iteration as the
+// single-school persistent kernel; schools differ only in key and range.
+// The first iteration index is read from a device counter that each launch
+// advances, so one captured launch can be replayed as a graph.
+#include "fsb_sweep.hpp"
+
+namespace fsb {
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// ---------------------------------------------------------------------------
+// Initial state of every school (not persistent).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void batch_init_fish(const BatchArgs& a, uint32_t k0, uint32_t k1,
+                                                uint64_t i, float& x, float& y, float& w,
+                                                float& c) {
+    const Words p = pair_words(i >> 1, 0, kDomainInit, k0, k1);
+    const Words q = pair_words(i >> 1, 1, kDomainInit, k0, k1);
+    const bool odd = i & 1;
+    x = a.H * signed_unit(odd ? p.r2 : p.r0);
+    y = a.H * signed_unit(odd ? p.r3 : p.r1);
+    const float span = a.whi - a.wlo;
+    w = a.wlo + span * unit(odd ? q.r2 : q.r0);
+    c = distance(x, y);
+}
+
+__global__ __launch_bounds__(256) void batch_init_kernel(BatchArgs a) {
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint32_t wave = uniform(blockIdx.x * (256 / kWave) + threadIdx.x / kWave);
+    const uint32_t n_waves = gridDim.x * (256 / kWave);
+    for (uint32_t tl = wave; tl < a.n_tiles; tl += n_waves) {
+        const Tile T = a.tiles[tl];
+        const uint32_t k0 = a.key[2 * T.school], k1 = a.key[2 * T.school + 1];
+        const uint64_t base = a.start[T.school], size = a.size[T.school];
+        for (uint32_t j = lane; j < T.n_groups; j += kWave) {
+            const uint64_t g = T.group0 + j;
+            for (int q = 0; q < 4; ++q) {
+                const uint64_t i = 4 * g + q;
+                if (i >= size) break;
+                float x, y, w, c;
+                batch_init_fish(a, k0, k1, i, x, y, w, c);
+                a.x[base + i] = x;
+                a.y[base + i] = y;
+                a.w[base + i] = w;
+                a.prev[base + i] = c;
+                a.cur[base + i] = c;
+            }
+        }
+    }
+}
+
+// Clears the barrier words, the per-school max ring and the naive sums
+// before a persistent launch (a kernel, so it can live in a graph).
+__global__ void batch_reset_kernel(BatchArgs a) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nth = gridDim.x * blockDim.x;
+    for (uint32_t i = tid; i < kSyncWords; i += nth)
+        if (i != kSyncPhase) a.sync[i] = 0u;
+    for (uint32_t i = tid; i < 3 * a.n_schools; i += nth) a.school_max[i] = 0u;
+    for (uint32_t i = tid; i < 8 * a.n_schools; i += nth) a.school_naive[i] = 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Record of iteration s for every school: one wavefront per school folds the
+// school's tile partials (lanes stride over tiles in order, then a butterfly).
+// ---------------------------------------------------------------------------
+template <bool kNaive>
+__device__ void combine_schools(const BatchArgs& a, uint32_t s, uint32_t wave, uint32_t n_waves,
+                                uint32_t lane) {
+    const uint32_t S = a.n_schools;
+    for (uint32_t c = wave; c < S; c += n_waves) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        if constexpr (!kNaive) {
+            const uint32_t tb = a.tile_begin[c], te = a.tile_begin[c + 1];
+            const double* part = a.tile_part + (size_t)(s & 1u) * 3 * a.tile_cap;
+            for (uint32_t i = tb + lane; i < te; i += kWave)
+                for (int k = 0; k < 3; ++k) acc[k] += part[(size_t)k * a.tile_cap + i];
+            for (int k = 0; k < 3; ++k) acc[k] = wave_sum_f64(acc[k]);
+        }
+        if (lane == 0) {
+            uint32_t* slot = a.school_max + (size_t)(s % 3u) * S + c;
+            fsb_record r;
+            if constexpr (kNaive) {
+                float* ns = a.school_naive + ((size_t)(s & 1u) * S + c) * 4;
+                for (int k = 0; k < 3; ++k) {
+                    acc[k] = (double)ns[k];
+                    ns[k] = 0.0f;
+                }
+            }
+            r.sum_w = acc[0];
+            r.sum_wx = acc[1];
+            r.sum_wy = acc[2];
+            r.max_delta = __uint_as_float(ld_agent(slot));
+            r.step_lo = s;
+            a.rec[(size_t)(s % a.hist_len) * S + c] = r;
+            st_agent(slot, 0u);
+        }
+    }
+}
+
+// Wave-wide sums of one tile -> its partial (lane 0 stores).
+template <bool kNaive>
+__device__ __forceinline__ void tile_sums(const BatchArgs& a, LaneSums<kNaive>& ls, uint32_t s,
+                                          uint32_t tl, uint32_t school, uint32_t lane) {
+    if constexpr (kNaive) {
+        float v[3];
+        for (int k = 0; k < 3; ++k) v[k] = wave_sum_f32(ls.f[k]);
+        if (lane == 0) {
+            float* ns = a.school_naive + ((size_t)(s & 1u) * a.n_schools + school) * 4;
+            for (int k = 0; k < 3; ++k) atomicAdd(ns + k, v[k]);
+        }
+    } else {
+        double v[3];
+        for (int k = 0; k < 3; ++k) v[k] = csum_value(wave_csum(ls.c[k]));
+        if (lane == 0) {
+            double* part = a.tile_part + (size_t)(s & 1u) * 3 * a.tile_cap;
+            for (int k = 0; k < 3; ++k) part[(size_t)k * a.tile_cap + tl] = v[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched kernel.  GPL = groups of four fish per lane per tile.
+// ---------------------------------------------------------------------------
+template <int BLOCK, int GPL, bool kNaive, bool kNT>
+__global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
+    constexpr uint32_t WPB = BLOCK / kWave;
+    __shared__ uint32_t M_sh;
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint32_t wave = uniform(blockIdx.x * WPB + threadIdx.x / kWave);
+    const uint32_t n_waves = gridDim.x * WPB;
+    const uint32_t S = a.n_schools;
+    const float H = a.H, Sw = a.S, wmin = a.wmin, wmax = a.wmax;
+    const Barrier bar{a.sync, a.ctrl, a.group_size, a.groups};
+    uint32_t phase = 0;
+    if (threadIdx.x == 0) phase = ld_agent(a.sync + kSyncPhase);
+    const uint32_t t0 = uniform(ld_agent(a.step));
+
+    // Prologue: swim t0 from (x, y, cur), keep (x, y, prev), school maxima.
+    for (uint32_t tl = wave; tl < a.n_tiles; tl += n_waves) {
+        const Tile T = a.tiles[tl];
+        const uint32_t sc = uniform(T.school);
+        const uint32_t k0 = a.key[2 * sc], k1 = a.key[2 * sc + 1];
+        const uint64_t b4 = a.start[sc] >> 2, size = a.size[sc];
+        uint32_t best = 0u;
+#pragma unroll
+        for (int q = 0; q < GPL; ++q) {
+            const uint32_t j = lane + q * kWave;
+            if (j >= T.n_groups) break;
+            const uint64_t g = T.group0 + j;
+            if (4 * g + 4 <= size) {
+                float4 X = ldv<kNT>(a.x, b4 + g), Y = ldv<kNT>(a.y, b4 + g);
+                float4 C = ldv<kNT>(a.cur, b4 + g);
+                float dx[4], dy[4];
+                group_draws(Sw, k0, k1, g, t0, dx, dy);
+#pragma unroll
+                for (int f = 0; f < 4; ++f) {
+                    const float nc = swim(lane_of(X, f), lane_of(Y, f), dx[f], dy[f], H);
+                    best = max(best, mag_bits(lane_of(C, f) - nc));
+                }
+                stv<kNT>(a.x, b4 + g, X);
+                stv<kNT>(a.y, b4 + g, Y);
+                stv<kNT>(a.prev, b4 + g, C);
+            } else {
+                for (uint64_t i = 4 * g; i < size; ++i) {
+                    const uint64_t o = 4 * b4 + i;
+                    float dx, dy;
+                    fish_draw(Sw, k0, k1, i, t0, dx, dy);
+                    float x = a.x[o], y = a.y[o];
+                    const float c = a.cur[o];
+                    const float nc = swim(x, y, dx, dy, H);
+                    best = max(best, mag_bits(c - nc));
+                    a.x[o] = x;
+                    a.y[o] = y;
+                    a.prev[o] = c;
+                }
+            }
+        }
+        best = wave_max_u32(best);
+        if (lane == 0) max_agent(a.school_max + (size_t)(t0 % 3u) * S + sc, best);
+    }
+    if (!barrier_max(bar, 0u, 0u, phase, &M_sh)) return;
+
+    for (uint32_t k = 0; k < a.steps; ++k) {
+        const uint32_t s = t0 + k;
+        const bool last = k + 1 == a.steps;
+        if (k > 0) combine_schools<kNaive>(a, s - 1u, wave, n_waves, lane);
+        for (uint32_t tl = wave; tl < a.n_tiles; tl += n_waves) {
+            const Tile T = a.tiles[tl];
+            const uint32_t sc = uniform(T.school);
+            const uint32_t k0 = a.key[2 * sc], k1 = a.key[2 * sc + 1];
+            const uint64_t b4 = a.start[sc] >> 2, size = a.size[sc];
+            const float M = __uint_as_float(ld_agent(a.school_max + (size_t)(s % 3u) * S + sc));
+            LaneSums<kNaive> ls;
+            uint32_t best = 0u;
+            float4 X[GPL], Y[GPL], W[GPL], P[GPL];
+#pragma unroll
+            for (int q = 0; q < GPL; ++q) {
+                const uint64_t g = T.group0 + lane + q * kWave;
+                if (lane + q * kWave < T.n_groups && 4 * g + 4 <= size) {
+                    X[q] = ldv<kNT>(a.x, b4 + g);
+                    Y[q] = ldv<kNT>(a.y, b4 + g);
+                    W[q] = ldv<kNT>(a.w, b4 + g);
+                    P[q] = ldv<kNT>(a.prev, b4 + g);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < GPL; ++q) {
+                const uint32_t j = lane + q * kWave;
+                if (j >= T.n_groups) break;
+                const uint64_t g = T.group0 + j;
+                if (4 * g + 4 <= size) {
+                    float4 C;
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) {
+                        lane_of(C, f) = distance(lane_of(X[q], f), lane_of(Y[q], f));
+                        const float diff = lane_of(P[q], f) - lane_of(C, f);
+                        lane_of(W[q], f) = feed(lane_of(W[q], f), diff, M, wmin, wmax);
+                        ls.add(lane_of(W[q], f), lane_of(X[q], f), lane_of(Y[q], f));
+                    }
+                    stv<kNT>(a.w, b4 + g, W[q]);
+                    if (last) {
+                        stv<kNT>(a.cur, b4 + g, C);
+                    } else {
+                        float dx[4], dy[4];
+                        group_draws(Sw, k0, k1, g, s + 1u, dx, dy);
+#pragma unroll
+                        for (int f = 0; f < 4; ++f) {
+                            const float nc =
+                                swim(lane_of(X[q], f), lane_of(Y[q], f), dx[f], dy[f], H);
+                            best = max(best, mag_bits(lane_of(C, f) - nc));
+                        }
+                        stv<kNT>(a.x, b4 + g, X[q]);
+                        stv<kNT>(a.y, b4 + g, Y[q]);
+                        stv<kNT>(a.prev, b4 + g, C);
+                    }
+                } else {
+                    for (uint64_t i = 4 * g; i < size; ++i) {
+                        const uint64_t o = 4 * b4 + i;
+                        float x = a.x[o], y = a.y[o];
+                        const float c = distance(x, y);
+                        const float nw = feed(a.w[o], a.prev[o] - c, M, wmin, wmax);
+                        a.w[o] = nw;
+                        ls.add(nw, x, y);
+                        if (last) {
+                            a.cur[o] = c;
+                        } else {
+                            float dx, dy;
+                            fish_draw(Sw, k0, k1, i, s + 1u, dx, dy);
+                            const float nc = swim(x, y, dx, dy, H);
+                            best = max(best, mag_bits(c - nc));
+                            a.x[o] = x;
+                            a.y[o] = y;
+                            a.prev[o] = c;
+                        }
+                    }
+                }
+            }
+            tile_sums<kNaive>(a, ls, s, tl, sc, lane);
+            if (!last) {
+                best = wave_max_u32(best);
+                if (lane == 0) max_agent(a.school_max + (size_t)((s + 1u) % 3u) * S + sc, best);
+            }
+        }
+        if (!barrier_max(bar, 0u, 0u, phase, &M_sh)) return;
+    }
+    combine_schools<kNaive>(a, t0 + a.steps - 1u, wave, n_waves, lane);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st_agent(a.step, t0 + a.steps);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_batch_init(const BatchArgs& a, uint32_t /*block*/, hipStream_t stream) {
+    uint64_t waves = a.n_tiles;
+    uint64_t blocks = (waves + 3) / 4;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(batch_init_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t stream) {
+    uint64_t work = 8ull * a.n_schools;
+    if (work < kSyncWords) work = kSyncWords;
+    uint64_t blocks = (work + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(batch_reset_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <int BLOCK, int GPL>
+const void* batch_fn4(uint32_t naive, uint32_t nt) {
+    if (naive)
+        return nt ? reinterpret_cast<const void*>(batch_kernel<BLOCK, GPL, true, true>)
+                  : reinterpret_cast<const void*>(batch_kernel<BLOCK, GPL, true, false>);
+    return nt ? reinterpret_cast<const void*>(batch_kernel<BLOCK, GPL, false, true>)
+              : reinterpret_cast<const void*>(batch_kernel<BLOCK, GPL, false, false>);
+}
+
+template <int BLOCK>
+const void* batch_fn2(uint32_t fpl, uint32_t naive, uint32_t nt) {
+    switch (fpl) {
+        case 4: return batch_fn4<BLOCK, 1>(naive, nt);
+        case 8: return batch_fn4<BLOCK, 2>(naive, nt);
+        case 16: return batch_fn4<BLOCK, 4>(naive, nt);
+        default: return nullptr;
+    }
+}
+
+const void* batch_fn(uint32_t block, uint32_t fpl, uint32_t naive, uint32_t nt) {
+    switch (block) {
+        case 256: return batch_fn2<256>(fpl, naive, nt);
+        case 1024: return batch_fn2<1024>(fpl, naive, nt);
+        default: return nullptr;
+    }
+}
+
+hipError_t batch_resident_grid(uint32_t block, uint32_t fish_per_lane, uint32_t naive,
+                               uint32_t* out_grid) {
+    *out_grid = 0;
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    int per_cu = 1 << 30;
+    for (uint32_t nt = 0; nt < 2; ++nt) {
+        const void* fn = batch_fn(block, fish_per_lane, naive, nt);
+        if (!fn) return hipErrorInvalidValue;
+        int b = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, (int)block, 0);
+        if (e != hipSuccess) return e;
+        per_cu = b < per_cu ? b : per_cu;
+    }
+    uint64_t g = (uint64_t)cus * (uint64_t)(per_cu > 0 ? per_cu : 0);
+    if (g > kMaxGroups * 16ull) g = kMaxGroups * 16ull;
+    *out_grid = (uint32_t)g;
+    return hipSuccess;
+}
+
+hipError_t launch_batch(const BatchArgs& a, uint32_t block, uint32_t fish_per_lane,
+                        uint32_t naive, uint32_t streaming, uint32_t grid, hipStream_t stream) {
+    const void* fn = batch_fn(block, fish_per_lane, naive, streaming);
+    if (!fn) return hipErrorInvalidValue;
+    hipError_t e = launch_batch_reset(a, stream);
+    if (e != hipSuccess) return e;
+    BatchArgs aa = a;
+    void* args[] = {&aa};
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, 0, stream);
+}
+
+}  // namespace fsb

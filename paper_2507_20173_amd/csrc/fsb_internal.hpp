@@ -18,7 +18,8 @@ constexpr size_t kAlign = 256;
 struct Ctrl {
     uint32_t last_max;        // bits of M of the last iteration whose record is pending
     uint32_t error;           // kernel-reported failure flags (kErr*)
-    uint32_t reserved0[2];
+    uint32_t step;            // batches: next iteration (advanced by each launch)
+    uint32_t reserved0;
     float naive_acc[2][4];    // float32 atomic sums of the naive mode, slot t & 1
     uint32_t pad[52];
 };
@@ -111,5 +112,84 @@ uint32_t fused_grid(uint64_t n, uint32_t resident);
 void fused_groups(uint32_t grid, uint32_t* group_size, uint32_t* groups);
 hipError_t launch_fused(const SchoolArgs& a, const FusedArgs& f, uint32_t grid,
                         hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// Batches of independent schools.
+// ---------------------------------------------------------------------------
+
+// A tile is one wavefront's share of one school for a sweep: `n_groups`
+// groups of four fish starting at group `group0` of school `school` (the
+// school's last group may hold fewer than four fish).  Tiles never straddle
+// schools and are listed school after school.
+struct Tile {
+    uint32_t school;
+    uint32_t group0;
+    uint32_t n_groups;
+    uint32_t pad;
+};
+
+struct BatchArgs {
+    float *x, *y, *w, *prev, *cur;  // packed columns
+    const uint64_t* start;          // [S] first fish of each school (multiple of 4)
+    const uint64_t* size;           // [S] fish in each school
+    const uint32_t* key;            // [2S] Philox key (seed lo, hi) of each school
+    const Tile* tiles;              // [n_tiles]
+    const uint32_t* tile_begin;     // [S+1] first tile of each school
+    uint32_t n_tiles;
+    uint32_t n_schools;
+    float H, S, wmin, wmax, wlo, whi;
+    Ctrl* ctrl;
+    uint32_t* sync;                 // barrier words
+    uint32_t* step;                 // device iteration counter (advanced by each launch)
+    uint32_t* school_max;           // [3][S] bits of M of iteration s in slot s % 3
+    double* tile_part;              // [2][3][tile_cap] per-tile binary64 sums, slot s & 1
+    uint32_t tile_cap;
+    float* school_naive;            // [2][S][4] float32 atomic sums of the naive mode
+    fsb_record* rec;                // [hist_len][S]
+    uint32_t hist_len;
+    uint32_t steps;                 // iterations per launch
+    uint32_t group_size, groups;    // barrier grouping
+};
+
+// Workspace of a batch (offsets in bytes).
+struct BatchLayout {
+    size_t ctrl, sync, start, size, key, tile_begin, tiles, tile_part, school_max, school_naive,
+        rec, total;
+    uint32_t tile_cap;
+};
+
+inline BatchLayout batch_layout(uint32_t n_schools, uint64_t tile_cap, uint32_t history_len) {
+    BatchLayout L;
+    const size_t S = n_schools;
+    L.tile_cap = (uint32_t)tile_cap;
+    L.ctrl = 0;
+    L.sync = align_up(sizeof(Ctrl), kAlign);
+    L.start = align_up(L.sync + kSyncWords * sizeof(uint32_t), kAlign);
+    L.size = align_up(L.start + S * 8, kAlign);
+    L.key = align_up(L.size + S * 8, kAlign);
+    L.tile_begin = align_up(L.key + S * 8, kAlign);
+    L.tiles = align_up(L.tile_begin + (S + 1) * 4, kAlign);
+    L.tile_part = align_up(L.tiles + tile_cap * sizeof(Tile), kAlign);
+    L.school_max = align_up(L.tile_part + 2 * 3 * tile_cap * sizeof(double), kAlign);
+    L.school_naive = align_up(L.school_max + 3 * S * 4, kAlign);
+    L.rec = align_up(L.school_naive + 2 * S * 4 * sizeof(float), kAlign);
+    L.total = align_up(L.rec + (size_t)history_len * S * sizeof(fsb_record), kAlign);
+    return L;
+}
+
+// Launch shapes of the batch kernel.
+constexpr uint32_t kBatchBlocks[2] = {256, 1024};
+constexpr uint32_t kBatchFishPerLane[3] = {4, 8, 16};
+constexpr uint32_t kBatchMinTileFish = 64 * 4;
+
+hipError_t launch_batch_init(const BatchArgs& a, uint32_t block, hipStream_t stream);
+hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t stream);
+// Persistent launch of a.steps iterations; `streaming` selects non-temporal
+// column access.  Cooperative, so the grid is guaranteed co-resident.
+hipError_t launch_batch(const BatchArgs& a, uint32_t block, uint32_t fish_per_lane,
+                        uint32_t naive, uint32_t streaming, uint32_t grid, hipStream_t stream);
+// Largest co-resident grid for a shape (0 if it cannot run).
+hipError_t batch_resident_grid(uint32_t block, uint32_t fish_per_lane, uint32_t naive,
+                               uint32_t* out_grid);
 
 }  // namespace fsb

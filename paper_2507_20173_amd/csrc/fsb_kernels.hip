@@ -24,70 +24,17 @@
 // (one float4 per column): two Philox calls, for fish pairs 2g and 2g+1.
 // The n % 4 fish past the last full group are handled one by one by the last
 // block.  A thread keeps the same fish in every sweep of a launch.
-#include "fsb_device.hpp"
-#include "fsb_internal.hpp"
+#include "fsb_sweep.hpp"
 
 namespace fsb {
 
 constexpr int kBlock = 256;
 constexpr uint32_t kPlainGridCap = 2048;  // 8 blocks of 4 waves per CU x 256 CUs
 constexpr int kUnroll = 2;                // groups in flight per thread
-constexpr uint32_t kBarrierSpinLimit = 1u << 22;
-
-__device__ __forceinline__ float4 ld4(const float* p, uint64_t g) {
-    return reinterpret_cast<const float4*>(p)[g];
-}
-__device__ __forceinline__ void st4(float* p, uint64_t g, float4 v) {
-    reinterpret_cast<float4*>(p)[g] = v;
-}
-__device__ __forceinline__ float& lane_of(float4& v, int k) {
-    return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w;
-}
 
 __device__ __forceinline__ double* partial_slot(const SchoolArgs& a, uint32_t t, int k) {
     return a.partials + ((size_t)(t & 1u) * 3 + k) * kMaxGrid;
 }
-
-// Swim displacements of the four fish of group g at iteration t.
-__device__ __forceinline__ void group_draws(const SchoolArgs& a, uint64_t g, uint32_t t,
-                                            float dx[4], float dy[4]) {
-    const float S = a.S;
-    const Words p0 = pair_words(2 * g, t, kDomainSwim, a.k0, a.k1);
-    const Words p1 = pair_words(2 * g + 1, t, kDomainSwim, a.k0, a.k1);
-    dx[0] = S * signed_unit(p0.r0); dy[0] = S * signed_unit(p0.r1);
-    dx[1] = S * signed_unit(p0.r2); dy[1] = S * signed_unit(p0.r3);
-    dx[2] = S * signed_unit(p1.r0); dy[2] = S * signed_unit(p1.r1);
-    dx[3] = S * signed_unit(p1.r2); dy[3] = S * signed_unit(p1.r3);
-}
-
-// Swim displacement of one fish i at iteration t.
-__device__ __forceinline__ void fish_draw(const SchoolArgs& a, uint64_t i, uint32_t t, float& dx,
-                                          float& dy) {
-    const Words p = pair_words(i >> 1, t, kDomainSwim, a.k0, a.k1);
-    const bool odd = i & 1;
-    dx = a.S * signed_unit(odd ? p.r2 : p.r0);
-    dy = a.S * signed_unit(odd ? p.r3 : p.r1);
-}
-
-// Per-lane sums of the barycentre: compensated (TwoSum) or plain float32.
-template <bool kNaive>
-struct LaneSums {
-    CSum c[3] = {{0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}};
-    float f[3] = {0.0f, 0.0f, 0.0f};
-    __device__ __forceinline__ void add(float w, float x, float y) {
-        const float wx = w * x;
-        const float wy = w * y;
-        if constexpr (kNaive) {
-            f[0] += w;
-            f[1] += wx;
-            f[2] += wy;
-        } else {
-            csum_add(c[0], w);
-            csum_add(c[1], wx);
-            csum_add(c[2], wy);
-        }
-    }
-};
 
 // Block-wide reduction of the lane sums: binary64 partial of this block for
 // iteration t (compensated mode) or float32 atomics into slot t & 1 (naive).
@@ -283,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
                 dx[0] = DX.x; dx[1] = DX.y; dx[2] = DX.z; dx[3] = DX.w;
                 dy[0] = DY.x; dy[1] = DY.y; dy[2] = DY.z; dy[3] = DY.w;
             } else {
-                group_draws(a, g, s.t, dx, dy);
+                group_draws(a.S, a.k0, a.k1, g, s.t, dx, dy);
             }
             float4 nx = X[u], ny = Y[u], nc;
 #pragma unroll
@@ -305,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
                 dx = s.dx[i];
                 dy = s.dy[i];
             } else {
-                fish_draw(a, i, s.t, dx, dy);
+                fish_draw(a.S, a.k0, a.k1, i, s.t, dx, dy);
             }
             float x = a.x[i], y = a.y[i];
             const float c = a.cur[i];
@@ -383,108 +330,6 @@ __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArg
 }
 
 // ---------------------------------------------------------------------------
-// Persistent kernel: two-level grid barrier that also reduces the max.
-//
-// Thread 0 of each block folds the block's max into its group's max word and
-// arrives on the group counter (agent-scope acquire-release: the block's
-// partial sums and max are published).  The last arrival of a group resets
-// the group words, folds the group max into the root max and arrives on the
-// root counter; the last root arrival publishes M (slot s & 1), resets the
-// root words and advances the phase word the other blocks wait on.  Same-
-// address atomics, which serialise, number at most one group per address.
-// Waits are bounded: on timeout, or when another block has flagged an error,
-// every block leaves the kernel and the host reports FSB_ERR_DEVICE.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint32_t arrive(uint32_t* p) {
-    return __hip_atomic_fetch_add(p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void max_agent(uint32_t* p, uint32_t v) {
-    __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Returns false if the launch must be abandoned.  `m` is this block's max;
-// on return *M_sh holds the grid max, published in slot `parity`.
-__device__ __forceinline__ bool barrier_max(const SchoolArgs& a, const FusedArgs& f, uint32_t m,
-                                           uint32_t parity, uint32_t& phase, uint32_t* M_sh) {
-    __shared__ int ok_sh;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t* sync = a.sync;
-        int ok = 1;
-        const uint32_t target = phase + 1u;
-        const uint32_t g = blockIdx.x / f.group_size;
-        const uint32_t members = min(f.group_size, gridDim.x - g * f.group_size);
-        uint32_t* grp = sync + kSyncGroups + g * kLineWords;
-        max_agent(grp + 1, m);
-        bool released = false;
-        if (arrive(grp) == members - 1u) {
-            const uint32_t gm = ld_agent(grp + 1);
-            st_agent(grp + 1, 0u);
-            st_agent(grp, 0u);
-            max_agent(sync + kSyncRootMax, gm);
-            if (arrive(sync + kSyncRootCount) == f.groups - 1u) {
-                const uint32_t M = ld_agent(sync + kSyncRootMax);
-                st_agent(sync + kSyncRootMax, 0u);
-                st_agent(sync + kSyncMaxPub + parity, M);
-                st_agent(sync + kSyncRootCount, 0u);
-                __hip_atomic_store(sync + kSyncPhase, target, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                released = true;
-            }
-        }
-        if (!released) {
-            uint32_t spins = 0;
-            while (ld_agent(sync + kSyncPhase) != target) {
-                if ((spins & 255u) == 0u && ld_agent(&a.ctrl->error)) {
-                    ok = 0;
-                    break;
-                }
-                if (++spins > kBarrierSpinLimit) {
-                    __hip_atomic_fetch_or(&a.ctrl->error, kErrBarrierTimeout, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
-        *M_sh = ld_agent(sync + kSyncMaxPub + parity);
-        phase = target;
-        ok_sh = ok;
-    }
-    __syncthreads();
-    return ok_sh != 0;
-}
-
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-template <bool kNT>
-__device__ __forceinline__ float4 ldv(const float* p, uint64_t g) {
-    if constexpr (kNT) {
-        const v4f v = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p) + g);
-        return make_float4(v.x, v.y, v.z, v.w);
-    } else {
-        return ld4(p, g);
-    }
-}
-template <bool kNT>
-__device__ __forceinline__ void stv(float* p, uint64_t g, float4 v) {
-    if constexpr (kNT) {
-        const v4f w = {v.x, v.y, v.z, v.w};
-        __builtin_nontemporal_store(w, reinterpret_cast<v4f*>(p) + g);
-    } else {
-        st4(p, g, v);
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Persistent multi-iteration kernel (1024 threads: one block per CU, so the
 // barrier has few participants).
 // ---------------------------------------------------------------------------
@@ -501,6 +346,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
     const uint64_t gbase = (uint64_t)blockIdx.x * B + threadIdx.x;
     const uint64_t tail_i = 4 * n4 + threadIdx.x;
     const bool has_tail = blockIdx.x == grid - 1 && tail_i < a.n;
+    const Barrier bar{a.sync, a.ctrl, f.group_size, f.groups};
     uint32_t phase = 0;
     if (threadIdx.x == 0) phase = ld_agent(a.sync + kSyncPhase);
 
@@ -510,7 +356,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
         for (uint64_t g = gbase; g < n4; g += stride) {
             float4 X = ldv<kNT>(a.x, g), Y = ldv<kNT>(a.y, g), C = ldv<kNT>(a.cur, g);
             float dx[4], dy[4];
-            group_draws(a, g, f.t0, dx, dy);
+            group_draws(a.S, a.k0, a.k1, g, f.t0, dx, dy);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const float nc = swim(lane_of(X, q), lane_of(Y, q), dx[q], dy[q], H);
@@ -522,7 +368,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
         }
         if (has_tail) {
             float dx, dy;
-            fish_draw(a, tail_i, f.t0, dx, dy);
+            fish_draw(a.S, a.k0, a.k1, tail_i, f.t0, dx, dy);
             float x = a.x[tail_i], y = a.y[tail_i];
             const float c = a.cur[tail_i];
             const float nc = swim(x, y, dx, dy, H);
@@ -532,7 +378,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
             a.prev[tail_i] = c;
         }
         const uint32_t m = block_max<B>(best);
-        if (!barrier_max(a, f, m, f.t0 & 1u, phase, &M_sh)) return;
+        if (!barrier_max(bar, m, f.t0 & 1u, phase, &M_sh)) return;
     }
 
     for (uint32_t k = 0; k < f.steps; ++k) {
@@ -574,7 +420,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
                     stv<kNT>(a.cur, g, C);
                 } else {
                     float dx[4], dy[4];
-                    group_draws(a, g, s + 1u, dx, dy);
+                    group_draws(a.S, a.k0, a.k1, g, s + 1u, dx, dy);
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const float nc =
@@ -597,7 +443,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
                 a.cur[tail_i] = c;
             } else {
                 float dx, dy;
-                fish_draw(a, tail_i, s + 1u, dx, dy);
+                fish_draw(a.S, a.k0, a.k1, tail_i, s + 1u, dx, dy);
                 const float nc = swim(x, y, dx, dy, H);
                 best = max(best, mag_bits(c - nc));
                 a.x[tail_i] = x;
@@ -610,7 +456,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
             if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->last_max = M_sh;
         } else {
             const uint32_t m = block_max<B>(best);
-            if (!barrier_max(a, f, m, (s + 1u) & 1u, phase, &M_sh)) return;
+            if (!barrier_max(bar, m, (s + 1u) & 1u, phase, &M_sh)) return;
         }
     }
 }

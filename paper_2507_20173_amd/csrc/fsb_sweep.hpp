@@ -1,0 +1,179 @@
+// fsb_sweep.hpp -- pieces shared by the single-school and batched kernels:
+// float4 column access, the swim draws of a group of four fish, per-lane
+// barycentre sums, and the persistent kernels' two-level grid barrier.
+#pragma once
+
+#include "fsb_device.hpp"
+#include "fsb_internal.hpp"
+
+namespace fsb {
+
+__device__ __forceinline__ float4 ld4(const float* p, uint64_t g) {
+    return reinterpret_cast<const float4*>(p)[g];
+}
+__device__ __forceinline__ void st4(float* p, uint64_t g, float4 v) {
+    reinterpret_cast<float4*>(p)[g] = v;
+}
+__device__ __forceinline__ float& lane_of(float4& v, int k) {
+    return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w;
+}
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Column access, non-temporal when the live state outgrows the cache.
+template <bool kNT>
+__device__ __forceinline__ float4 ldv(const float* p, uint64_t g) {
+    if constexpr (kNT) {
+        const v4f v = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p) + g);
+        return make_float4(v.x, v.y, v.z, v.w);
+    } else {
+        return ld4(p, g);
+    }
+}
+template <bool kNT>
+__device__ __forceinline__ void stv(float* p, uint64_t g, float4 v) {
+    if constexpr (kNT) {
+        const v4f w = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(w, reinterpret_cast<v4f*>(p) + g);
+    } else {
+        st4(p, g, v);
+    }
+}
+
+// Swim displacements of the four fish of group g (fish 4g..4g+3 of a school
+// with key (k0, k1)) at iteration t: pairs 2g and 2g+1.
+__device__ __forceinline__ void group_draws(float S, uint32_t k0, uint32_t k1, uint64_t g,
+                                            uint32_t t, float dx[4], float dy[4]) {
+    const Words p0 = pair_words(2 * g, t, kDomainSwim, k0, k1);
+    const Words p1 = pair_words(2 * g + 1, t, kDomainSwim, k0, k1);
+    dx[0] = S * signed_unit(p0.r0); dy[0] = S * signed_unit(p0.r1);
+    dx[1] = S * signed_unit(p0.r2); dy[1] = S * signed_unit(p0.r3);
+    dx[2] = S * signed_unit(p1.r0); dy[2] = S * signed_unit(p1.r1);
+    dx[3] = S * signed_unit(p1.r2); dy[3] = S * signed_unit(p1.r3);
+}
+
+// Swim displacement of fish i of a school at iteration t.
+__device__ __forceinline__ void fish_draw(float S, uint32_t k0, uint32_t k1, uint64_t i,
+                                          uint32_t t, float& dx, float& dy) {
+    const Words p = pair_words(i >> 1, t, kDomainSwim, k0, k1);
+    const bool odd = i & 1;
+    dx = S * signed_unit(odd ? p.r2 : p.r0);
+    dy = S * signed_unit(odd ? p.r3 : p.r1);
+}
+
+// Per-lane sums of the barycentre: compensated (TwoSum) or plain float32.
+template <bool kNaive>
+struct LaneSums {
+    CSum c[3] = {{0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}};
+    float f[3] = {0.0f, 0.0f, 0.0f};
+    __device__ __forceinline__ void add(float w, float x, float y) {
+        const float wx = w * x;
+        const float wy = w * y;
+        if constexpr (kNaive) {
+            f[0] += w;
+            f[1] += wx;
+            f[2] += wy;
+        } else {
+            csum_add(c[0], w);
+            csum_add(c[1], wx);
+            csum_add(c[2], wy);
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Two-level grid barrier of the persistent kernels, which also reduces a max.
+//
+// Thread 0 of each block folds the block's max into its group's max word and
+// arrives on the group counter (agent-scope acquire-release: everything the
+// block wrote before is published).  The last arrival of a group resets the
+// group words, folds the group max into the root max and arrives on the root
+// counter; the last root arrival publishes the max (slot `parity`), resets
+// the root words and advances the phase word the other blocks wait on.
+// Same-address atomics, which serialise, number at most one group per
+// address.  Waits are bounded: on timeout, or when another block has flagged
+// an error, every block leaves the kernel and the host reports
+// FSB_ERR_DEVICE.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kBarrierSpinLimit = 1u << 22;
+
+struct Barrier {
+    uint32_t* sync;       // kSyncWords words, zeroed (except the phase) before the launch
+    Ctrl* ctrl;           // error flags
+    uint32_t group_size;  // blocks per group
+    uint32_t groups;      // number of groups
+};
+
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t arrive(uint32_t* p) {
+    return __hip_atomic_fetch_add(p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void max_agent(uint32_t* p, uint32_t v) {
+    __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Returns false if the launch must be abandoned.  `m` is this block's max;
+// on return *M_sh holds the grid max.  `phase` is thread 0's phase count.
+__device__ __forceinline__ bool barrier_max(const Barrier& b, uint32_t m, uint32_t parity,
+                                           uint32_t& phase, uint32_t* M_sh) {
+    __shared__ int ok_sh;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t* sync = b.sync;
+        int ok = 1;
+        const uint32_t target = phase + 1u;
+        const uint32_t g = blockIdx.x / b.group_size;
+        const uint32_t members = min(b.group_size, gridDim.x - g * b.group_size);
+        uint32_t* grp = sync + kSyncGroups + g * kLineWords;
+        max_agent(grp + 1, m);
+        bool released = false;
+        if (arrive(grp) == members - 1u) {
+            const uint32_t gm = ld_agent(grp + 1);
+            st_agent(grp + 1, 0u);
+            st_agent(grp, 0u);
+            max_agent(sync + kSyncRootMax, gm);
+            if (arrive(sync + kSyncRootCount) == b.groups - 1u) {
+                const uint32_t M = ld_agent(sync + kSyncRootMax);
+                st_agent(sync + kSyncRootMax, 0u);
+                st_agent(sync + kSyncMaxPub + parity, M);
+                st_agent(sync + kSyncRootCount, 0u);
+                __hip_atomic_store(sync + kSyncPhase, target, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                released = true;
+            }
+        }
+        if (!released) {
+            uint32_t spins = 0;
+            while (ld_agent(sync + kSyncPhase) != target) {
+                if ((spins & 255u) == 0u && ld_agent(&b.ctrl->error)) {
+                    ok = 0;
+                    break;
+                }
+                if (++spins > kBarrierSpinLimit) {
+                    __hip_atomic_fetch_or(&b.ctrl->error, kErrBarrierTimeout, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        *M_sh = ld_agent(sync + kSyncMaxPub + parity);
+        phase = target;
+        ok_sh = ok;
+    }
+    __syncthreads();
+    return ok_sh != 0;
+}
+
+// Clears a barrier's counters and maxima before a persistent launch (the
+// phase word only ever advances).
+__global__ void reset_sync_kernel(uint32_t* sync);
+
+}  // namespace fsb

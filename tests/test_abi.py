@@ -133,3 +133,57 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError, match="no fallback"):
         _lib.lib()
+
+
+def batch_ws(c, starts, sizes):
+    import numpy as np
+    st = np.asarray(starts, np.uint64)
+    sz = np.asarray(sizes, np.uint64)
+    out = ctypes.c_size_t()
+    rc = _lib.lib().fsb_batch_workspace_bytes(ctypes.byref(c), len(sizes), st.ctypes.data,
+                                              sz.ctypes.data, ctypes.byref(out))
+    return rc, out.value
+
+
+def test_batch_workspace_bytes_pure_host():
+    rc, b = batch_ws(cfg(), [0, 1000, 3000], [1000, 2000, 5])
+    assert rc == 0 and b % 256 == 0
+    rc2, b2 = batch_ws(cfg(), [0, 1000, 3000, 4000], [1000, 2000, 5, 70000])
+    assert rc2 == 0 and b2 > b
+
+
+@pytest.mark.parametrize("starts,sizes", [
+    ([0, 10], [8, 4]),          # start not a multiple of 4
+    ([0, 4], [8, 4]),           # overlap
+    ([8, 0], [4, 4]),           # decreasing
+    ([0, 8], [4, 0]),           # empty school
+    ([], []),                   # no schools
+])
+def test_batch_bad_schools_rejected(starts, sizes):
+    rc, _ = batch_ws(cfg(), starts, sizes)
+    assert rc == _lib.FSB_ERR_INVALID_ARG
+    assert _lib.lib().fsb_last_error()
+
+
+def test_batch_init_rejects_before_any_hip_call():
+    import numpy as np
+    c = cfg()
+    st = np.asarray([0, 8], np.uint64)
+    sz = np.asarray([8, 8], np.uint64)
+    seeds = np.asarray([1, 2], np.uint64)
+    h = ctypes.c_void_p()
+    L = _lib.lib()
+    # packed columns shorter than the last school
+    rc = L.fsb_batch_init(ctypes.byref(c), 2, st.ctypes.data, sz.ctypes.data, seeds.ctypes.data,
+                          cols(), 15, FAKE + (8 << 20), 1 << 30, None, ctypes.byref(h))
+    assert rc == _lib.FSB_ERR_INVALID_ARG
+    # NULL seeds
+    rc = L.fsb_batch_init(ctypes.byref(c), 2, st.ctypes.data, sz.ctypes.data, None, cols(), 16,
+                          FAKE + (8 << 20), 1 << 30, None, ctypes.byref(h))
+    assert rc == _lib.FSB_ERR_INVALID_ARG
+    # workspace too small
+    rc = L.fsb_batch_init(ctypes.byref(c), 2, st.ctypes.data, sz.ctypes.data, seeds.ctypes.data,
+                          cols(), 16, FAKE + (8 << 20), 64, None, ctypes.byref(h))
+    assert rc == _lib.FSB_ERR_INVALID_ARG
+    assert L.fsb_batch_run(None, 1, None) == _lib.FSB_ERR_INVALID_ARG
+    assert L.fsb_batch_destroy(None) == _lib.FSB_ERR_INVALID_ARG
