@@ -196,6 +196,76 @@ def precision_form(n: int, steps: int, oracle_steps: int):
     return out
 
 
+def batched_form(n_schools: int, steps: int, probe_steps: int, baseline_schools: int):
+    """4096 independent schools of log-uniform sizes, each its own seed,
+    advanced by graph-replayed persistent launches with an autotuned shape;
+    against advancing the same schools one by one with per-iteration launches
+    (on the first `baseline_schools` schools)."""
+    import numpy as np
+    import torch
+
+    import paper_2507_20173_amd as fsb
+    from paper_2507_20173_amd.workloads import log_uniform_school_sizes, school_seeds
+
+    sizes = log_uniform_school_sizes(n_schools)
+    seeds = school_seeds(n_schools)
+    total = int(sizes.sum())
+    common = fsb.FsbConfig(n_fish=0)
+    probe = fsb.Batch(common, sizes, seeds)
+    tune = probe.autotune(probe_steps)
+    probe.close()
+    del probe
+    torch.cuda.empty_cache()
+
+    b = fsb.Batch(common, sizes, seeds)
+    b.sync()
+    fsb.fsb_batch_profile_enable(b.h, True)
+    fsb.fsb_batch_kernel_times(b.h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(steps, tune)
+    b.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launches, ms = fsb.fsb_batch_kernel_times(b.h)
+    xy, sums, mx = b.results()
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    K = min(tune.steps_per_launch, steps)
+    bytes_total = total * (24 * launches + 32 * (steps - launches) + 24 * launches)
+
+    # baseline: the first schools one by one, fsb_step per iteration
+    base_fish, base_wall = 0, 0.0
+    for i in range(baseline_schools):
+        sch = fsb.School(fsb.FsbConfig(n_fish=int(sizes[i]), seed=int(seeds[i])))
+        sch.sync()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sch.run(steps)
+        sch.sync()
+        torch.cuda.synchronize()
+        base_wall += time.perf_counter() - t1
+        base_fish += int(sizes[i])
+        sch.close()
+    value = total * steps / wall
+    base = base_fish * steps / base_wall
+    return {
+        "workload": f"batched form: {n_schools} schools, sizes log-uniform in [1e3, 1e6] "
+                    f"({total} fish), seed_s = s, {steps} iterations, graph-replayed persistent "
+                    f"launches of {K} iterations, autotuned",
+        "n_schools": n_schools, "total_fish": total, "iterations": steps,
+        "tuning": fsb.tuning_dict(tune), "autotune_probe_steps": probe_steps,
+        "value": value, "ms_per_step": wall / steps * 1e3, "launches": int(launches),
+        "algorithmic_bytes_per_fish_step": 32,
+        "kernel_achieved_GBs": bytes_total / (ms / 1e3) / 1e9,
+        "kernel_hbm_frac": bytes_total / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+        "baseline_per_school_plain": {"schools": baseline_schools, "fish": base_fish,
+                                      "value": base, "speedup_of_batched": value / base},
+        "mean_max_delta_last_iteration": float(np.mean(mx)),
+    }
+
+
 def cpu_baseline(n: int, budget_s: float = 12.0, max_steps: int = 400):
     """The oracle as it stands, on this host's cores, on a bounded prefix of
     the same workload."""
@@ -222,10 +292,16 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n-fish", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--plain-only", action="store_true", help="skip the fused/batched forms")
+    ap.add_argument("--plain-only", action="store_true", help="skip the other forms")
+    ap.add_argument("--forms", default="fused,precision,batched",
+                    help="comma list of the forms to measure beside the headline")
     ap.add_argument("--fused-steps", type=int, default=2000)
     ap.add_argument("--precision-steps", type=int, default=200)
     ap.add_argument("--precision-oracle-steps", type=int, default=3)
+    ap.add_argument("--schools", type=int, default=4096)
+    ap.add_argument("--batch-steps", type=int, default=500)
+    ap.add_argument("--autotune-steps", type=int, default=16)
+    ap.add_argument("--baseline-schools", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         log(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -266,17 +342,21 @@ def main() -> int:
         "hbm_frac_whole_step": (sum(BYTES_PER_FISH.values()) * n * args.steps / wall / 1e9)
         / HBM_PEAK_GBS,
     }
-    if not args.plain_only:
-        line["forms"] = {
-            "fused_cfg4": fused_vs_plain(1 << 26, args.fused_steps,
-                                         "persistent form: N=2^26 fish, 2000 iterations in one "
-                                         "cooperative launch vs per-iteration launches"),
-            "fused_cfg2": fused_vs_plain(n, args.steps, "persistent form on the headline school "
-                                                        "(N=2^24, 1000 iterations)"),
-        }
-    if not args.plain_only:
+    forms = set() if args.plain_only else set(args.forms.split(","))
+    line["forms"] = {}
+    if "fused" in forms:
+        line["forms"]["fused_cfg4"] = fused_vs_plain(
+            1 << 26, args.fused_steps,
+            "persistent form: N=2^26 fish, 2000 iterations in one cooperative launch vs "
+            "per-iteration launches")
+        line["forms"]["fused_cfg2"] = fused_vs_plain(
+            n, args.steps, "persistent form on the headline school (N=2^24, 1000 iterations)")
+    if "precision" in forms:
         line["forms"]["precision_cfg3"] = precision_form(1 << 27, args.precision_steps,
                                                          args.precision_oracle_steps)
+    if "batched" in forms:
+        line["forms"]["batched_cfg5"] = batched_form(args.schools, args.batch_steps,
+                                                     args.autotune_steps, args.baseline_schools)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(line), flush=True)

@@ -47,21 +47,16 @@ __global__ __launch_bounds__(256) void batch_init_kernel(BatchArgs a) {
     const uint32_t n_waves = gridDim.x * (256 / kWave);
     for (uint32_t tl = wave; tl < a.n_tiles; tl += n_waves) {
         const Tile T = a.tiles[tl];
-        const uint32_t k0 = a.key[2 * T.school], k1 = a.key[2 * T.school + 1];
-        const uint64_t base = a.start[T.school], size = a.size[T.school];
-        for (uint32_t j = lane; j < T.n_groups; j += kWave) {
-            const uint64_t g = T.group0 + j;
-            for (int q = 0; q < 4; ++q) {
-                const uint64_t i = 4 * g + q;
-                if (i >= size) break;
-                float x, y, w, c;
-                batch_init_fish(a, k0, k1, i, x, y, w, c);
-                a.x[base + i] = x;
-                a.y[base + i] = y;
-                a.w[base + i] = w;
-                a.prev[base + i] = c;
-                a.cur[base + i] = c;
-            }
+        const uint64_t base = 4 * T.col4;  // packed index of the tile's first fish
+        for (uint32_t f = lane; f < T.n_fish; f += kWave) {
+            const uint64_t i = 4ull * T.group0 + f;  // fish index within the school
+            float x, y, w, c;
+            batch_init_fish(a, T.k0, T.k1, i, x, y, w, c);
+            a.x[base + f] = x;
+            a.y[base + f] = y;
+            a.w[base + f] = w;
+            a.prev[base + f] = c;
+            a.cur[base + f] = c;
         }
     }
 }
@@ -138,7 +133,52 @@ __device__ __forceinline__ void tile_sums(const BatchArgs& a, LaneSums<kNaive>& 
 
 // ---------------------------------------------------------------------------
 // Persistent batched kernel.  GPL = groups of four fish per lane per tile.
+// Within a sweep a wavefront walks its tiles with the next tile's record and
+// its school's max fetched while the current tile streams.
 // ---------------------------------------------------------------------------
+
+// Prologue work of one tile: swim t0 from (x, y, cur), keep (x, y, prev).
+template <int GPL, bool kNT>
+__device__ __forceinline__ uint32_t tile_prologue(const BatchArgs& a, const Tile& T, uint32_t t0,
+                                                  uint32_t lane) {
+    const float H = a.H, Sw = a.S;
+    uint32_t best = 0u;
+#pragma unroll
+    for (int q = 0; q < GPL; ++q) {
+        const uint32_t j = lane + q * kWave;  // group within the tile
+        if (4 * j >= T.n_fish) break;
+        const uint64_t g = (uint64_t)T.group0 + j;
+        const uint64_t c4 = T.col4 + j;
+        if (4 * j + 4 <= T.n_fish) {
+            float4 X = ldv<kNT>(a.x, c4), Y = ldv<kNT>(a.y, c4), C = ldv<kNT>(a.cur, c4);
+            float dx[4], dy[4];
+            group_draws(Sw, T.k0, T.k1, g, t0, dx, dy);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const float nc = swim(lane_of(X, f), lane_of(Y, f), dx[f], dy[f], H);
+                best = max(best, mag_bits(lane_of(C, f) - nc));
+            }
+            stv<kNT>(a.x, c4, X);
+            stv<kNT>(a.y, c4, Y);
+            stv<kNT>(a.prev, c4, C);
+        } else {
+            for (uint32_t f = 0; 4 * j + f < T.n_fish; ++f) {
+                const uint64_t o = 4 * c4 + f;
+                float dx, dy;
+                fish_draw(Sw, T.k0, T.k1, 4 * g + f, t0, dx, dy);
+                float x = a.x[o], y = a.y[o];
+                const float c = a.cur[o];
+                const float nc = swim(x, y, dx, dy, H);
+                best = max(best, mag_bits(c - nc));
+                a.x[o] = x;
+                a.y[o] = y;
+                a.prev[o] = c;
+            }
+        }
+    }
+    return best;
+}
+
 template <int BLOCK, int GPL, bool kNaive, bool kNT>
 __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
     constexpr uint32_t WPB = BLOCK / kWave;
@@ -153,48 +193,13 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
     if (threadIdx.x == 0) phase = ld_agent(a.sync + kSyncPhase);
     const uint32_t t0 = uniform(ld_agent(a.step));
 
-    // Prologue: swim t0 from (x, y, cur), keep (x, y, prev), school maxima.
-    for (uint32_t tl = wave; tl < a.n_tiles; tl += n_waves) {
-        const Tile T = a.tiles[tl];
-        const uint32_t sc = uniform(T.school);
-        const uint32_t k0 = a.key[2 * sc], k1 = a.key[2 * sc + 1];
-        const uint64_t b4 = a.start[sc] >> 2, size = a.size[sc];
-        uint32_t best = 0u;
-#pragma unroll
-        for (int q = 0; q < GPL; ++q) {
-            const uint32_t j = lane + q * kWave;
-            if (j >= T.n_groups) break;
-            const uint64_t g = T.group0 + j;
-            if (4 * g + 4 <= size) {
-                float4 X = ldv<kNT>(a.x, b4 + g), Y = ldv<kNT>(a.y, b4 + g);
-                float4 C = ldv<kNT>(a.cur, b4 + g);
-                float dx[4], dy[4];
-                group_draws(Sw, k0, k1, g, t0, dx, dy);
-#pragma unroll
-                for (int f = 0; f < 4; ++f) {
-                    const float nc = swim(lane_of(X, f), lane_of(Y, f), dx[f], dy[f], H);
-                    best = max(best, mag_bits(lane_of(C, f) - nc));
-                }
-                stv<kNT>(a.x, b4 + g, X);
-                stv<kNT>(a.y, b4 + g, Y);
-                stv<kNT>(a.prev, b4 + g, C);
-            } else {
-                for (uint64_t i = 4 * g; i < size; ++i) {
-                    const uint64_t o = 4 * b4 + i;
-                    float dx, dy;
-                    fish_draw(Sw, k0, k1, i, t0, dx, dy);
-                    float x = a.x[o], y = a.y[o];
-                    const float c = a.cur[o];
-                    const float nc = swim(x, y, dx, dy, H);
-                    best = max(best, mag_bits(c - nc));
-                    a.x[o] = x;
-                    a.y[o] = y;
-                    a.prev[o] = c;
-                }
-            }
+    {
+        uint32_t* next_max = a.school_max + (size_t)(t0 % 3u) * S;
+        for (uint32_t tl = wave; tl < a.n_tiles; tl += n_waves) {
+            const Tile T = a.tiles[tl];
+            const uint32_t best = wave_max_u32(tile_prologue<GPL, kNT>(a, T, t0, lane));
+            if (lane == 0) max_agent(next_max + T.school, best);
         }
-        best = wave_max_u32(best);
-        if (lane == 0) max_agent(a.school_max + (size_t)(t0 % 3u) * S + sc, best);
     }
     if (!barrier_max(bar, 0u, 0u, phase, &M_sh)) return;
 
@@ -202,31 +207,41 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
         const uint32_t s = t0 + k;
         const bool last = k + 1 == a.steps;
         if (k > 0) combine_schools<kNaive>(a, s - 1u, wave, n_waves, lane);
-        for (uint32_t tl = wave; tl < a.n_tiles; tl += n_waves) {
-            const Tile T = a.tiles[tl];
-            const uint32_t sc = uniform(T.school);
-            const uint32_t k0 = a.key[2 * sc], k1 = a.key[2 * sc + 1];
-            const uint64_t b4 = a.start[sc] >> 2, size = a.size[sc];
-            const float M = __uint_as_float(ld_agent(a.school_max + (size_t)(s % 3u) * S + sc));
-            LaneSums<kNaive> ls;
-            uint32_t best = 0u;
+        const uint32_t* cur_max = a.school_max + (size_t)(s % 3u) * S;
+        uint32_t* next_max = a.school_max + (size_t)((s + 1u) % 3u) * S;
+        uint32_t tl = wave;
+        Tile T{};
+        uint32_t Mb = 0u;
+        if (tl < a.n_tiles) {
+            T = a.tiles[tl];
+            Mb = ld_agent(cur_max + T.school);
+        }
+        while (tl < a.n_tiles) {
+            const uint32_t nx = tl + n_waves;
+            Tile Tn{};
+            if (nx < a.n_tiles) Tn = a.tiles[nx];
             float4 X[GPL], Y[GPL], W[GPL], P[GPL];
 #pragma unroll
             for (int q = 0; q < GPL; ++q) {
-                const uint64_t g = T.group0 + lane + q * kWave;
-                if (lane + q * kWave < T.n_groups && 4 * g + 4 <= size) {
-                    X[q] = ldv<kNT>(a.x, b4 + g);
-                    Y[q] = ldv<kNT>(a.y, b4 + g);
-                    W[q] = ldv<kNT>(a.w, b4 + g);
-                    P[q] = ldv<kNT>(a.prev, b4 + g);
+                const uint32_t j = lane + q * kWave;
+                if (4 * j + 4 <= T.n_fish) {
+                    X[q] = ldv<kNT>(a.x, T.col4 + j);
+                    Y[q] = ldv<kNT>(a.y, T.col4 + j);
+                    W[q] = ldv<kNT>(a.w, T.col4 + j);
+                    P[q] = ldv<kNT>(a.prev, T.col4 + j);
                 }
             }
+            const uint32_t Mn = nx < a.n_tiles ? ld_agent(cur_max + Tn.school) : 0u;
+            const float M = __uint_as_float(Mb);
+            LaneSums<kNaive> ls;
+            uint32_t best = 0u;
 #pragma unroll
             for (int q = 0; q < GPL; ++q) {
                 const uint32_t j = lane + q * kWave;
-                if (j >= T.n_groups) break;
-                const uint64_t g = T.group0 + j;
-                if (4 * g + 4 <= size) {
+                if (4 * j >= T.n_fish) break;
+                const uint64_t g = (uint64_t)T.group0 + j;
+                const uint64_t c4 = T.col4 + j;
+                if (4 * j + 4 <= T.n_fish) {
                     float4 C;
 #pragma unroll
                     for (int f = 0; f < 4; ++f) {
@@ -235,25 +250,25 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
                         lane_of(W[q], f) = feed(lane_of(W[q], f), diff, M, wmin, wmax);
                         ls.add(lane_of(W[q], f), lane_of(X[q], f), lane_of(Y[q], f));
                     }
-                    stv<kNT>(a.w, b4 + g, W[q]);
+                    stv<kNT>(a.w, c4, W[q]);
                     if (last) {
-                        stv<kNT>(a.cur, b4 + g, C);
+                        stv<kNT>(a.cur, c4, C);
                     } else {
                         float dx[4], dy[4];
-                        group_draws(Sw, k0, k1, g, s + 1u, dx, dy);
+                        group_draws(Sw, T.k0, T.k1, g, s + 1u, dx, dy);
 #pragma unroll
                         for (int f = 0; f < 4; ++f) {
                             const float nc =
                                 swim(lane_of(X[q], f), lane_of(Y[q], f), dx[f], dy[f], H);
                             best = max(best, mag_bits(lane_of(C, f) - nc));
                         }
-                        stv<kNT>(a.x, b4 + g, X[q]);
-                        stv<kNT>(a.y, b4 + g, Y[q]);
-                        stv<kNT>(a.prev, b4 + g, C);
+                        stv<kNT>(a.x, c4, X[q]);
+                        stv<kNT>(a.y, c4, Y[q]);
+                        stv<kNT>(a.prev, c4, C);
                     }
                 } else {
-                    for (uint64_t i = 4 * g; i < size; ++i) {
-                        const uint64_t o = 4 * b4 + i;
+                    for (uint32_t f = 0; 4 * j + f < T.n_fish; ++f) {
+                        const uint64_t o = 4 * c4 + f;
                         float x = a.x[o], y = a.y[o];
                         const float c = distance(x, y);
                         const float nw = feed(a.w[o], a.prev[o] - c, M, wmin, wmax);
@@ -263,7 +278,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
                             a.cur[o] = c;
                         } else {
                             float dx, dy;
-                            fish_draw(Sw, k0, k1, i, s + 1u, dx, dy);
+                            fish_draw(Sw, T.k0, T.k1, 4 * g + f, s + 1u, dx, dy);
                             const float nc = swim(x, y, dx, dy, H);
                             best = max(best, mag_bits(c - nc));
                             a.x[o] = x;
@@ -273,11 +288,14 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
                     }
                 }
             }
-            tile_sums<kNaive>(a, ls, s, tl, sc, lane);
+            tile_sums<kNaive>(a, ls, s, tl, T.school, lane);
             if (!last) {
                 best = wave_max_u32(best);
-                if (lane == 0) max_agent(a.school_max + (size_t)((s + 1u) % 3u) * S + sc, best);
+                if (lane == 0) max_agent(next_max + T.school, best);
             }
+            T = Tn;
+            Mb = Mn;
+            tl = nx;
         }
         if (!barrier_max(bar, 0u, 0u, phase, &M_sh)) return;
     }

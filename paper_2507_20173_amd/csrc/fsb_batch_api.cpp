@@ -96,8 +96,16 @@ int upload_tiles(fsb_batch* b, uint32_t fpl) {
         begin[s] = (uint32_t)tiles.size();
         const uint64_t groups = (b->size[s] + 3) / 4;
         for (uint64_t g0 = 0; g0 < groups; g0 += per_tile) {
-            const uint64_t left = groups - g0;
-            tiles.push_back(Tile{s, (uint32_t)g0, (uint32_t)(left < per_tile ? left : per_tile), 0u});
+            const uint64_t fish_left = b->size[s] - 4 * g0;
+            const uint64_t cap = 4ull * per_tile;
+            Tile t{};
+            t.col4 = b->start[s] / 4 + g0;
+            t.school = s;
+            t.group0 = (uint32_t)g0;
+            t.n_fish = (uint32_t)(fish_left < cap ? fish_left : cap);
+            t.k0 = (uint32_t)b->seed[s];
+            t.k1 = (uint32_t)(b->seed[s] >> 32);
+            tiles.push_back(t);
         }
     }
     begin[b->n] = (uint32_t)tiles.size();
@@ -399,9 +407,6 @@ int fsb_batch_init(const fsb_config* common, uint32_t n_schools, const uint64_t*
     a.w = packed.w;
     a.prev = packed.prev;
     a.cur = packed.cur;
-    a.start = reinterpret_cast<const uint64_t*>(base + L.start);
-    a.size = reinterpret_cast<const uint64_t*>(base + L.size);
-    a.key = reinterpret_cast<const uint32_t*>(base + L.key);
     a.tiles = reinterpret_cast<const Tile*>(base + L.tiles);
     a.tile_begin = reinterpret_cast<const uint32_t*>(base + L.tile_begin);
     a.n_schools = n_schools;
@@ -421,25 +426,15 @@ int fsb_batch_init(const fsb_config* common, uint32_t n_schools, const uint64_t*
     a.rec = reinterpret_cast<fsb_record*>(base + L.rec);
     a.hist_len = common->history_len;
 
-    std::vector<uint32_t> keys(2 * (size_t)n_schools);
-    for (uint32_t s = 0; s < n_schools; ++s) {
-        keys[2 * s] = (uint32_t)seeds[s];
-        keys[2 * s + 1] = (uint32_t)(seeds[s] >> 32);
-    }
     auto cleanup = [&](int code) {
         delete b;
         return code;
     };
-    hipError_t e = hipStreamSynchronize(b->stream);
-    if (e == hipSuccess) e = hipMemcpy(base + L.start, starts, 8ull * n_schools, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(base + L.size, sizes, 8ull * n_schools, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(base + L.key, keys.data(), 4 * keys.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return cleanup(hip_fail(e, "school table upload"));
     rc = upload_tiles(b, b->tuning.fish_per_thread);
     if (rc) return cleanup(rc);
     SchoolArgs sa{};
     sa.ctrl = a.ctrl;
-    e = launch_reset(sa, b->stream);
+    hipError_t e = launch_reset(sa, b->stream);
     if (e == hipSuccess) e = launch_batch_init(a, 256, b->stream);
     if (e != hipSuccess) return cleanup(hip_fail(e, "batch init launch"));
     *out = b;

@@ -117,22 +117,23 @@ hipError_t launch_fused(const SchoolArgs& a, const FusedArgs& f, uint32_t grid,
 // Batches of independent schools.
 // ---------------------------------------------------------------------------
 
-// A tile is one wavefront's share of one school for a sweep: `n_groups`
-// groups of four fish starting at group `group0` of school `school` (the
-// school's last group may hold fewer than four fish).  Tiles never straddle
-// schools and are listed school after school.
+// A tile is one wavefront's share of one school for a sweep: the fish
+// [4*group0, 4*group0 + n_fish) of school `school`, whose packed float4 index
+// starts at `col4`.  It carries what the sweep needs (key, extent) so one
+// 32-byte load describes it.  Tiles never straddle schools and are listed
+// school after school.
 struct Tile {
+    uint64_t col4;     // float4 index of the tile's first group in the packed columns
     uint32_t school;
-    uint32_t group0;
-    uint32_t n_groups;
+    uint32_t group0;   // first group (4 fish) of the tile within its school
+    uint32_t n_fish;   // fish in the tile (the school's last group may be partial)
+    uint32_t k0, k1;   // the school's Philox key
     uint32_t pad;
 };
+static_assert(sizeof(Tile) == 32, "one 32-byte load per tile");
 
 struct BatchArgs {
     float *x, *y, *w, *prev, *cur;  // packed columns
-    const uint64_t* start;          // [S] first fish of each school (multiple of 4)
-    const uint64_t* size;           // [S] fish in each school
-    const uint32_t* key;            // [2S] Philox key (seed lo, hi) of each school
     const Tile* tiles;              // [n_tiles]
     const uint32_t* tile_begin;     // [S+1] first tile of each school
     uint32_t n_tiles;
@@ -153,8 +154,7 @@ struct BatchArgs {
 
 // Workspace of a batch (offsets in bytes).
 struct BatchLayout {
-    size_t ctrl, sync, start, size, key, tile_begin, tiles, tile_part, school_max, school_naive,
-        rec, total;
+    size_t ctrl, sync, tile_begin, tiles, tile_part, school_max, school_naive, rec, total;
     uint32_t tile_cap;
 };
 
@@ -164,10 +164,7 @@ inline BatchLayout batch_layout(uint32_t n_schools, uint64_t tile_cap, uint32_t 
     L.tile_cap = (uint32_t)tile_cap;
     L.ctrl = 0;
     L.sync = align_up(sizeof(Ctrl), kAlign);
-    L.start = align_up(L.sync + kSyncWords * sizeof(uint32_t), kAlign);
-    L.size = align_up(L.start + S * 8, kAlign);
-    L.key = align_up(L.size + S * 8, kAlign);
-    L.tile_begin = align_up(L.key + S * 8, kAlign);
+    L.tile_begin = align_up(L.sync + kSyncWords * sizeof(uint32_t), kAlign);
     L.tiles = align_up(L.tile_begin + (S + 1) * 4, kAlign);
     L.tile_part = align_up(L.tiles + tile_cap * sizeof(Tile), kAlign);
     L.school_max = align_up(L.tile_part + 2 * 3 * tile_cap * sizeof(double), kAlign);

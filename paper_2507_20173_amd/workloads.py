@@ -18,11 +18,14 @@ def log_uniform_school_sizes(n_schools: int, lo: int = 1_000, hi: int = 1_000_00
     return np.maximum(sizes, 1)
 
 
-def packed_starts(sizes) -> np.ndarray:
+def packed_starts(sizes, align: int = 64) -> np.ndarray:
     """Start of each school in packed columns: consecutive, each rounded up
-    to a multiple of 4 fish so every school is 16-byte aligned."""
+    to a multiple of `align` fish (64 fish = 256 bytes by default, so a
+    wavefront's float4 row never straddles an extra cache line; any multiple
+    of 4 is accepted by the library)."""
     sizes = np.asarray(sizes, np.uint64)
-    padded = (sizes + np.uint64(3)) // np.uint64(4) * np.uint64(4)
+    a = np.uint64(align)
+    padded = (sizes + a - np.uint64(1)) // a * a
     starts = np.zeros(sizes.size, np.uint64)
     if sizes.size > 1:
         starts[1:] = np.cumsum(padded)[:-1]

@@ -52,11 +52,12 @@ def check_batch_against_oracle(O, b, steps, schools=None, what=""):
         assert_columns_equal(b.school_state(i), school, f"{what} school {i}")
 
 
-def test_batch_matches_oracle_per_school(torch_cuda, O):
-    announce(f"{len(SIZES)} schools, 6 iterations")
+@pytest.mark.parametrize("align", [4, 64])
+def test_batch_matches_oracle_per_school(torch_cuda, O, align):
+    announce(f"{len(SIZES)} schools, 6 iterations, starts aligned to {align} fish")
     common = fsb.FsbConfig(n_fish=0, history_len=6)
     seeds = [17 * i + 3 for i in range(len(SIZES))]
-    b = fsb.Batch(common, SIZES, seeds)
+    b = fsb.Batch(common, SIZES, seeds, starts=packed_starts(SIZES, align))
     b.run(6)
     check_batch_against_oracle(O, b, 6, what="default tuning")
     for step in range(6):
