@@ -245,9 +245,10 @@ def fsb_batch_kernel_times(b) -> tuple[int, float]:
 
 # ---- convenience owners ---------------------------------------------------------
 
-def alloc_columns(n: int, device="cuda"):
+def alloc_columns(n: int, device="cuda", zero: bool = False):
     import torch
-    return {k: torch.empty(n, dtype=torch.float32, device=device) for k in COLUMNS}
+    make = torch.zeros if zero else torch.empty
+    return {k: make(n, dtype=torch.float32, device=device) for k in COLUMNS}
 
 
 class School:
@@ -329,7 +330,7 @@ class Batch:
         self.common = common
         length = int(self.starts[-1] + self.sizes[-1])
         length = (length + 3) // 4 * 4
-        self.cols = alloc_columns(length, device)
+        self.cols = alloc_columns(length, device, zero=True)  # padding between schools is 0
         self.workspace = torch.empty(fsb_batch_workspace_bytes(common, self.starts, self.sizes),
                                      dtype=torch.uint8, device=device)
         self.h = fsb_batch_init(common, self.starts, self.sizes, self.seeds, self.cols,

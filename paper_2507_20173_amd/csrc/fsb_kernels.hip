@@ -199,8 +199,15 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(SchoolArgs a, uint32_t 
 // ---------------------------------------------------------------------------
 // Plain swim pass.
 // ---------------------------------------------------------------------------
-template <bool kInject>
+// Cache policy of the plain passes (chosen on the host from the footprint):
+// kCached keeps every column in the last-level cache, kStreamW streams only
+// w (touched by the feed pass alone) so x, y, prev, cur stay resident, and
+// kStreamAll streams every column once even four of them cannot fit.
+constexpr int kCached = 0, kStreamW = 1, kStreamAll = 2;
+
+template <bool kInject, int kPolicy>
 __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArgs s) {
+    constexpr bool NT = kPolicy == kStreamAll;
     if (s.combine && blockIdx.x == 0)
         combine_block(a, s.prev_t, s.prev_grid, s.naive, a.ctrl->last_max);
 
@@ -215,9 +222,9 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
         for (int u = 0; u < kUnroll; ++u) {
             const uint64_t g = g0 + u * stride;
             if (g < n4) {
-                X[u] = ld4(a.x, g);
-                Y[u] = ld4(a.y, g);
-                C[u] = ld4(a.cur, g);
+                X[u] = ldv<NT>(a.x, g);
+                Y[u] = ldv<NT>(a.y, g);
+                C[u] = ldv<NT>(a.cur, g);
             }
         }
 #pragma unroll
@@ -238,10 +245,10 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
                 lane_of(nc, k) = swim(lane_of(nx, k), lane_of(ny, k), dx[k], dy[k], H);
                 best = max(best, mag_bits(lane_of(C[u], k) - lane_of(nc, k)));
             }
-            st4(a.x, g, nx);
-            st4(a.y, g, ny);
-            st4(a.prev, g, C[u]);
-            st4(a.cur, g, nc);
+            stv<NT>(a.x, g, nx);
+            stv<NT>(a.y, g, ny);
+            stv<NT>(a.prev, g, C[u]);
+            stv<NT>(a.cur, g, nc);
         }
     }
     if (blockIdx.x == gridDim.x - 1) {
@@ -271,8 +278,10 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
 // ---------------------------------------------------------------------------
 // Plain feed pass.
 // ---------------------------------------------------------------------------
-template <bool kNaive>
+template <bool kNaive, int kPolicy>
 __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArgs s) {
+    constexpr bool NT = kPolicy == kStreamAll;
+    constexpr bool NTW = kPolicy != kCached;
     __shared__ uint32_t M_bits;
     // M = max over the swim pass's block maxima.
     uint32_t mb = 0u;
@@ -296,11 +305,11 @@ __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArg
         for (int u = 0; u < kUnroll; ++u) {
             const uint64_t g = g0 + u * stride;
             if (g < n4) {
-                P[u] = ld4(a.prev, g);
-                C[u] = ld4(a.cur, g);
-                W[u] = ld4(a.w, g);
-                X[u] = ld4(a.x, g);
-                Y[u] = ld4(a.y, g);
+                P[u] = ldv<NT>(a.prev, g);
+                C[u] = ldv<NT>(a.cur, g);
+                W[u] = ldv<NTW>(a.w, g);
+                X[u] = ldv<NT>(a.x, g);
+                Y[u] = ldv<NT>(a.y, g);
             }
         }
 #pragma unroll
@@ -314,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArg
                 lane_of(nw, k) = feed(lane_of(W[u], k), diff, M, wmin, wmax);
                 ls.add(lane_of(nw, k), lane_of(X[u], k), lane_of(Y[u], k));
             }
-            st4(a.w, g, nw);
+            stv<NTW>(a.w, g, nw);
         }
     }
     if (blockIdx.x == gridDim.x - 1) {
@@ -490,21 +499,50 @@ hipError_t launch_init(const SchoolArgs& a, float wlo, float whi, hipStream_t st
     return hipGetLastError();
 }
 
+// Footprint rule of the plain passes' cache policy (256 MiB last-level cache).
+constexpr uint64_t kLastLevelCache = 256ull << 20;
+
+int plain_policy(uint64_t n) {
+    if (n * 20ull <= kLastLevelCache) return kCached;
+    if (n * 16ull <= kLastLevelCache) return kStreamW;
+    return kStreamAll;
+}
+
+template <bool kInject>
+const void* swim_fn(int pol) {
+    switch (pol) {
+        case kCached: return reinterpret_cast<const void*>(swim_eval_kernel<kInject, kCached>);
+        case kStreamW: return reinterpret_cast<const void*>(swim_eval_kernel<kInject, kStreamW>);
+        default: return reinterpret_cast<const void*>(swim_eval_kernel<kInject, kStreamAll>);
+    }
+}
+
+template <bool kNaive>
+const void* feed_fn(int pol) {
+    switch (pol) {
+        case kCached: return reinterpret_cast<const void*>(feed_bary_kernel<kNaive, kCached>);
+        case kStreamW: return reinterpret_cast<const void*>(feed_bary_kernel<kNaive, kStreamW>);
+        default: return reinterpret_cast<const void*>(feed_bary_kernel<kNaive, kStreamAll>);
+    }
+}
+
+hipError_t launch_plain(const void* fn, uint32_t grid, const SchoolArgs& a, const StepArgs& s,
+                        hipStream_t stream) {
+    SchoolArgs aa = a;
+    StepArgs ss = s;
+    void* args[] = {&aa, &ss};
+    return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, stream);
+}
+
 hipError_t launch_swim_eval(const SchoolArgs& a, const StepArgs& s, hipStream_t stream) {
-    if (s.dx)
-        hipLaunchKernelGGL(swim_eval_kernel<true>, dim3(s.swim_grid), dim3(kBlock), 0, stream, a, s);
-    else
-        hipLaunchKernelGGL(swim_eval_kernel<false>, dim3(s.swim_grid), dim3(kBlock), 0, stream, a, s);
-    return hipGetLastError();
+    const int pol = plain_policy(a.n);
+    return launch_plain(s.dx ? swim_fn<true>(pol) : swim_fn<false>(pol), s.swim_grid, a, s, stream);
 }
 
 hipError_t launch_feed_bary(const SchoolArgs& a, const StepArgs& s, uint32_t grid,
                             hipStream_t stream) {
-    if (s.naive)
-        hipLaunchKernelGGL(feed_bary_kernel<true>, dim3(grid), dim3(kBlock), 0, stream, a, s);
-    else
-        hipLaunchKernelGGL(feed_bary_kernel<false>, dim3(grid), dim3(kBlock), 0, stream, a, s);
-    return hipGetLastError();
+    const int pol = plain_policy(a.n);
+    return launch_plain(s.naive ? feed_fn<true>(pol) : feed_fn<false>(pol), grid, a, s, stream);
 }
 
 hipError_t launch_combine(const SchoolArgs& a, uint32_t t, uint32_t grid, uint32_t naive,

@@ -74,15 +74,17 @@ def test_every_launch_shape_gives_identical_state(torch_cuda, block, fpl):
     seeds = list(range(len(SIZES)))
     ref = fsb.Batch(common, SIZES, seeds)
     ref.run(5, fsb.tuning(1024, 8, 5))
-    ref_cols = {k: v.cpu().numpy() for k, v in ref.cols.items()}
+    ref_state = [ref.school_state(i) for i in range(ref.n)]
     _, ref_sums, ref_max = ref.results()
     for k_launch in (1, 2, 5):
         b = fsb.Batch(common, SIZES, seeds)
         b.run(5, fsb.tuning(block, fpl, k_launch))
-        b.sync()
-        for k, v in b.cols.items():
-            assert np.array_equal(v.cpu().numpy().view(np.uint32), ref_cols[k].view(np.uint32)), (
-                f"{k} differs for block={block} fpl={fpl} steps/launch={k_launch}")
+        for i in range(b.n):
+            got = b.school_state(i)
+            for k in got:
+                assert np.array_equal(got[k].view(np.uint32), ref_state[i][k].view(np.uint32)), (
+                    f"school {i} column {k} differs for block={block} fpl={fpl} "
+                    f"steps/launch={k_launch}")
         _, sums, mx = b.results()
         assert np.array_equal(mx, ref_max)
         assert np.allclose(sums, ref_sums, rtol=1e-12, atol=1e-9)

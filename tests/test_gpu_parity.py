@@ -52,7 +52,8 @@ def test_init_matches_oracle(torch_cuda, O, n):
 
 
 @pytest.mark.parametrize("n,steps", [(1, 6), (3, 6), (5, 6), (65, 6), (1000, 6), (4097, 5),
-                                     (65539, 4), ((1 << 21) + 1, 3), ((1 << 23) + 6, 2)])
+                                     (65539, 4), ((1 << 21) + 1, 3), ((1 << 23) + 6, 2),
+                                     ((1 << 24) + 5, 2)])
 def test_steps_match_oracle(torch_cuda, O, n, steps):
     announce(f"steps n={n} steps={steps}")
     cfg = fsb.FsbConfig(n_fish=n, seed=1234567 + n, history_len=steps)
