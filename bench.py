@@ -27,6 +27,9 @@ BYTES_PER_FISH = {
     "swim_eval": 12 + 16,  # reads x, y, cur; writes x, y, prev, cur
     "feed_bary": 20 + 4,   # reads prev, cur, w, x, y; writes w
 }
+# Every PROFILE_EVERY-th launch of each kernel is bracketed by HIP events
+# inside the timed region (sampling keeps the event packets off the others).
+PROFILE_EVERY = 8
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2507_20173_amd", "csrc", "fsb_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plain_n16777216.json")
 
@@ -66,7 +69,7 @@ def plain_run(n: int, steps: int, warmup: int):
     sch = fsb.School(cfg)
     sch.run(warmup)
     sch.sync()
-    fsb.fsb_profile_enable(sch.h, True)
+    fsb.fsb_profile_enable(sch.h, PROFILE_EVERY)
     fsb.fsb_kernel_times(sch.h)  # reset counters
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -100,7 +103,7 @@ def run_form(n: int, steps: int, mode: int, warmup: int = 2):
     sch = fsb.School(cfg)
     sch.run(warmup, mode)
     sch.sync()
-    fsb.fsb_profile_enable(sch.h, True)
+    fsb.fsb_profile_enable(sch.h, 1 if mode == fsb.FSB_RUN_FUSED else PROFILE_EVERY)
     fsb.fsb_kernel_times(sch.h)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -219,7 +222,7 @@ def batched_form(n_schools: int, steps: int, probe_steps: int, baseline_schools:
 
     b = fsb.Batch(common, sizes, seeds)
     b.sync()
-    fsb.fsb_batch_profile_enable(b.h, True)
+    fsb.fsb_batch_profile_enable(b.h, 1)
     fsb.fsb_batch_kernel_times(b.h)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -285,6 +288,69 @@ def cpu_baseline(n: int, budget_s: float = 12.0, max_steps: int = 400):
                       f"oracle with binary64 reference sums, {el:.1f} s"}
 
 
+COPY_FLOATS = 1 << 26  # calibration copy: 256 MiB read + 256 MiB written
+COPY_REPS = 4
+
+
+def calibrate_copy(reps: int = COPY_REPS) -> None:
+    """Device-to-device copies of a known size (torch's copy_, a plain copy
+    kernel), to scale the HBM counters of the same run."""
+    import torch
+    a = torch.ones(COPY_FLOATS, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+
+
+def _counter_rows(directory: str, counter: str):
+    """(kernel name, value) per dispatch from rocprofv3 counter CSVs."""
+    import csv
+    import glob
+    rows = []
+    for path in glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") == counter:
+                    rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def ingest_counters(fetch_dir: str, write_dir: str, n_fish: int) -> dict:
+    """Per-launch HBM bytes of the plain kernels from a FETCH_SIZE run and a
+    WRITE_SIZE run (KiB per dispatch), each scaled by what the same counter
+    reads for the calibration copy of known size."""
+    import statistics
+    out = {"n_fish": n_fish, "source_digest": source_digest(), "kernels": {}}
+    scale = {}
+    per = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _counter_rows(d, counter)
+        # the calibration copies (a copy may be split over several dispatches;
+        # the library's own small read-backs are left out by size)
+        copy = [v for k, v in rows if "copyBuffer" in k and v > 1024.0]
+        if not copy:
+            raise SystemExit(f"no calibration copy dispatches with {counter} in {d}")
+        known_kib = COPY_REPS * COPY_FLOATS * 4 / 1024
+        scale[counter] = known_kib / sum(copy)
+        for name in ("swim_eval_kernel", "feed_bary_kernel"):
+            vals = [v for k, v in rows if name in k]
+            if vals:
+                per.setdefault(name, {})[counter] = statistics.mean(vals)
+    out["copy_scale"] = scale
+    for name, key in (("swim_eval_kernel", "swim_eval"), ("feed_bary_kernel", "feed_bary")):
+        c = per.get(name, {})
+        if "FETCH_SIZE" in c and "WRITE_SIZE" in c:
+            rd = c["FETCH_SIZE"] * scale["FETCH_SIZE"] * 1024
+            wr = c["WRITE_SIZE"] * scale["WRITE_SIZE"] * 1024
+            out["kernels"][key] = {"fetch_bytes_per_launch": rd, "write_bytes_per_launch": wr,
+                                   "bytes_per_launch": rd + wr,
+                                   "algorithmic_bytes_per_launch": BYTES_PER_FISH[key] * n_fish}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -302,7 +368,15 @@ def main() -> int:
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--autotune-steps", type=int, default=16)
     ap.add_argument("--baseline-schools", type=int, default=64)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run known-size device copies first (for counter scaling)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the plain kernels' measured HBM traffic from two rocprofv3 "
+                         "--pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
     args = ap.parse_args()
+    if args.ingest_counters:
+        print(json.dumps(ingest_counters(*args.ingest_counters, args.n_fish), indent=1))
+        return 0
     if args.gpus != 1:
         log(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
             "the school would shard across GPUs with one small all-gather per iteration, "
@@ -314,6 +388,8 @@ def main() -> int:
         log("bench.py needs a GPU")
         return 1
     n = args.n_fish
+    if args.calibrate_copy:
+        calibrate_copy()
     wall, kernels, xy = plain_run(n, args.steps, args.warmup)
     value = n * args.steps / wall
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"])

@@ -265,21 +265,23 @@ int fsb_batch_destroy(fsb_batch *b);
 
 /* ---- instrumentation --------------------------------------------------- */
 
-/* Kernel timing: when enabled, every kernel the handle launches is
- * bracketed by HIP events on its stream.  fsb_kernel_times synchronises and
- * returns, per kernel kind (FSB_KERNEL_*), the number of launches and their
- * summed duration in milliseconds since the previous read (reading resets
- * the counts). */
+/* Kernel timing: with every = n > 0, every n-th launch of each kernel kind
+ * (the 1st, the (n+1)-th, ...) is bracketed by HIP events on the handle's
+ * stream (n = 1 times every launch; sampling keeps the event packets' own
+ * cost out of the other launches); every = 0 turns timing off.
+ * fsb_kernel_times synchronises and returns, per kernel kind
+ * (FSB_KERNEL_*), the number of timed launches and their summed duration in
+ * milliseconds since the previous read (reading resets the counts). */
 #define FSB_KERNEL_SWIM_EVAL 0 /* plain pass 1: swim, objective, max |diff| */
 #define FSB_KERNEL_FEED_BARY 1 /* plain pass 2: feeding, barycentre sums */
 #define FSB_KERNEL_FUSED 2     /* persistent multi-iteration kernel */
 #define FSB_KERNEL_INIT 3
 #define FSB_KERNEL_KINDS 4
-int fsb_profile_enable(fsb_school *h, int enable);
+int fsb_profile_enable(fsb_school *h, int every);
 int fsb_kernel_times(fsb_school *h, uint64_t counts[FSB_KERNEL_KINDS],
                      double ms[FSB_KERNEL_KINDS]);
 /* The same for a batch: launches of the persistent batched kernel. */
-int fsb_batch_profile_enable(fsb_batch *b, int enable);
+int fsb_batch_profile_enable(fsb_batch *b, int every);
 int fsb_batch_kernel_times(fsb_batch *b, uint64_t *count, double *ms);
 
 #ifdef __cplusplus

@@ -141,8 +141,9 @@ def fsb_destroy(h) -> None:
     check(lib().fsb_destroy(h))
 
 
-def fsb_profile_enable(h, enable: bool = True) -> None:
-    check(lib().fsb_profile_enable(h, 1 if enable else 0))
+def fsb_profile_enable(h, every: int = 1) -> None:
+    """Time every `every`-th launch of each kernel kind (0 = off)."""
+    check(lib().fsb_profile_enable(h, int(every)))
 
 
 def fsb_kernel_times(h) -> tuple[np.ndarray, np.ndarray]:
@@ -232,8 +233,9 @@ def fsb_batch_destroy(b) -> None:
     check(lib().fsb_batch_destroy(b))
 
 
-def fsb_batch_profile_enable(b, enable: bool = True) -> None:
-    check(lib().fsb_batch_profile_enable(b, 1 if enable else 0))
+def fsb_batch_profile_enable(b, every: int = 1) -> None:
+    """Time every `every`-th launch (0 = off)."""
+    check(lib().fsb_batch_profile_enable(b, int(every)))
 
 
 def fsb_batch_kernel_times(b) -> tuple[int, float]:

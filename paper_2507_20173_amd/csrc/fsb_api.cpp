@@ -30,7 +30,8 @@ struct fsb_school {
     bool pending;          // last feed pass's partials not yet combined
     uint32_t pending_t;
     uint32_t pending_grid;
-    bool profile;
+    uint32_t profile_every;  // time every n-th launch of each kind (0 = off)
+    uint64_t launches[FSB_KERNEL_KINDS];
     uint32_t resident[2];  // co-resident grid of the persistent kernel (per reduce mode; 0 = unknown)
     Timer timers[FSB_KERNEL_KINDS];
 };
@@ -41,7 +42,7 @@ namespace {
 template <class F>
 int timed(fsb_school* h, int kind, const char* what, F&& fn) {
     std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
-    if (h->profile) {
+    if (h->profile_every && h->launches[kind]++ % h->profile_every == 0) {
         FSB_HIP_TRY(h->timers[kind].next(&ev), "hipEventCreate");
         FSB_HIP_TRY(hipEventRecord(ev->first, h->stream), "hipEventRecord");
     }
@@ -98,7 +99,7 @@ int new_school(const fsb_config* cfg, fsb_state state, void* ws, size_t ws_bytes
     h->first_valid = t;
     h->has_result = false;
     h->pending = false;
-    h->profile = false;
+    h->profile_every = 0;
     hipError_t e = launch_reset(h->args, h->stream);
     if (e != hipSuccess) {
         delete h;
@@ -178,7 +179,7 @@ int run_fused(fsb_school* h, uint64_t n_steps) {
     // last-level cache (below that, keeping lines cached is faster).
     f.streaming = h->cfg.n_fish * 16ull > (256ull << 20);
     std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
-    if (h->profile) {
+    if (h->profile_every && h->launches[FSB_KERNEL_FUSED]++ % h->profile_every == 0) {
         FSB_HIP_TRY(h->timers[FSB_KERNEL_FUSED].next(&ev), "hipEventCreate");
         FSB_HIP_TRY(hipEventRecord(ev->first, h->stream), "hipEventRecord");
     }
@@ -361,9 +362,11 @@ int fsb_destroy(fsb_school* h) {
     return FSB_OK;
 }
 
-int fsb_profile_enable(fsb_school* h, int enable) {
+int fsb_profile_enable(fsb_school* h, int every) {
     if (!h) return fail(FSB_ERR_INVALID_ARG, "handle is NULL");
-    h->profile = enable != 0;
+    if (every < 0) return fail(FSB_ERR_INVALID_ARG, "every must be >= 0");
+    h->profile_every = (uint32_t)every;
+    for (int k = 0; k < FSB_KERNEL_KINDS; ++k) h->launches[k] = 0;
     return FSB_OK;
 }
 

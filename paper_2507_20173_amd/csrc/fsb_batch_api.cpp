@@ -36,7 +36,8 @@ struct fsb_batch {
     uint32_t n_tiles;
     hipGraphExec_t graph;
     uint32_t graph_steps, graph_grid, graph_block, graph_fpl;
-    bool profile;
+    uint32_t profile_every;  // time every n-th launch (0 = off)
+    uint64_t launches;
     Timer timer;
     ~fsb_batch() {
         if (graph) (void)hipGraphExecDestroy(graph);
@@ -206,7 +207,7 @@ int ensure_graph(fsb_batch* b, uint32_t steps, uint32_t grid) {
 template <class F>
 int timed(fsb_batch* b, const char* what, F&& fn) {
     std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
-    if (b->profile) {
+    if (b->profile_every && b->launches++ % b->profile_every == 0) {
         FSB_HIP_TRY(b->timer.next(&ev), "hipEventCreate");
         FSB_HIP_TRY(hipEventRecord(ev->first, b->stream), "hipEventRecord");
     }
@@ -554,9 +555,11 @@ int fsb_batch_destroy(fsb_batch* b) {
     return FSB_OK;
 }
 
-int fsb_batch_profile_enable(fsb_batch* b, int enable) {
+int fsb_batch_profile_enable(fsb_batch* b, int every) {
     if (!b) return fail(FSB_ERR_INVALID_ARG, "handle is NULL");
-    b->profile = enable != 0;
+    if (every < 0) return fail(FSB_ERR_INVALID_ARG, "every must be >= 0");
+    b->profile_every = (uint32_t)every;
+    b->launches = 0;
     return FSB_OK;
 }
 
