@@ -382,7 +382,7 @@ hipError_t launch_batch(const BatchArgs& a, uint32_t block, uint32_t fish_per_la
     if (e != hipSuccess) return e;
     BatchArgs aa = a;
     void* args[] = {&aa};
-    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, 0, stream);
+    return launch_persistent(fn, dim3(grid), dim3(block), args, stream);
 }
 
 }  // namespace fsb

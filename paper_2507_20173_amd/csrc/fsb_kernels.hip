@@ -24,6 +24,9 @@
 // (one float4 per column): two Philox calls, for fish pairs 2g and 2g+1.
 // The n % 4 fish past the last full group are handled one by one by the last
 // block.  A thread keeps the same fish in every sweep of a launch.
+#include <cstdlib>
+#include <cstring>
+
 #include "fsb_sweep.hpp"
 
 namespace fsb {
@@ -596,6 +599,16 @@ void fused_groups(uint32_t grid, uint32_t* group_size, uint32_t* groups) {
     *groups = (grid + gs - 1) / gs;
 }
 
+hipError_t launch_persistent(const void* fn, dim3 grid, dim3 block, void** args,
+                             hipStream_t stream) {
+    static const bool regular = [] {
+        const char* v = std::getenv("FSB_PERSISTENT_LAUNCH");
+        return v && std::strcmp(v, "regular") == 0;
+    }();
+    if (regular) return hipLaunchKernel(fn, grid, block, args, 0, stream);
+    return hipLaunchCooperativeKernel(fn, grid, block, args, 0, stream);
+}
+
 hipError_t launch_fused(const SchoolArgs& a, const FusedArgs& f, uint32_t grid,
                         hipStream_t stream) {
     hipLaunchKernelGGL(reset_sync_kernel, dim3(1), dim3(256), 0, stream, a.sync);
@@ -604,8 +617,8 @@ hipError_t launch_fused(const SchoolArgs& a, const FusedArgs& f, uint32_t grid,
     SchoolArgs sa = a;
     FusedArgs fa = f;
     void* args[] = {&sa, &fa};
-    return hipLaunchCooperativeKernel(pick_fused(f.naive, f.streaming), dim3(grid),
-                                      dim3(kFusedBlock), args, 0, stream);
+    return launch_persistent(pick_fused(f.naive, f.streaming), dim3(grid), dim3(kFusedBlock),
+                             args, stream);
 }
 
 }  // namespace fsb

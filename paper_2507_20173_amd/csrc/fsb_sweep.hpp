@@ -176,4 +176,14 @@ __device__ __forceinline__ bool barrier_max(const Barrier& b, uint32_t m, uint32
 // phase word only ever advances).
 __global__ void reset_sync_kernel(uint32_t* sync);
 
+// Launch of a persistent kernel.  Cooperative by default (the runtime then
+// guarantees the grid is co-resident or refuses the launch).  With the
+// environment variable FSB_PERSISTENT_LAUNCH=regular (read once) the same
+// grid, never larger than the occupancy maximum, is launched ordinarily --
+// for profilers that cannot follow cooperative launches; on an otherwise
+// idle GPU every block is then resident, and if one were not, the bounded
+// barrier would report FSB_ERR_DEVICE rather than hang.
+hipError_t launch_persistent(const void* fn, dim3 grid, dim3 block, void** args,
+                             hipStream_t stream);
+
 }  // namespace fsb

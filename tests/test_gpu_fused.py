@@ -124,3 +124,41 @@ def test_cfg4_full_size_prefix(torch_cuda, O):
     assert_sums_close(history_sums(h), s, a, what="cfg4 prefix")
     assert_columns_equal(sch.state(), school, "cfg4 prefix")
     sch.close()
+
+
+CHILD = r"""
+import sys, numpy as np
+sys.path.insert(0, sys.argv[1])
+import paper_2507_20173_amd as fsb
+s = fsb.School(fsb.FsbConfig(n_fish=50_003, seed=31, history_len=4))
+s.run(4, fsb.FSB_RUN_FUSED)
+st = s.state()
+b = fsb.Batch(fsb.FsbConfig(n_fish=0), [5, 1000, 4099], [1, 2, 3])
+b.run(3)
+bs = [b.school_state(i) for i in range(3)]
+np.savez(sys.argv[2], *[st[k] for k in fsb.COLUMNS], *[x[k] for x in bs for k in fsb.COLUMNS])
+"""
+
+
+def test_regular_launch_matches_cooperative(torch_cuda, tmp_path):
+    """FSB_PERSISTENT_LAUNCH=regular (for tools that cannot follow cooperative
+    launches) runs the same kernels with an ordinary launch: identical bits."""
+    import os
+    import subprocess
+    import sys
+    announce("regular launch in a child process")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = tmp_path / "regular.npz"
+    env = dict(os.environ, FSB_PERSISTENT_LAUNCH="regular")
+    subprocess.run([sys.executable, "-c", CHILD, root, str(out)], env=env, check=True,
+                   timeout=240)
+    got = np.load(out)
+    s = fsb.School(fsb.FsbConfig(n_fish=50_003, seed=31, history_len=4))
+    s.run(4, FUSED)
+    st = s.state()
+    b = fsb.Batch(fsb.FsbConfig(n_fish=0), [5, 1000, 4099], [1, 2, 3])
+    b.run(3)
+    want = [st[k] for k in fsb.COLUMNS] + [b.school_state(i)[k] for i in range(3)
+                                           for k in fsb.COLUMNS]
+    for i, w in enumerate(want):
+        assert np.array_equal(got[f"arr_{i}"].view(np.uint32), w.view(np.uint32)), i
