@@ -118,27 +118,37 @@ def run_form(n: int, steps: int, mode: int, warmup: int = 2):
     return wall, counts, ms
 
 
+def persistent_bytes(variant: str, n: int, steps: int) -> int:
+    """Algorithmic bytes of one persistent launch of `steps` iterations."""
+    if variant == "lean":  # prologue reads x, y; sweeps 24 B; the last also writes prev, cur
+        return n * (8 + 24 * steps + 8)
+    return n * (24 + 32 * (steps - 1) + 24)  # prologue 24 B, sweeps 32 B, last sweep 24 B
+
+
 def fused_vs_plain(n: int, steps: int, label: str):
-    """The persistent form against per-iteration launches on the same school."""
+    """The persistent form (both variants, and the one FSB_RUN_FUSED picks)
+    against per-iteration launches on the same school."""
     import paper_2507_20173_amd as fsb
 
-    wf, cf, mf = run_form(n, steps, fsb.FSB_RUN_FUSED)
+    out = {"workload": label, "n_fish": n, "iterations": steps}
+    for key, mode in (("fused", fsb.FSB_RUN_FUSED), ("fused_prev", fsb.FSB_RUN_FUSED_PREV),
+                      ("fused_lean", fsb.FSB_RUN_FUSED_LEAN)):
+        wall, counts, ms = run_form(n, steps, mode)
+        variant = {"fused_prev": "prev", "fused_lean": "lean"}.get(
+            key, "lean" if n * 16 > (256 << 20) else "prev")
+        kernel_s = ms[fsb.FSB_KERNEL_FUSED] / 1e3
+        nbytes = persistent_bytes(variant, n, steps)
+        out[key] = {"variant": variant, "value": n * steps / wall, "ms_per_step": wall / steps * 1e3,
+                    "launches": int(counts[fsb.FSB_KERNEL_FUSED]),
+                    "algorithmic_bytes_per_fish_step": 24 if variant == "lean" else 32,
+                    "kernel_achieved_GBs": nbytes / kernel_s / 1e9,
+                    "kernel_hbm_frac": nbytes / kernel_s / 1e9 / HBM_PEAK_GBS}
     wp, cp, mp = run_form(n, steps, fsb.FSB_RUN_PLAIN)
-    fused_kernel_s = mf[fsb.FSB_KERNEL_FUSED] / 1e3
-    # one launch: prologue 24 B + (steps - 1) sweeps of 32 B + last sweep 24 B
-    fused_bytes = n * (24 + 32 * (steps - 1) + 24)
-    return {
-        "workload": label, "n_fish": n, "iterations": steps,
-        "fused": {"value": n * steps / wf, "ms_per_step": wf / steps * 1e3,
-                  "launches": int(cf[fsb.FSB_KERNEL_FUSED]),
-                  "algorithmic_bytes_per_fish_step": 32,
-                  "kernel_achieved_GBs": fused_bytes / fused_kernel_s / 1e9,
-                  "kernel_hbm_frac": fused_bytes / fused_kernel_s / 1e9 / HBM_PEAK_GBS},
-        "plain": {"value": n * steps / wp, "ms_per_step": wp / steps * 1e3,
-                  "algorithmic_bytes_per_fish_step": 52,
-                  "hbm_frac": 52 * n * steps / wp / 1e9 / HBM_PEAK_GBS},
-        "fused_speedup": wp / wf,
-    }
+    out["plain"] = {"value": n * steps / wp, "ms_per_step": wp / steps * 1e3,
+                    "algorithmic_bytes_per_fish_step": 52,
+                    "hbm_frac": 52 * n * steps / wp / 1e9 / HBM_PEAK_GBS}
+    out["fused_speedup"] = out["fused"]["value"] / out["plain"]["value"]
+    return out
 
 
 def precision_form(n: int, steps: int, oracle_steps: int):
@@ -423,10 +433,11 @@ def main() -> int:
     if "fused" in forms:
         line["forms"]["fused_cfg4"] = fused_vs_plain(
             1 << 26, args.fused_steps,
-            "persistent form: N=2^26 fish, 2000 iterations in one cooperative launch vs "
-            "per-iteration launches")
+            f"persistent form: N=2^26 fish, {args.fused_steps} iterations in one cooperative "
+            "launch vs per-iteration launches")
         line["forms"]["fused_cfg2"] = fused_vs_plain(
-            n, args.steps, "persistent form on the headline school (N=2^24, 1000 iterations)")
+            n, args.steps,
+            f"persistent form on the headline school (N=2^24, {args.steps} iterations)")
     if "precision" in forms:
         line["forms"]["precision_cfg3"] = precision_form(1 << 27, args.precision_steps,
                                                          args.precision_oracle_steps)

@@ -73,8 +73,12 @@ extern "C" {
 #define FSB_REDUCE_NAIVE_F32 1u   /* float32 block trees + float32 atomicAdd (accuracy baseline) */
 
 /* fsb_run modes. */
-#define FSB_RUN_PLAIN 0u /* one fsb_step (two kernels) per iteration */
-#define FSB_RUN_FUSED 1u /* one persistent launch with a grid barrier per iteration */
+#define FSB_RUN_PLAIN 0u      /* one fsb_step (two kernels) per iteration */
+#define FSB_RUN_FUSED 1u      /* one persistent launch with a grid barrier per iteration;
+                                 the library picks one of the two variants below */
+#define FSB_RUN_FUSED_PREV 2u /* persistent, x, y, w, prev live: 32 B/fish per iteration */
+#define FSB_RUN_FUSED_LEAN 3u /* persistent, x, y, w live and each swim computed twice:
+                                 24 B/fish per iteration, more arithmetic */
 
 typedef struct fsb_config {
     uint64_t n_fish;      /* fish in the school, >= 1 */
@@ -161,8 +165,8 @@ int fsb_attach(const fsb_config *cfg, fsb_state state, void *workspace,
 int fsb_step(fsb_school *h);
 
 /* n_steps iterations.  FSB_RUN_PLAIN issues fsb_step n_steps times;
- * FSB_RUN_FUSED runs them in persistent launches with a grid barrier per
- * iteration.  Both give bit-identical columns and maxima (the sums agree to
+ * the FSB_RUN_FUSED* modes run them in one persistent launch with a grid
+ * barrier per iteration.  Both give bit-identical columns and maxima (the sums agree to
  * rounding; each mode is deterministic).  Asynchronous; FSB_ERR_UNSUPPORTED
  * if the fused grid cannot be co-resident. */
 int fsb_run(fsb_school *h, uint64_t n_steps, uint32_t mode);

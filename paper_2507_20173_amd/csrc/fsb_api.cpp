@@ -158,9 +158,13 @@ int do_step(fsb_school* h, const float* dx, const float* dy) {
     return FSB_OK;
 }
 
+// FSB_RUN_FUSED: the lean variant trades a second swim per fish for a
+// quarter less traffic; it wins once the live columns are streamed from HBM.
+bool lean_pays(uint64_t n) { return n * 16ull > (256ull << 20); }
+
 // n_steps iterations in one persistent launch (cooperative, so the grid is
 // guaranteed co-resident or the launch fails).
-int run_fused(fsb_school* h, uint64_t n_steps) {
+int run_fused(fsb_school* h, uint64_t n_steps, uint32_t mode) {
     if (n_steps == 0) return FSB_OK;
     const uint32_t naive = h->cfg.reduce_mode == FSB_REDUCE_NAIVE_F32;
     if (h->resident[naive] == 0)
@@ -178,6 +182,7 @@ int run_fused(fsb_school* h, uint64_t n_steps) {
     // Non-temporal streaming once the four live columns outgrow the 256 MB
     // last-level cache (below that, keeping lines cached is faster).
     f.streaming = h->cfg.n_fish * 16ull > (256ull << 20);
+    f.lean = mode == FSB_RUN_FUSED_LEAN || (mode == FSB_RUN_FUSED && lean_pays(h->cfg.n_fish));
     std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
     if (h->profile_every && h->launches[FSB_KERNEL_FUSED]++ % h->profile_every == 0) {
         FSB_HIP_TRY(h->timers[FSB_KERNEL_FUSED].next(&ev), "hipEventCreate");
@@ -268,9 +273,9 @@ int fsb_step_displaced(fsb_school* h, const float* dx, const float* dy) {
 
 int fsb_run(fsb_school* h, uint64_t n_steps, uint32_t mode) {
     if (!h) return fail(FSB_ERR_INVALID_ARG, "handle is NULL");
-    if (mode != FSB_RUN_PLAIN && mode != FSB_RUN_FUSED) return fail(FSB_ERR_INVALID_ARG, "unknown run mode");
+    if (mode > FSB_RUN_FUSED_LEAN) return fail(FSB_ERR_INVALID_ARG, "unknown run mode");
     if (n_steps > kStepLimit - h->t) return fail(FSB_ERR_INVALID_ARG, "iteration index would pass 2^32");
-    if (mode == FSB_RUN_FUSED) return run_fused(h, n_steps);
+    if (mode != FSB_RUN_PLAIN) return run_fused(h, n_steps, mode);
     for (uint64_t k = 0; k < n_steps; ++k) {
         int rc = do_step(h, nullptr, nullptr);
         if (rc) return rc;

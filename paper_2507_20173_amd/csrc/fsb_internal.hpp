@@ -92,6 +92,8 @@ struct FusedArgs {
     uint32_t group_size;  // blocks per barrier group
     uint32_t groups;      // barrier groups (<= kMaxGroups)
     uint32_t streaming;   // non-temporal loads/stores (state larger than the last-level cache)
+    uint32_t lean;        // keep (x, y, w) live and redo each swim (24 B/fish) instead of
+                          // keeping (x, y, w, prev) (32 B/fish)
 };
 
 // Launchers (fsb_kernels.hip).  All enqueue on `stream` and return the HIP

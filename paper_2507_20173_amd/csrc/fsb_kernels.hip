@@ -473,6 +473,138 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
     }
 }
 
+// ---------------------------------------------------------------------------
+// Lean persistent kernel: keeps only (x, y, w) live, 24 B/fish per iteration.
+// Positions stay one swim behind: sweep s reads the positions before swim s,
+// redoes that swim (the same draws and binary32 ops, so the same bits), feeds
+// with M_s, adds the partial sums of s, then swims s+1 on a copy only to get
+// its max.  Each swim is computed twice, which the VALU can afford; the last
+// sweep also writes (prev, cur), leaving the five columns complete.
+// ---------------------------------------------------------------------------
+template <bool kNaive, bool kNT>
+__global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, FusedArgs f) {
+    constexpr int B = kFusedBlock;
+    __shared__ uint32_t M_sh;
+    const float H = a.H, wmin = a.wmin, wmax = a.wmax;
+    const uint32_t grid = gridDim.x;
+    const uint64_t n4 = a.n >> 2;
+    const uint64_t stride = (uint64_t)grid * B;
+    const uint64_t gbase = (uint64_t)blockIdx.x * B + threadIdx.x;
+    const uint64_t tail_i = 4 * n4 + threadIdx.x;
+    const bool has_tail = blockIdx.x == grid - 1 && tail_i < a.n;
+    const Barrier bar{a.sync, a.ctrl, f.group_size, f.groups};
+    uint32_t phase = 0;
+    if (threadIdx.x == 0) phase = ld_agent(a.sync + kSyncPhase);
+
+    // Prologue: M_t0 from a look-ahead swim of t0; nothing is stored.
+    {
+        uint32_t best = 0u;
+        for (uint64_t g = gbase; g < n4; g += stride) {
+            const float4 X = ldv<kNT>(a.x, g), Y = ldv<kNT>(a.y, g);
+            float dx[4], dy[4];
+            group_draws(a.S, a.k0, a.k1, g, f.t0, dx, dy);
+            float4 nx = X, ny = Y;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float c = distance(lane_of(nx, q), lane_of(ny, q));
+                const float nc = swim(lane_of(nx, q), lane_of(ny, q), dx[q], dy[q], H);
+                best = max(best, mag_bits(c - nc));
+            }
+        }
+        if (has_tail) {
+            float dx, dy;
+            fish_draw(a.S, a.k0, a.k1, tail_i, f.t0, dx, dy);
+            float x = a.x[tail_i], y = a.y[tail_i];
+            const float c = distance(x, y);
+            const float nc = swim(x, y, dx, dy, H);
+            best = max(best, mag_bits(c - nc));
+        }
+        const uint32_t m = block_max<B>(best);
+        if (!barrier_max(bar, m, f.t0 & 1u, phase, &M_sh)) return;
+    }
+
+    for (uint32_t k = 0; k < f.steps; ++k) {
+        const uint32_t s = f.t0 + k;
+        const bool last = k + 1 == f.steps;
+        const float M = __uint_as_float(M_sh);
+        if (k > 0 && blockIdx.x == (s - 1u) % grid)
+            combine_block<B>(a, s - 1u, grid, f.naive, ld_agent(a.sync + kSyncMaxPub + ((s - 1u) & 1u)));
+
+        LaneSums<kNaive> ls;
+        uint32_t best = 0u;
+        for (uint64_t g0 = gbase; g0 < n4; g0 += kUnroll * stride) {
+            float4 X[kUnroll], Y[kUnroll], W[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint64_t g = g0 + u * stride;
+                if (g < n4) {
+                    X[u] = ldv<kNT>(a.x, g);
+                    Y[u] = ldv<kNT>(a.y, g);
+                    W[u] = ldv<kNT>(a.w, g);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint64_t g = g0 + u * stride;
+                if (g >= n4) break;
+                float dx[4], dy[4];
+                group_draws(a.S, a.k0, a.k1, g, s, dx, dy);
+                float4 C0, C1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    lane_of(C0, q) = distance(lane_of(X[u], q), lane_of(Y[u], q));
+                    lane_of(C1, q) = swim(lane_of(X[u], q), lane_of(Y[u], q), dx[q], dy[q], H);
+                    const float diff = lane_of(C0, q) - lane_of(C1, q);
+                    lane_of(W[u], q) = feed(lane_of(W[u], q), diff, M, wmin, wmax);
+                    ls.add(lane_of(W[u], q), lane_of(X[u], q), lane_of(Y[u], q));
+                }
+                stv<kNT>(a.x, g, X[u]);
+                stv<kNT>(a.y, g, Y[u]);
+                stv<kNT>(a.w, g, W[u]);
+                if (last) {
+                    stv<kNT>(a.prev, g, C0);
+                    stv<kNT>(a.cur, g, C1);
+                } else {
+                    group_draws(a.S, a.k0, a.k1, g, s + 1u, dx, dy);
+                    float4 nx = X[u], ny = Y[u];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const float nc = swim(lane_of(nx, q), lane_of(ny, q), dx[q], dy[q], H);
+                        best = max(best, mag_bits(lane_of(C1, q) - nc));
+                    }
+                }
+            }
+        }
+        if (has_tail) {
+            float dx, dy;
+            fish_draw(a.S, a.k0, a.k1, tail_i, s, dx, dy);
+            float x = a.x[tail_i], y = a.y[tail_i];
+            const float c0 = distance(x, y);
+            const float c1 = swim(x, y, dx, dy, H);
+            const float nw = feed(a.w[tail_i], c0 - c1, M, wmin, wmax);
+            a.x[tail_i] = x;
+            a.y[tail_i] = y;
+            a.w[tail_i] = nw;
+            ls.add(nw, x, y);
+            if (last) {
+                a.prev[tail_i] = c0;
+                a.cur[tail_i] = c1;
+            } else {
+                fish_draw(a.S, a.k0, a.k1, tail_i, s + 1u, dx, dy);
+                const float nc = swim(x, y, dx, dy, H);
+                best = max(best, mag_bits(c1 - nc));
+            }
+        }
+        block_sums<kNaive, B>(a, ls, s);
+        if (last) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->last_max = M_sh;
+        } else {
+            const uint32_t m = block_max<B>(best);
+            if (!barrier_max(bar, m, (s + 1u) & 1u, phase, &M_sh)) return;
+        }
+    }
+}
+
 // Clears the barrier's counters and maxima before a persistent launch (the
 // phase word only ever advances).
 __global__ void reset_sync_kernel(uint32_t* sync) {
@@ -555,13 +687,14 @@ hipError_t launch_combine(const SchoolArgs& a, uint32_t t, uint32_t grid, uint32
 }
 
 template <bool kNaive, bool kNT>
-const void* fused_fn() {
-    return reinterpret_cast<const void*>(fused_kernel<kNaive, kNT>);
+const void* fused_fn(uint32_t lean) {
+    return lean ? reinterpret_cast<const void*>(fused_lean_kernel<kNaive, kNT>)
+                : reinterpret_cast<const void*>(fused_kernel<kNaive, kNT>);
 }
 
-const void* pick_fused(uint32_t naive, uint32_t streaming) {
-    if (naive) return streaming ? fused_fn<true, true>() : fused_fn<true, false>();
-    return streaming ? fused_fn<false, true>() : fused_fn<false, false>();
+const void* pick_fused(uint32_t naive, uint32_t streaming, uint32_t lean) {
+    if (naive) return streaming ? fused_fn<true, true>(lean) : fused_fn<true, false>(lean);
+    return streaming ? fused_fn<false, true>(lean) : fused_fn<false, false>(lean);
 }
 
 hipError_t fused_resident_grid(uint32_t naive, uint32_t* out_grid) {
@@ -571,9 +704,10 @@ hipError_t fused_resident_grid(uint32_t naive, uint32_t* out_grid) {
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     int per_cu = 1 << 30;
-    for (uint32_t nt = 0; nt < 2; ++nt) {  // both variants must fit
+    for (uint32_t v = 0; v < 4; ++v) {  // every variant must fit
         int b = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, pick_fused(naive, nt), kFusedBlock, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, pick_fused(naive, v & 1, v >> 1),
+                                                         kFusedBlock, 0);
         if (e != hipSuccess) return e;
         per_cu = b < per_cu ? b : per_cu;
     }
@@ -617,8 +751,8 @@ hipError_t launch_fused(const SchoolArgs& a, const FusedArgs& f, uint32_t grid,
     SchoolArgs sa = a;
     FusedArgs fa = f;
     void* args[] = {&sa, &fa};
-    return launch_persistent(pick_fused(f.naive, f.streaming), dim3(grid), dim3(kFusedBlock),
-                             args, stream);
+    return launch_persistent(pick_fused(f.naive, f.streaming, f.lean), dim3(grid),
+                             dim3(kFusedBlock), args, stream);
 }
 
 }  // namespace fsb

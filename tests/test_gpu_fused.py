@@ -32,17 +32,21 @@ def history_sums(h):
     return np.stack([h["sum_w"], h["sum_wx"], h["sum_wy"]], 1)
 
 
+VARIANTS = [fsb.FSB_RUN_FUSED_PREV, fsb.FSB_RUN_FUSED_LEAN]
+
+
+@pytest.mark.parametrize("variant", VARIANTS, ids=["prev", "lean"])
 @pytest.mark.parametrize("n,steps", [(1, 5), (2, 3), (3, 1), (5, 7), (64, 4), (1001, 6),
                                      (4097, 5), (65539, 4), ((1 << 20) + 3, 3),
-                                     ((1 << 23) + 6, 2)])
-def test_fused_matches_oracle(torch_cuda, O, n, steps):
-    announce(f"n={n} steps={steps}")
+                                     ((1 << 23) + 6, 2), ((1 << 24) + 7, 2)])
+def test_fused_matches_oracle(torch_cuda, O, n, steps, variant):
+    announce(f"n={n} steps={steps} variant={variant}")
     cfg = fsb.FsbConfig(n_fish=n, seed=4242 + n, history_len=steps)
     ocfg = oracle_config(cfg)
     school = O.init(ocfg)
     m, s, a = O.run(ocfg, school, 0, steps)
     sch = fsb.School(cfg)
-    sch.run(steps, FUSED)
+    sch.run(steps, variant)
     h = sch.history(0, steps)
     assert np.array_equal(h["step_lo"], np.arange(steps))
     assert np.array_equal(h["max_delta"], m), f"maxima {h['max_delta']} vs {m}"
@@ -52,7 +56,7 @@ def test_fused_matches_oracle(torch_cuda, O, n, steps):
 
 
 def test_fused_plain_interleaved(torch_cuda, O):
-    """plain 2 + fused 3 + plain 1 + fused 1 + fused 4 == oracle 11."""
+    """plain 2 + prev 3 + plain 1 + lean 1 + lean 2 + prev 2 == oracle 11."""
     announce("interleaved")
     n = 30_011
     cfg = fsb.FsbConfig(n_fish=n, seed=5, history_len=11)
@@ -60,7 +64,8 @@ def test_fused_plain_interleaved(torch_cuda, O):
     school = O.init(ocfg)
     m, s, a = O.run(ocfg, school, 0, 11)
     sch = fsb.School(cfg)
-    for k, mode in ((2, PLAIN), (3, FUSED), (1, PLAIN), (1, FUSED), (4, FUSED)):
+    for k, mode in ((2, PLAIN), (3, VARIANTS[0]), (1, PLAIN), (1, VARIANTS[1]), (2, VARIANTS[1]),
+                    (2, VARIANTS[0])):
         sch.run(k, mode)
     h = sch.history(0, 11)
     assert np.array_equal(h["max_delta"], m)
@@ -68,27 +73,29 @@ def test_fused_plain_interleaved(torch_cuda, O):
     assert_columns_equal(sch.state(), school, "interleaved")
 
 
-def test_fused_naive_reduction(torch_cuda, O):
-    announce("naive")
+@pytest.mark.parametrize("variant", VARIANTS, ids=["prev", "lean"])
+def test_fused_naive_reduction(torch_cuda, O, variant):
+    announce(f"naive variant={variant}")
     n = 100_003
     cfg = fsb.FsbConfig(n_fish=n, seed=6, reduce_mode=fsb.FSB_REDUCE_NAIVE_F32, history_len=4)
     ocfg = oracle_config(cfg)
     school = O.init(ocfg)
     m, s, a = O.run(ocfg, school, 0, 4)
     sch = fsb.School(cfg)
-    sch.run(4, FUSED)
+    sch.run(4, variant)
     h = sch.history(0, 4)
     assert np.array_equal(h["max_delta"], m)
     assert_sums_close(history_sums(h), s, a, tol=1e-3, what="fused naive")
     assert_columns_equal(sch.state(), school, "fused naive")
 
 
-def test_fused_zero_swim(torch_cuda):
+@pytest.mark.parametrize("variant", VARIANTS, ids=["prev", "lean"])
+def test_fused_zero_swim(torch_cuda, variant):
     announce("zero swim")
     cfg = fsb.FsbConfig(n_fish=7777, seed=3, swim_step=0.0, history_len=5)
     sch = fsb.School(cfg)
     before = sch.state()
-    sch.run(5, FUSED)
+    sch.run(5, variant)
     assert (sch.history(0, 5)["max_delta"] == 0).all()
     after = sch.state()
     for k in before:
@@ -108,17 +115,18 @@ def test_fused_is_deterministic(torch_cuda):
     assert runs[0] == runs[1]
 
 
-def test_cfg4_full_size_prefix(torch_cuda, O):
+@pytest.mark.parametrize("variant", [fsb.FSB_RUN_FUSED] + VARIANTS, ids=["auto", "prev", "lean"])
+def test_cfg4_full_size_prefix(torch_cuda, O, variant):
     """N = 2^26 (the persistent-form workload) for the first iterations,
     every fish bit-exact."""
     n, steps = 1 << 26, 2
-    announce(f"cfg4 N={n} prefix {steps}")
+    announce(f"cfg4 N={n} prefix {steps} variant={variant}")
     cfg = fsb.FsbConfig(n_fish=n, seed=0, history_len=steps)
     ocfg = oracle_config(cfg)
     school = O.init(ocfg)
     m, s, a = O.run(ocfg, school, 0, steps)
     sch = fsb.School(cfg)
-    sch.run(steps, FUSED)
+    sch.run(steps, variant)
     h = sch.history(0, steps)
     assert np.array_equal(h["max_delta"], m)
     assert_sums_close(history_sums(h), s, a, what="cfg4 prefix")
