@@ -159,8 +159,11 @@ int do_step(fsb_school* h, const float* dx, const float* dy) {
 }
 
 // FSB_RUN_FUSED: the lean variant trades a second swim per fish for a
-// quarter less traffic; it wins once the live columns are streamed from HBM.
-bool lean_pays(uint64_t n) { return n * 16ull > (256ull << 20); }
+// quarter less traffic.  Measured on MI355X it wins once the 32-byte
+// variant's live columns (16 B/fish) no longer fit the 256 MiB last-level
+// cache with room to spare (N >= 2^24); below that the cache feeds both and
+// the extra arithmetic costs more than the saved bytes.
+bool lean_pays(uint64_t n) { return n * 16ull >= (256ull << 20); }
 
 // n_steps iterations in one persistent launch (cooperative, so the grid is
 // guaranteed co-resident or the launch fails).

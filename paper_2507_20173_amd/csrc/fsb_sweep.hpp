@@ -130,9 +130,20 @@ __device__ __forceinline__ bool barrier_max(const Barrier& b, uint32_t m, uint32
         const uint32_t g = blockIdx.x / b.group_size;
         const uint32_t members = min(b.group_size, gridDim.x - g * b.group_size);
         uint32_t* grp = sync + kSyncGroups + g * kLineWords;
-        max_agent(grp + 1, m);
         bool released = false;
-        if (arrive(grp) == members - 1u) {
+        if (b.groups == 1u) {
+            // one group: its counter is the root
+            max_agent(sync + kSyncRootMax, m);
+            if (arrive(sync + kSyncRootCount) == members - 1u) {
+                const uint32_t M = ld_agent(sync + kSyncRootMax);
+                st_agent(sync + kSyncRootMax, 0u);
+                st_agent(sync + kSyncMaxPub + parity, M);
+                st_agent(sync + kSyncRootCount, 0u);
+                __hip_atomic_store(sync + kSyncPhase, target, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                released = true;
+            }
+        } else if (max_agent(grp + 1, m), arrive(grp) == members - 1u) {
             const uint32_t gm = ld_agent(grp + 1);
             st_agent(grp + 1, 0u);
             st_agent(grp, 0u);
