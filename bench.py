@@ -246,7 +246,9 @@ def batched_form(n_schools: int, steps: int, probe_steps: int, baseline_schools:
     del b
     torch.cuda.empty_cache()
     K = min(tune.steps_per_launch, steps)
-    bytes_total = total * (24 * launches + 32 * (steps - launches) + 24 * launches)
+    lean = tune.variant == fsb.FSB_RUN_FUSED_LEAN
+    bytes_total = (total * (8 * launches + 24 * steps + 8 * launches) if lean
+                   else total * (24 * launches + 32 * (steps - launches) + 24 * launches))
 
     # baseline: the first schools one by one, fsb_step per iteration
     base_fish, base_wall = 0, 0.0
@@ -270,7 +272,8 @@ def batched_form(n_schools: int, steps: int, probe_steps: int, baseline_schools:
         "n_schools": n_schools, "total_fish": total, "iterations": steps,
         "tuning": fsb.tuning_dict(tune), "autotune_probe_steps": probe_steps,
         "value": value, "ms_per_step": wall / steps * 1e3, "launches": int(launches),
-        "algorithmic_bytes_per_fish_step": 32,
+        "variant": "lean" if lean else "prev",
+        "algorithmic_bytes_per_fish_step": 24 if lean else 32,
         "kernel_achieved_GBs": bytes_total / (ms / 1e3) / 1e9,
         "kernel_hbm_frac": bytes_total / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
         "baseline_per_school_plain": {"schools": baseline_schools, "fish": base_fish,

@@ -123,6 +123,9 @@ typedef struct fsb_tuning {
                                   wavefront's share of one school: 64 x this many fish) */
     uint32_t steps_per_launch; /* iterations per persistent launch, >= 1 */
     uint32_t blocks_per_cu;    /* resident blocks per compute unit to use (0 = all that fit) */
+    uint32_t variant;          /* 0 = chosen by the library, FSB_RUN_FUSED_PREV (x, y, w, prev
+                                  live: 32 B/fish per iteration) or FSB_RUN_FUSED_LEAN (x, y, w
+                                  live, each swim done twice: 24 B/fish) */
 } fsb_tuning;
 
 /* ---- errors ------------------------------------------------------------ */
@@ -227,7 +230,7 @@ int fsb_batch_workspace_bytes(const fsb_config *common, uint32_t n_schools,
 
 /* Initialise every school (Sec. 2.1.1 draws, per-school key) and return a
  * handle at iteration 0 with the default tuning (1024 threads, 8 fish per
- * lane, 100 iterations per launch).  Uploads the school tables (synchronous
+ * lane, 100 iterations per launch, variant chosen by the library).  Uploads the school tables (synchronous
  * copies), then enqueues the init kernel on `stream`. */
 int fsb_batch_init(const fsb_config *common, uint32_t n_schools,
                    const uint64_t *starts, const uint64_t *sizes,
@@ -254,8 +257,8 @@ int fsb_batch_results(fsb_batch *b, double *out_xy, double *out_sums,
 int fsb_batch_history(fsb_batch *b, uint64_t step, fsb_record *out);
 
 /* Time candidate tunings (256 or 1024 threads x 4, 8 or 16 fish per lane,
- * then iterations per launch), each on probe_steps real iterations (the
- * schools advance), keep the fastest as the handle's tuning and copy it to
+ * then the two variants, then iterations per launch), each on probe_steps
+ * real iterations (the schools advance), keep the fastest as the handle's tuning and copy it to
  * *out.  If the environment variable FSB_AUTOTUNE_CACHE names a file, a
  * tuning recorded there for this device and batch shape is reused without
  * probing, and new results are appended.  Synchronises. */

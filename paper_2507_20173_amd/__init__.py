@@ -181,8 +181,8 @@ def fsb_batch_init(common: FsbConfig, starts, sizes, seeds, cols: dict, workspac
     return h
 
 
-def tuning(block_size=1024, fish_per_thread=8, steps_per_launch=100, blocks_per_cu=0):
-    return _lib.fsb_tuning(block_size, fish_per_thread, steps_per_launch, blocks_per_cu)
+def tuning(block_size=1024, fish_per_thread=8, steps_per_launch=100, blocks_per_cu=0, variant=0):
+    return _lib.fsb_tuning(block_size, fish_per_thread, steps_per_launch, blocks_per_cu, variant)
 
 
 def tuning_dict(t: _lib.fsb_tuning) -> dict:

@@ -53,7 +53,8 @@ class fsb_record(ctypes.Structure):
 
 class fsb_tuning(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_uint32), ("fish_per_thread", ctypes.c_uint32),
-                ("steps_per_launch", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32)]
+                ("steps_per_launch", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
+                ("variant", ctypes.c_uint32)]
 
 
 class FsbError(RuntimeError):

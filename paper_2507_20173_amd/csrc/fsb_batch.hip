@@ -137,8 +137,10 @@ __device__ __forceinline__ void tile_sums(const BatchArgs& a, LaneSums<kNaive>& 
 // its school's max fetched while the current tile streams.
 // ---------------------------------------------------------------------------
 
-// Prologue work of one tile: swim t0 from (x, y, cur), keep (x, y, prev).
-template <int GPL, bool kNT>
+// Prologue work of one tile.  32-byte variant: swim t0 from (x, y, cur),
+// keep (x, y, prev).  Lean variant: a look-ahead swim of t0 for the max only,
+// nothing stored.
+template <int GPL, bool kNT, bool kLean>
 __device__ __forceinline__ uint32_t tile_prologue(const BatchArgs& a, const Tile& T, uint32_t t0,
                                                   uint32_t lane) {
     const float H = a.H, Sw = a.S;
@@ -150,7 +152,14 @@ __device__ __forceinline__ uint32_t tile_prologue(const BatchArgs& a, const Tile
         const uint64_t g = (uint64_t)T.group0 + j;
         const uint64_t c4 = T.col4 + j;
         if (4 * j + 4 <= T.n_fish) {
-            float4 X = ldv<kNT>(a.x, c4), Y = ldv<kNT>(a.y, c4), C = ldv<kNT>(a.cur, c4);
+            float4 X = ldv<kNT>(a.x, c4), Y = ldv<kNT>(a.y, c4);
+            float4 C;
+            if constexpr (kLean) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f) lane_of(C, f) = distance(lane_of(X, f), lane_of(Y, f));
+            } else {
+                C = ldv<kNT>(a.cur, c4);
+            }
             float dx[4], dy[4];
             group_draws(Sw, T.k0, T.k1, g, t0, dx, dy);
 #pragma unroll
@@ -158,28 +167,32 @@ __device__ __forceinline__ uint32_t tile_prologue(const BatchArgs& a, const Tile
                 const float nc = swim(lane_of(X, f), lane_of(Y, f), dx[f], dy[f], H);
                 best = max(best, mag_bits(lane_of(C, f) - nc));
             }
-            stv<kNT>(a.x, c4, X);
-            stv<kNT>(a.y, c4, Y);
-            stv<kNT>(a.prev, c4, C);
+            if constexpr (!kLean) {
+                stv<kNT>(a.x, c4, X);
+                stv<kNT>(a.y, c4, Y);
+                stv<kNT>(a.prev, c4, C);
+            }
         } else {
             for (uint32_t f = 0; 4 * j + f < T.n_fish; ++f) {
                 const uint64_t o = 4 * c4 + f;
                 float dx, dy;
                 fish_draw(Sw, T.k0, T.k1, 4 * g + f, t0, dx, dy);
                 float x = a.x[o], y = a.y[o];
-                const float c = a.cur[o];
+                const float c = kLean ? distance(x, y) : a.cur[o];
                 const float nc = swim(x, y, dx, dy, H);
                 best = max(best, mag_bits(c - nc));
-                a.x[o] = x;
-                a.y[o] = y;
-                a.prev[o] = c;
+                if constexpr (!kLean) {
+                    a.x[o] = x;
+                    a.y[o] = y;
+                    a.prev[o] = c;
+                }
             }
         }
     }
     return best;
 }
 
-template <int BLOCK, int GPL, bool kNaive, bool kNT>
+template <int BLOCK, int GPL, bool kNaive, bool kNT, bool kLean>
 __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
     constexpr uint32_t WPB = BLOCK / kWave;
     __shared__ uint32_t M_sh;
@@ -197,7 +210,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
         uint32_t* next_max = a.school_max + (size_t)(t0 % 3u) * S;
         for (uint32_t tl = wave; tl < a.n_tiles; tl += n_waves) {
             const Tile T = a.tiles[tl];
-            const uint32_t best = wave_max_u32(tile_prologue<GPL, kNT>(a, T, t0, lane));
+            const uint32_t best = wave_max_u32(tile_prologue<GPL, kNT, kLean>(a, T, t0, lane));
             if (lane == 0) max_agent(next_max + T.school, best);
         }
     }
@@ -228,7 +241,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
                     X[q] = ldv<kNT>(a.x, T.col4 + j);
                     Y[q] = ldv<kNT>(a.y, T.col4 + j);
                     W[q] = ldv<kNT>(a.w, T.col4 + j);
-                    P[q] = ldv<kNT>(a.prev, T.col4 + j);
+                    if constexpr (!kLean) P[q] = ldv<kNT>(a.prev, T.col4 + j);
                 }
             }
             const uint32_t Mn = nx < a.n_tiles ? ld_agent(cur_max + Tn.school) : 0u;
@@ -243,47 +256,80 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
                 const uint64_t c4 = T.col4 + j;
                 if (4 * j + 4 <= T.n_fish) {
                     float4 C;
+                    float dx[4], dy[4];
+                    if constexpr (kLean) {
+                        // redo swim s from the stored pre-swim position
+                        group_draws(Sw, T.k0, T.k1, g, s, dx, dy);
+#pragma unroll
+                        for (int f = 0; f < 4; ++f) {
+                            lane_of(P[q], f) = distance(lane_of(X[q], f), lane_of(Y[q], f));
+                            lane_of(C, f) = swim(lane_of(X[q], f), lane_of(Y[q], f), dx[f], dy[f], H);
+                        }
+                    } else {
+#pragma unroll
+                        for (int f = 0; f < 4; ++f)
+                            lane_of(C, f) = distance(lane_of(X[q], f), lane_of(Y[q], f));
+                    }
 #pragma unroll
                     for (int f = 0; f < 4; ++f) {
-                        lane_of(C, f) = distance(lane_of(X[q], f), lane_of(Y[q], f));
                         const float diff = lane_of(P[q], f) - lane_of(C, f);
                         lane_of(W[q], f) = feed(lane_of(W[q], f), diff, M, wmin, wmax);
                         ls.add(lane_of(W[q], f), lane_of(X[q], f), lane_of(Y[q], f));
                     }
                     stv<kNT>(a.w, c4, W[q]);
+                    if constexpr (kLean) {
+                        stv<kNT>(a.x, c4, X[q]);
+                        stv<kNT>(a.y, c4, Y[q]);
+                    }
                     if (last) {
+                        if constexpr (kLean) stv<kNT>(a.prev, c4, P[q]);
                         stv<kNT>(a.cur, c4, C);
                     } else {
-                        float dx[4], dy[4];
                         group_draws(Sw, T.k0, T.k1, g, s + 1u, dx, dy);
+                        float4 nx = X[q], ny = Y[q];
 #pragma unroll
                         for (int f = 0; f < 4; ++f) {
                             const float nc =
-                                swim(lane_of(X[q], f), lane_of(Y[q], f), dx[f], dy[f], H);
+                                swim(lane_of(nx, f), lane_of(ny, f), dx[f], dy[f], H);
                             best = max(best, mag_bits(lane_of(C, f) - nc));
                         }
-                        stv<kNT>(a.x, c4, X[q]);
-                        stv<kNT>(a.y, c4, Y[q]);
-                        stv<kNT>(a.prev, c4, C);
+                        if constexpr (!kLean) {
+                            stv<kNT>(a.x, c4, nx);
+                            stv<kNT>(a.y, c4, ny);
+                            stv<kNT>(a.prev, c4, C);
+                        }
                     }
                 } else {
                     for (uint32_t f = 0; 4 * j + f < T.n_fish; ++f) {
                         const uint64_t o = 4 * c4 + f;
                         float x = a.x[o], y = a.y[o];
-                        const float c = distance(x, y);
-                        const float nw = feed(a.w[o], a.prev[o] - c, M, wmin, wmax);
+                        float pv, c;
+                        float dx, dy;
+                        if constexpr (kLean) {
+                            fish_draw(Sw, T.k0, T.k1, 4 * g + f, s, dx, dy);
+                            pv = distance(x, y);
+                            c = swim(x, y, dx, dy, H);
+                            a.x[o] = x;
+                            a.y[o] = y;
+                        } else {
+                            pv = a.prev[o];
+                            c = distance(x, y);
+                        }
+                        const float nw = feed(a.w[o], pv - c, M, wmin, wmax);
                         a.w[o] = nw;
                         ls.add(nw, x, y);
                         if (last) {
+                            if constexpr (kLean) a.prev[o] = pv;
                             a.cur[o] = c;
                         } else {
-                            float dx, dy;
                             fish_draw(Sw, T.k0, T.k1, 4 * g + f, s + 1u, dx, dy);
                             const float nc = swim(x, y, dx, dy, H);
                             best = max(best, mag_bits(c - nc));
-                            a.x[o] = x;
-                            a.y[o] = y;
-                            a.prev[o] = c;
+                            if constexpr (!kLean) {
+                                a.x[o] = x;
+                                a.y[o] = y;
+                                a.prev[o] = c;
+                            }
                         }
                     }
                 }
@@ -324,29 +370,33 @@ hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t stream) {
     return hipGetLastError();
 }
 
+template <int BLOCK, int GPL, bool kNaive>
+const void* batch_fn8(uint32_t nt, uint32_t lean) {
+    if (nt) return lean ? reinterpret_cast<const void*>(batch_kernel<BLOCK, GPL, kNaive, true, true>)
+                        : reinterpret_cast<const void*>(batch_kernel<BLOCK, GPL, kNaive, true, false>);
+    return lean ? reinterpret_cast<const void*>(batch_kernel<BLOCK, GPL, kNaive, false, true>)
+                : reinterpret_cast<const void*>(batch_kernel<BLOCK, GPL, kNaive, false, false>);
+}
+
 template <int BLOCK, int GPL>
-const void* batch_fn4(uint32_t naive, uint32_t nt) {
-    if (naive)
-        return nt ? reinterpret_cast<const void*>(batch_kernel<BLOCK, GPL, true, true>)
-                  : reinterpret_cast<const void*>(batch_kernel<BLOCK, GPL, true, false>);
-    return nt ? reinterpret_cast<const void*>(batch_kernel<BLOCK, GPL, false, true>)
-              : reinterpret_cast<const void*>(batch_kernel<BLOCK, GPL, false, false>);
+const void* batch_fn4(uint32_t naive, uint32_t nt, uint32_t lean) {
+    return naive ? batch_fn8<BLOCK, GPL, true>(nt, lean) : batch_fn8<BLOCK, GPL, false>(nt, lean);
 }
 
 template <int BLOCK>
-const void* batch_fn2(uint32_t fpl, uint32_t naive, uint32_t nt) {
+const void* batch_fn2(uint32_t fpl, uint32_t naive, uint32_t nt, uint32_t lean) {
     switch (fpl) {
-        case 4: return batch_fn4<BLOCK, 1>(naive, nt);
-        case 8: return batch_fn4<BLOCK, 2>(naive, nt);
-        case 16: return batch_fn4<BLOCK, 4>(naive, nt);
+        case 4: return batch_fn4<BLOCK, 1>(naive, nt, lean);
+        case 8: return batch_fn4<BLOCK, 2>(naive, nt, lean);
+        case 16: return batch_fn4<BLOCK, 4>(naive, nt, lean);
         default: return nullptr;
     }
 }
 
-const void* batch_fn(uint32_t block, uint32_t fpl, uint32_t naive, uint32_t nt) {
+const void* batch_fn(uint32_t block, uint32_t fpl, uint32_t naive, uint32_t nt, uint32_t lean) {
     switch (block) {
-        case 256: return batch_fn2<256>(fpl, naive, nt);
-        case 1024: return batch_fn2<1024>(fpl, naive, nt);
+        case 256: return batch_fn2<256>(fpl, naive, nt, lean);
+        case 1024: return batch_fn2<1024>(fpl, naive, nt, lean);
         default: return nullptr;
     }
 }
@@ -360,8 +410,8 @@ hipError_t batch_resident_grid(uint32_t block, uint32_t fish_per_lane, uint32_t 
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     int per_cu = 1 << 30;
-    for (uint32_t nt = 0; nt < 2; ++nt) {
-        const void* fn = batch_fn(block, fish_per_lane, naive, nt);
+    for (uint32_t v = 0; v < 4; ++v) {  // every variant must fit
+        const void* fn = batch_fn(block, fish_per_lane, naive, v & 1, v >> 1);
         if (!fn) return hipErrorInvalidValue;
         int b = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, (int)block, 0);
@@ -375,8 +425,9 @@ hipError_t batch_resident_grid(uint32_t block, uint32_t fish_per_lane, uint32_t 
 }
 
 hipError_t launch_batch(const BatchArgs& a, uint32_t block, uint32_t fish_per_lane,
-                        uint32_t naive, uint32_t streaming, uint32_t grid, hipStream_t stream) {
-    const void* fn = batch_fn(block, fish_per_lane, naive, streaming);
+                        uint32_t naive, uint32_t streaming, uint32_t lean, uint32_t grid,
+                        hipStream_t stream) {
+    const void* fn = batch_fn(block, fish_per_lane, naive, streaming, lean);
     if (!fn) return hipErrorInvalidValue;
     hipError_t e = launch_batch_reset(a, stream);
     if (e != hipSuccess) return e;

@@ -35,7 +35,7 @@ struct fsb_batch {
     uint32_t table_fpl;   // fish per lane of the uploaded tile table (0 = none)
     uint32_t n_tiles;
     hipGraphExec_t graph;
-    uint32_t graph_steps, graph_grid, graph_block, graph_fpl;
+    uint32_t graph_steps, graph_grid, graph_block, graph_fpl, graph_lean;
     uint32_t profile_every;  // time every n-th launch (0 = off)
     uint64_t launches;
     Timer timer;
@@ -84,7 +84,17 @@ int check_tuning(const fsb_tuning* t) {
     if (!valid_fpl(t->fish_per_thread))
         return fail(FSB_ERR_INVALID_ARG, "fish_per_thread must be 4, 8 or 16");
     if (t->steps_per_launch == 0) return fail(FSB_ERR_INVALID_ARG, "steps_per_launch must be >= 1");
+    if (t->variant != 0 && t->variant != FSB_RUN_FUSED_PREV && t->variant != FSB_RUN_FUSED_LEAN)
+        return fail(FSB_ERR_INVALID_ARG, "variant must be 0, FSB_RUN_FUSED_PREV or FSB_RUN_FUSED_LEAN");
     return FSB_OK;
+}
+
+// Variant 0: lean once the 32-byte variant's live columns reach the 256 MiB
+// last-level cache (the single-school rule, measured the same way).
+uint32_t use_lean(const fsb_batch* b) {
+    if (b->tuning.variant == FSB_RUN_FUSED_LEAN) return 1;
+    if (b->tuning.variant == FSB_RUN_FUSED_PREV) return 0;
+    return b->total_fish * 16ull >= (256ull << 20) ? 1 : 0;
 }
 
 // Build and upload the tile table for `fpl` fish per lane (synchronises).
@@ -161,8 +171,8 @@ int launch_once(fsb_batch* b, uint32_t steps, uint32_t grid) {
     const uint32_t naive = b->cfg.reduce_mode == FSB_REDUCE_NAIVE_F32;
     const uint32_t nt = b->total_fish * 16ull > (256ull << 20);
     const BatchArgs a = launch_args(b, steps, grid);
-    hipError_t e = launch_batch(a, b->tuning.block_size, b->tuning.fish_per_thread, naive, nt, grid,
-                                b->stream);
+    hipError_t e = launch_batch(a, b->tuning.block_size, b->tuning.fish_per_thread, naive, nt,
+                                use_lean(b), grid, b->stream);
     if (e == hipErrorCooperativeLaunchTooLarge)
         return fail(FSB_ERR_UNSUPPORTED, "batched grid cannot be co-resident");
     if (e != hipSuccess) return hip_fail(e, "batched kernel launch");
@@ -172,7 +182,8 @@ int launch_once(fsb_batch* b, uint32_t steps, uint32_t grid) {
 // Capture [reset, persistent launch of `steps` iterations] once per shape.
 int ensure_graph(fsb_batch* b, uint32_t steps, uint32_t grid) {
     if (b->graph && b->graph_steps == steps && b->graph_grid == grid &&
-        b->graph_block == b->tuning.block_size && b->graph_fpl == b->tuning.fish_per_thread)
+        b->graph_block == b->tuning.block_size && b->graph_fpl == b->tuning.fish_per_thread &&
+        b->graph_lean == use_lean(b))
         return FSB_OK;
     if (b->graph) {
         (void)hipGraphExecDestroy(b->graph);
@@ -183,8 +194,8 @@ int ensure_graph(fsb_batch* b, uint32_t steps, uint32_t grid) {
     const uint32_t nt = b->total_fish * 16ull > (256ull << 20);
     const BatchArgs a = launch_args(b, steps, grid);
     FSB_HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    hipError_t e = launch_batch(a, b->tuning.block_size, b->tuning.fish_per_thread, naive, nt, grid,
-                                b->capture);
+    hipError_t e = launch_batch(a, b->tuning.block_size, b->tuning.fish_per_thread, naive, nt,
+                                use_lean(b), grid, b->capture);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->capture, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -201,6 +212,7 @@ int ensure_graph(fsb_batch* b, uint32_t steps, uint32_t grid) {
     b->graph_grid = grid;
     b->graph_block = b->tuning.block_size;
     b->graph_fpl = b->tuning.fish_per_thread;
+    b->graph_lean = use_lean(b);
     return FSB_OK;
 }
 
@@ -302,8 +314,8 @@ bool cache_lookup(const std::string& key, fsb_tuning* out) {
     while (std::fgets(line, sizeof(line), f)) {
         char k[300];
         fsb_tuning t;
-        if (std::sscanf(line, "%299s %u %u %u %u", k, &t.block_size, &t.fish_per_thread,
-                        &t.steps_per_launch, &t.blocks_per_cu) == 5 &&
+        if (std::sscanf(line, "%299s %u %u %u %u %u", k, &t.block_size, &t.fish_per_thread,
+                        &t.steps_per_launch, &t.blocks_per_cu, &t.variant) == 6 &&
             key == k && check_tuning(&t) == FSB_OK) {
             *out = t;
             found = true;
@@ -318,8 +330,8 @@ void cache_store(const std::string& key, const fsb_tuning& t) {
     if (!path || !*path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %u %u %u %u\n", key.c_str(), t.block_size, t.fish_per_thread,
-                 t.steps_per_launch, t.blocks_per_cu);
+    std::fprintf(f, "%s %u %u %u %u %u\n", key.c_str(), t.block_size, t.fish_per_thread,
+                 t.steps_per_launch, t.blocks_per_cu, t.variant);
     std::fclose(f);
 }
 
@@ -398,7 +410,7 @@ int fsb_batch_init(const fsb_config* common, uint32_t n_schools, const uint64_t*
     b->ws_bytes = workspace_bytes;
     b->stream = static_cast<hipStream_t>(stream);
     b->L = L;
-    b->tuning = fsb_tuning{1024, 8, 100, 0};
+    b->tuning = fsb_tuning{1024, 8, 100, 0, 0};
 
     char* base = static_cast<char*>(workspace);
     BatchArgs& a = b->args;
@@ -498,7 +510,7 @@ int fsb_autotune(fsb_batch* b, uint64_t probe_steps, fsb_tuning* out) {
     best = b->tuning;
     for (uint32_t block : kBatchBlocks)
         for (uint32_t fpl : kBatchFishPerLane) {
-            fsb_tuning tu{block, fpl, (uint32_t)probe_steps, 0};
+            fsb_tuning tu{block, fpl, (uint32_t)probe_steps, 0, 0};
             double ms = 0.0;
             int rc = probe(b, tu, probe_steps, &ms);
             if (rc == FSB_ERR_UNSUPPORTED) continue;
@@ -508,6 +520,18 @@ int fsb_autotune(fsb_batch* b, uint64_t probe_steps, fsb_tuning* out) {
                 best = tu;
             }
         }
+    // both variants for the best shape
+    for (uint32_t v : {(uint32_t)FSB_RUN_FUSED_PREV, (uint32_t)FSB_RUN_FUSED_LEAN}) {
+        fsb_tuning tu = best;
+        tu.variant = v;
+        double ms = 0.0;
+        int rc = probe(b, tu, probe_steps, &ms);
+        if (rc) return rc;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = tu;
+        }
+    }
     // iterations per launch for the best shape: short launches against one
     // launch of probe_steps (each launch re-reads the state once more in its
     // prologue and pays one graph launch)

@@ -184,9 +184,11 @@ constexpr uint32_t kBatchMinTileFish = 64 * 4;
 hipError_t launch_batch_init(const BatchArgs& a, uint32_t block, hipStream_t stream);
 hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t stream);
 // Persistent launch of a.steps iterations; `streaming` selects non-temporal
-// column access.  Cooperative, so the grid is guaranteed co-resident.
+// column access, `lean` the 24-byte variant (x, y, w live, each swim done
+// twice).  Cooperative, so the grid is guaranteed co-resident.
 hipError_t launch_batch(const BatchArgs& a, uint32_t block, uint32_t fish_per_lane,
-                        uint32_t naive, uint32_t streaming, uint32_t grid, hipStream_t stream);
+                        uint32_t naive, uint32_t streaming, uint32_t lean, uint32_t grid,
+                        hipStream_t stream);
 // Largest co-resident grid for a shape (0 if it cannot run).
 hipError_t batch_resident_grid(uint32_t block, uint32_t fish_per_lane, uint32_t naive,
                                uint32_t* out_grid);

@@ -52,13 +52,16 @@ def check_batch_against_oracle(O, b, steps, schools=None, what=""):
         assert_columns_equal(b.school_state(i), school, f"{what} school {i}")
 
 
+@pytest.mark.parametrize("variant", [fsb.FSB_RUN_FUSED_PREV, fsb.FSB_RUN_FUSED_LEAN],
+                         ids=["prev", "lean"])
 @pytest.mark.parametrize("align", [4, 64])
-def test_batch_matches_oracle_per_school(torch_cuda, O, align):
-    announce(f"{len(SIZES)} schools, 6 iterations, starts aligned to {align} fish")
+def test_batch_matches_oracle_per_school(torch_cuda, O, align, variant):
+    announce(f"{len(SIZES)} schools, 6 iterations, starts aligned to {align} fish, "
+             f"variant {variant}")
     common = fsb.FsbConfig(n_fish=0, history_len=6)
     seeds = [17 * i + 3 for i in range(len(SIZES))]
     b = fsb.Batch(common, SIZES, seeds, starts=packed_starts(SIZES, align))
-    b.run(6)
+    b.run(6, fsb.tuning(variant=variant))
     check_batch_against_oracle(O, b, 6, what="default tuning")
     for step in range(6):
         h = b.history(step)
@@ -66,10 +69,12 @@ def test_batch_matches_oracle_per_school(torch_cuda, O, align):
     b.close()
 
 
+@pytest.mark.parametrize("variant", [fsb.FSB_RUN_FUSED_PREV, fsb.FSB_RUN_FUSED_LEAN],
+                         ids=["prev", "lean"])
 @pytest.mark.parametrize("block", [256, 1024])
 @pytest.mark.parametrize("fpl", [4, 8, 16])
-def test_every_launch_shape_gives_identical_state(torch_cuda, block, fpl):
-    announce(f"shape block={block} fish_per_thread={fpl}")
+def test_every_launch_shape_gives_identical_state(torch_cuda, block, fpl, variant):
+    announce(f"shape block={block} fish_per_thread={fpl} variant={variant}")
     common = fsb.FsbConfig(n_fish=0)
     seeds = list(range(len(SIZES)))
     ref = fsb.Batch(common, SIZES, seeds)
@@ -78,7 +83,7 @@ def test_every_launch_shape_gives_identical_state(torch_cuda, block, fpl):
     _, ref_sums, ref_max = ref.results()
     for k_launch in (1, 2, 5):
         b = fsb.Batch(common, SIZES, seeds)
-        b.run(5, fsb.tuning(block, fpl, k_launch))
+        b.run(5, fsb.tuning(block, fpl, k_launch, variant=variant))
         for i in range(b.n):
             got = b.school_state(i)
             for k in got:
@@ -159,6 +164,7 @@ def test_autotune_and_cache(torch_cuda, tmp_path):
         d = fsb.tuning_dict(tune)
         assert d["block_size"] in (256, 1024) and d["fish_per_thread"] in (4, 8, 16)
         assert d["steps_per_launch"] >= 1
+        assert d["variant"] in (fsb.FSB_RUN_FUSED_PREV, fsb.FSB_RUN_FUSED_LEAN)
         assert b.t > t0
         assert fsb.tuning_dict(b.tuning) == d
         assert cache.exists() and cache.read_text().strip()
