@@ -134,8 +134,10 @@ def fused_vs_plain(n: int, steps: int, label: str):
     for key, mode in (("fused", fsb.FSB_RUN_FUSED), ("fused_prev", fsb.FSB_RUN_FUSED_PREV),
                       ("fused_lean", fsb.FSB_RUN_FUSED_LEAN)):
         wall, counts, ms = run_form(n, steps, mode)
+        # FSB_RUN_FUSED picks lean once the 16 B/fish of the 32-byte variant's
+        # live columns reach the 256 MiB last-level cache
         variant = {"fused_prev": "prev", "fused_lean": "lean"}.get(
-            key, "lean" if n * 16 > (256 << 20) else "prev")
+            key, "lean" if n * 16 >= (256 << 20) else "prev")
         kernel_s = ms[fsb.FSB_KERNEL_FUSED] / 1e3
         nbytes = persistent_bytes(variant, n, steps)
         out[key] = {"variant": variant, "value": n * steps / wall, "ms_per_step": wall / steps * 1e3,
