@@ -153,26 +153,56 @@ def fused_vs_plain(n: int, steps: int, label: str):
     return out
 
 
-def precision_form(n: int, steps: int, oracle_steps: int):
+def column_reference(sch):
+    """Reference values of the last iteration from the columns the kernels
+    left behind: binary64 sums (a binary32 product is exact in binary64;
+    numpy's pairwise summation adds ~1e-15 relative) and the max of
+    |prev - cur| formed in binary32 like the kernels' diff."""
+    import numpy as np
+
+    st = sch.state()
+    w = st["w"].astype(np.float64)
+    wx = w * st["x"].astype(np.float64)
+    wy = w * st["y"].astype(np.float64)
+    ref = np.array([w.sum(), wx.sum(), wy.sum()])
+    den = np.array([np.abs(w).sum(), np.abs(wx).sum(), np.abs(wy).sum()])
+    m = np.abs(st["prev"] - st["cur"]).max() if len(w) else np.float32(0)
+    return ref, den, m
+
+
+def checked_iterations(sch, k: int):
+    """k single iterations, each checked against its column reference: the
+    largest sum error (|got - ref| / sum|terms|) and whether M was exact."""
+    import numpy as np
+
+    errs, exact = [], True
+    for _ in range(k):
+        sch.step()
+        _, got = sch.barycentre()
+        ref, den, m = column_reference(sch)
+        errs.append((np.abs(np.asarray(got) - ref) / den).tolist())
+        exact &= bool(sch.max_delta() == m)
+    return errs, exact
+
+
+def precision_form(n: int, steps: int, checked_steps: int):
     """Compensated (default) vs naive float32-atomic barycentre sums on one
-    school: throughput of each, and the error of each recorded iteration
-    against the oracle's binary64 sums (first `oracle_steps` iterations) and
-    against numpy's binary64 sums of the final columns (last iteration)."""
+    school: throughput of each, and the error of the first `checked_steps`
+    iterations and of the last one against binary64 sums of the columns."""
     import numpy as np
     import torch
 
     import paper_2507_20173_amd as fsb
-    from oracle.oracle import Config, default
 
     out = {"workload": f"precision form: N=2^{n.bit_length() - 1} fish, {steps} iterations, "
                        "per-iteration launches; compensated float32 lane sums + binary64 block "
                        "combine vs float32 trees + float32 atomicAdd",
            "n_fish": n, "iterations": steps}
-    recs = {}
     for name, mode in (("compensated", fsb.FSB_REDUCE_COMPENSATED),
                        ("naive_f32_atomics", fsb.FSB_REDUCE_NAIVE_F32)):
-        cfg = fsb.FsbConfig(n_fish=n, seed=0, reduce_mode=mode, history_len=steps)
+        cfg = fsb.FsbConfig(n_fish=n, seed=0, reduce_mode=mode, history_len=1)
         sch = fsb.School(cfg)
+        first, exact = checked_iterations(sch, checked_steps)
         sch.sync()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -180,34 +210,76 @@ def precision_form(n: int, steps: int, oracle_steps: int):
         sch.sync()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        hist = sch.history(0, steps)
-        final = sch.state()
+        _, got = sch.barycentre()
+        ref, den, m = column_reference(sch)
+        last_exact = bool(sch.max_delta() == m)
         sch.close()
         del sch
         torch.cuda.empty_cache()
-        w = final["w"].astype(np.float64)
-        ref = np.array([w.sum(), (w * final["x"]).sum(), (w * final["y"]).sum()])
-        den = np.array([w.sum(), np.abs(w * final["x"]).sum(), np.abs(w * final["y"]).sum()])
-        got = np.array([hist["sum_w"][-1], hist["sum_wx"][-1], hist["sum_wy"][-1]])
-        recs[name] = hist
         out[name] = {"value": n * steps / wall, "ms_per_step": wall / steps * 1e3,
-                     "last_iteration_error_vs_columns": (np.abs(got - ref) / den).tolist()}
-    O = default()
-    ocfg = Config(numFish=n, seed=0)
-    school = O.init(ocfg)
-    per_step = {k: [] for k in recs}
-    for t in range(oracle_steps):
-        m, s_ref, a_ref = O.step(ocfg, school, t)
-        for k, hist in recs.items():
-            got = np.array([hist["sum_w"][t], hist["sum_wx"][t], hist["sum_wy"][t]])
-            per_step[k].append({"iteration": t, "max_exact": bool(hist["max_delta"][t] == m),
-                                "error": (np.abs(got - s_ref) / a_ref).tolist()})
-    del school
-    for k in recs:
-        out[k]["error_vs_oracle"] = per_step[k]
-        out[k]["max_error_vs_oracle"] = max(max(e["error"]) for e in per_step[k])
+                     "first_iterations_error": first,
+                     "last_iteration_error": (np.abs(np.asarray(got) - ref) / den).tolist(),
+                     "max_exact": exact and last_exact,
+                     "max_error": max(max(max(e) for e in first),
+                                      float((np.abs(np.asarray(got) - ref) / den).max()))}
     out["error_definition"] = ("|got - ref| / sum|terms| per sum (sum w, sum w*x, sum w*y); "
-                               "ref = oracle binary64 Neumaier sums of exact products")
+                               "ref = binary64 sums of the iteration's columns (exact products)")
+    return out
+
+
+def ablation_form(sizes, checked_steps: int, budget_s: float = 0.5):
+    """Construct ablation (Sec. 2.3.2, Experiment 3: reduction clause vs
+    critical section) on the plain path: the compensated tree, float32 trees
+    with one atomic per block, and the critical mode's one atomic per fish for
+    the max and the three sums.  Per school size: time per iteration, the two
+    passes' event-timed durations, and the first iterations' errors against
+    binary64 sums of their columns (the max must be exact in every mode)."""
+    import torch
+
+    import paper_2507_20173_amd as fsb
+
+    modes = (("tree_compensated", fsb.FSB_REDUCE_COMPENSATED),
+             ("tree_f32_block_atomics", fsb.FSB_REDUCE_NAIVE_F32),
+             ("critical_f32_fish_atomics", fsb.FSB_REDUCE_CRITICAL_F32))
+    out = {"workload": "construct ablation: one school, per-iteration launches, seed 0; "
+                       "the three reductions of the school max and the barycentre sums",
+           "error_definition": "max over the first iterations of |got - ref| / sum|terms| "
+                               "(sum w, sum w*x, sum w*y); ref = binary64 sums of the columns"}
+    for n in sizes:
+        row = {}
+        for name, mode in modes:
+            sch = fsb.School(fsb.FsbConfig(n_fish=n, seed=0, reduce_mode=mode, history_len=1))
+            errs, exact = checked_iterations(sch, checked_steps)
+            sch.sync()
+            t0 = time.perf_counter()
+            sch.step()
+            sch.sync()
+            one = time.perf_counter() - t0
+            steps = int(min(200, max(3, budget_s / max(one, 1e-6))))
+            fsb.fsb_profile_enable(sch.h, 1)
+            fsb.fsb_kernel_times(sch.h)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sch.run(steps)
+            sch.sync()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            counts, ms = fsb.fsb_kernel_times(sch.h)
+            sch.close()
+            del sch
+            torch.cuda.empty_cache()
+            per = {k: ms[kind] / max(int(counts[kind]), 1) * 1e3
+                   for k, kind in (("swim_us", fsb.FSB_KERNEL_SWIM_EVAL),
+                                   ("feed_us", fsb.FSB_KERNEL_FEED_BARY))}
+            row[name] = {"iterations": steps, "value": n * steps / wall,
+                         "ms_per_step": wall / steps * 1e3, **per,
+                         "max_exact": exact, "max_error": max(max(e) for e in errs)}
+        base = row["tree_compensated"]["ms_per_step"]
+        for name in row:
+            row[name]["slowdown_vs_tree"] = row[name]["ms_per_step"] / base
+        out[f"n={n}"] = row
+        log(f"ablation n={n}: " + ", ".join(f"{k} {v['ms_per_step']:.4f} ms"
+                                            for k, v in row.items()))
     return out
 
 
@@ -374,15 +446,18 @@ def main() -> int:
     ap.add_argument("--n-fish", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-only", action="store_true", help="skip the other forms")
-    ap.add_argument("--forms", default="fused,precision,batched",
+    ap.add_argument("--forms", default="fused,precision,batched,ablation",
                     help="comma list of the forms to measure beside the headline")
     ap.add_argument("--fused-steps", type=int, default=2000)
     ap.add_argument("--precision-steps", type=int, default=200)
-    ap.add_argument("--precision-oracle-steps", type=int, default=3)
+    ap.add_argument("--precision-checked-steps", type=int, default=3)
     ap.add_argument("--schools", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--autotune-steps", type=int, default=16)
     ap.add_argument("--baseline-schools", type=int, default=64)
+    ap.add_argument("--ablation-sizes", default="10000,1048576,16777216",
+                    help="school sizes of the construct ablation")
+    ap.add_argument("--ablation-checked-steps", type=int, default=2)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run known-size device copies first (for counter scaling)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -445,10 +520,13 @@ def main() -> int:
             f"persistent form on the headline school (N=2^24, {args.steps} iterations)")
     if "precision" in forms:
         line["forms"]["precision_cfg3"] = precision_form(1 << 27, args.precision_steps,
-                                                         args.precision_oracle_steps)
+                                                         args.precision_checked_steps)
     if "batched" in forms:
         line["forms"]["batched_cfg5"] = batched_form(args.schools, args.batch_steps,
                                                      args.autotune_steps, args.baseline_schools)
+    if "ablation" in forms:
+        line["forms"]["construct_ablation"] = ablation_form(
+            [int(v) for v in args.ablation_sizes.split(",")], args.ablation_checked_steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(line), flush=True)

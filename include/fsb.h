@@ -68,9 +68,17 @@ extern "C" {
 #define FSB_ERR_STATE (-4)       /* call not valid in the handle's state   */
 #define FSB_ERR_DEVICE (-5)      /* a kernel reported a failure (barrier timeout) */
 
-/* fsb_config.reduce_mode: how the barycentre sums are reduced. */
+/* fsb_config.reduce_mode: how the school max and the barycentre sums are
+ * reduced.  The max is exact in every mode (it does not depend on order). */
 #define FSB_REDUCE_COMPENSATED 0u /* per-lane compensated (TwoSum) float32, binary64 cross-block combine, fixed order */
 #define FSB_REDUCE_NAIVE_F32 1u   /* float32 block trees + float32 atomicAdd (accuracy baseline) */
+#define FSB_REDUCE_CRITICAL_F32 2u /* no tree: every fish updates one shared max word and three
+                                      shared float32 sums with its own device-scope atomic, the GPU
+                                      counterpart of the critical-section construct of Sec. 2.3.2
+                                      (Experiment 3).  An ablation baseline: plain iterations only
+                                      (fsb_step, fsb_step_displaced, FSB_RUN_PLAIN); the persistent
+                                      modes and batches return FSB_ERR_UNSUPPORTED.  The sums are
+                                      not deterministic (atomic order). */
 
 /* fsb_run modes. */
 #define FSB_RUN_PLAIN 0u      /* one fsb_step (two kernels) per iteration */
@@ -171,7 +179,8 @@ int fsb_step(fsb_school *h);
  * the FSB_RUN_FUSED* modes run them in one persistent launch with a grid
  * barrier per iteration.  Both give bit-identical columns and maxima (the sums agree to
  * rounding; each mode is deterministic).  Asynchronous; FSB_ERR_UNSUPPORTED
- * if the fused grid cannot be co-resident. */
+ * if the fused grid cannot be co-resident, or for a fused mode under
+ * FSB_REDUCE_CRITICAL_F32. */
 int fsb_run(fsb_school *h, uint64_t n_steps, uint32_t mode);
 
 /* Test hook: one iteration with the displacements dx[n_fish], dy[n_fish]
@@ -230,8 +239,9 @@ int fsb_batch_workspace_bytes(const fsb_config *common, uint32_t n_schools,
 
 /* Initialise every school (Sec. 2.1.1 draws, per-school key) and return a
  * handle at iteration 0 with the default tuning (1024 threads, 8 fish per
- * lane, 100 iterations per launch, variant chosen by the library).  Uploads the school tables (synchronous
- * copies), then enqueues the init kernel on `stream`. */
+ * lane, 100 iterations per launch, variant chosen by the library).  Uploads
+ * the school tables (synchronous copies), then enqueues the init kernel on
+ * `stream`.  FSB_ERR_UNSUPPORTED for reduce_mode FSB_REDUCE_CRITICAL_F32. */
 int fsb_batch_init(const fsb_config *common, uint32_t n_schools,
                    const uint64_t *starts, const uint64_t *sizes,
                    const uint64_t *seeds, fsb_state packed, uint64_t packed_len,

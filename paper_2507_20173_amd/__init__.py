@@ -15,8 +15,9 @@ import numpy as np
 from . import _lib
 from ._lib import (FSB_KERNEL_FEED_BARY, FSB_KERNEL_FUSED, FSB_KERNEL_INIT,  # noqa: F401
                    FSB_KERNEL_KINDS, FSB_KERNEL_SWIM_EVAL, FSB_REDUCE_COMPENSATED,
-                   FSB_REDUCE_NAIVE_F32, FSB_RUN_FUSED, FSB_RUN_FUSED_LEAN, FSB_RUN_FUSED_PREV,
-                   FSB_RUN_PLAIN, FsbError, check, lib)
+                   FSB_REDUCE_CRITICAL_F32, FSB_REDUCE_NAIVE_F32, FSB_RUN_FUSED,
+                   FSB_RUN_FUSED_LEAN, FSB_RUN_FUSED_PREV, FSB_RUN_PLAIN, FsbError, check,
+                   lib)
 
 RECORD = np.dtype([("sum_w", "<f8"), ("sum_wx", "<f8"), ("sum_wy", "<f8"),
                    ("max_delta", "<f4"), ("step_lo", "<u4")])

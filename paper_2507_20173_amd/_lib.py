@@ -20,6 +20,7 @@ FSB_ERR_DEVICE = -5
 
 FSB_REDUCE_COMPENSATED = 0
 FSB_REDUCE_NAIVE_F32 = 1
+FSB_REDUCE_CRITICAL_F32 = 2
 FSB_RUN_PLAIN = 0
 FSB_RUN_FUSED = 1
 FSB_RUN_FUSED_PREV = 2

@@ -112,7 +112,7 @@ int new_school(const fsb_config* cfg, fsb_state state, void* ws, size_t ws_bytes
 // Write the pending record (iteration pending_t) with a one-block launch.
 int finish_pending(fsb_school* h) {
     if (!h->pending) return FSB_OK;
-    const uint32_t naive = h->cfg.reduce_mode == FSB_REDUCE_NAIVE_F32;
+    const uint32_t naive = h->cfg.reduce_mode != FSB_REDUCE_COMPENSATED;
     FSB_HIP_TRY(launch_combine(h->args, h->pending_t, h->pending_grid, naive, h->stream),
                 "combine launch");
     h->pending = false;
@@ -139,7 +139,8 @@ int do_step(fsb_school* h, const float* dx, const float* dy) {
     s.combine = h->pending ? 1u : 0u;
     s.prev_t = h->pending_t;
     s.prev_grid = h->pending_grid;
-    s.naive = h->cfg.reduce_mode == FSB_REDUCE_NAIVE_F32;
+    s.naive = h->cfg.reduce_mode != FSB_REDUCE_COMPENSATED;
+    s.critical = h->cfg.reduce_mode == FSB_REDUCE_CRITICAL_F32;
     s.dx = dx;
     s.dy = dy;
     int rc = timed(h, FSB_KERNEL_SWIM_EVAL, "swim pass launch",
@@ -169,6 +170,8 @@ bool lean_pays(uint64_t n) { return n * 16ull >= (256ull << 20); }
 // guaranteed co-resident or the launch fails).
 int run_fused(fsb_school* h, uint64_t n_steps, uint32_t mode) {
     if (n_steps == 0) return FSB_OK;
+    if (h->cfg.reduce_mode == FSB_REDUCE_CRITICAL_F32)
+        return fail(FSB_ERR_UNSUPPORTED, "the critical reduction is a plain-path ablation only");
     const uint32_t naive = h->cfg.reduce_mode == FSB_REDUCE_NAIVE_F32;
     if (h->resident[naive] == 0)
         FSB_HIP_TRY(fused_resident_grid(naive, &h->resident[naive]), "occupancy query");

@@ -384,6 +384,8 @@ int fsb_batch_init(const fsb_config* common, uint32_t n_schools, const uint64_t*
                    fsb_batch** out) {
     int rc = check_config(common, false);
     if (rc) return rc;
+    if (common->reduce_mode == FSB_REDUCE_CRITICAL_F32)
+        return fail(FSB_ERR_UNSUPPORTED, "the critical reduction is a plain-path ablation only");
     if (!out) return fail(FSB_ERR_INVALID_ARG, "out is NULL");
     if (!seeds) return fail(FSB_ERR_INVALID_ARG, "seeds is NULL");
     uint64_t cap = 0, total = 0;

@@ -52,7 +52,8 @@ inline int check_config(const fsb_config* c, bool need_fish) {
         return fail(FSB_ERR_INVALID_ARG, "need finite w_init_lo <= w_init_hi");
     if (!(std::isfinite(c->w_min) && std::isfinite(c->w_max) && c->w_min <= c->w_max))
         return fail(FSB_ERR_INVALID_ARG, "need finite w_min <= w_max");
-    if (c->reduce_mode != FSB_REDUCE_COMPENSATED && c->reduce_mode != FSB_REDUCE_NAIVE_F32)
+    if (c->reduce_mode != FSB_REDUCE_COMPENSATED && c->reduce_mode != FSB_REDUCE_NAIVE_F32 &&
+        c->reduce_mode != FSB_REDUCE_CRITICAL_F32)
         return fail(FSB_ERR_INVALID_ARG, "unknown reduce_mode");
     if (c->history_len == 0 || c->history_len > kMaxHistory)
         return fail(FSB_ERR_INVALID_ARG, "history_len must be in [1, 2^24]");

@@ -20,8 +20,9 @@ struct Ctrl {
     uint32_t error;           // kernel-reported failure flags (kErr*)
     uint32_t step;            // batches: next iteration (advanced by each launch)
     uint32_t reserved0;
-    float naive_acc[2][4];    // float32 atomic sums of the naive mode, slot t & 1
-    uint32_t pad[52];
+    float naive_acc[2][4];    // float32 atomic sums of the naive and critical modes, slot t & 1
+    uint32_t crit_max[2];     // critical mode: max |diff| bits by per-fish atomics, slot t & 1
+    uint32_t pad[50];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl is one aligned block");
 
@@ -79,7 +80,8 @@ struct StepArgs {
     uint32_t combine;     // swim pass block 0 first writes the pending record
     uint32_t prev_t;      // iteration whose record is pending
     uint32_t prev_grid;   // blocks that produced its partials
-    uint32_t naive;       // FSB_REDUCE_NAIVE_F32
+    uint32_t naive;       // sums in float32 accumulators (naive or critical mode)
+    uint32_t critical;    // FSB_REDUCE_CRITICAL_F32: one atomic per fish for M and the sums
     const float *dx;      // test hook: displacements instead of draws (or null)
     const float *dy;
 };

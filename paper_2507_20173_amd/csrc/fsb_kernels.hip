@@ -19,6 +19,10 @@
 //              write (x, y, w, prev); grid barrier.  The last sweep writes
 //              (w, cur) instead, leaving the five columns complete.
 //   The record of s is written after the barrier by block s % grid.
+// Critical mode (an ablation of the reduction, plain passes only): every fish
+// folds its |diff| into one shared max word and its three terms into three
+// shared float32 sums with its own device-scope atomic, the way a critical
+// section entered once per fish serialises the update; no tree at all.
 // Records are combined in a fixed order, so every sum is deterministic for a
 // given launch shape.  Each thread handles groups of four consecutive fish
 // (one float4 per column): two Philox calls, for fish pairs 2g and 2g+1.
@@ -89,6 +93,24 @@ __device__ __forceinline__ uint32_t block_max(uint32_t v) {
     uint32_t m = wave_best[0];
     for (int w = 1; w < W; ++w) m = max(m, wave_best[w]);
     return m;
+}
+
+// Critical-mode updates of a shared word by every lane.  The address is
+// hidden from the compiler's uniformity analysis: otherwise it may turn
+// per-lane atomics on one address into a wave reduction followed by a single
+// atomic, which is the tree the critical mode is there to leave out.  The
+// global address space keeps them global (not flat) atomics.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* per_lane(T* p) {
+    auto q = (__attribute__((address_space(1))) T*)p;
+    asm volatile("" : "+v"(q));
+    return q;
+}
+__device__ __forceinline__ void lane_atomic_max(uint32_t* p, uint32_t v) {
+    __hip_atomic_fetch_max(per_lane(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void lane_atomic_add(float* p, float v) {
+    __hip_atomic_fetch_add(per_lane(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------
@@ -190,6 +212,7 @@ __device__ void combine_block(const SchoolArgs& a, uint32_t t, uint32_t grid, ui
         r.max_delta = __uint_as_float(max_bits);
         r.step_lo = t;
         a.hist[t % a.hist_len] = r;
+        a.ctrl->crit_max[t & 1u] = 0u;  // critical mode: slot free for iteration t + 2
     }
     __syncthreads();
 }
@@ -208,9 +231,10 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(SchoolArgs a, uint32_t 
 // kStreamAll streams every column once even four of them cannot fit.
 constexpr int kCached = 0, kStreamW = 1, kStreamAll = 2;
 
-template <bool kInject, int kPolicy>
+template <bool kInject, int kPolicy, bool kCritical>
 __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArgs s) {
     constexpr bool NT = kPolicy == kStreamAll;
+    uint32_t* const crit = &a.ctrl->crit_max[s.t & 1u];
     if (s.combine && blockIdx.x == 0)
         combine_block(a, s.prev_t, s.prev_grid, s.naive, a.ctrl->last_max);
 
@@ -246,7 +270,9 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 lane_of(nc, k) = swim(lane_of(nx, k), lane_of(ny, k), dx[k], dy[k], H);
-                best = max(best, mag_bits(lane_of(C[u], k) - lane_of(nc, k)));
+                const uint32_t d = mag_bits(lane_of(C[u], k) - lane_of(nc, k));
+                if constexpr (kCritical) lane_atomic_max(crit, d);
+                else best = max(best, d);
             }
             stv<NT>(a.x, g, nx);
             stv<NT>(a.y, g, ny);
@@ -267,29 +293,42 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
             float x = a.x[i], y = a.y[i];
             const float c = a.cur[i];
             const float nc = swim(x, y, dx, dy, H);
-            best = max(best, mag_bits(c - nc));
+            const uint32_t d = mag_bits(c - nc);
+            if constexpr (kCritical) lane_atomic_max(crit, d);
+            else best = max(best, d);
             a.x[i] = x;
             a.y[i] = y;
             a.prev[i] = c;
             a.cur[i] = nc;
         }
     }
-    const uint32_t m = block_max(best);
-    if (threadIdx.x == 0) a.blockmax[blockIdx.x] = m;
+    if constexpr (!kCritical) {
+        const uint32_t m = block_max(best);
+        if (threadIdx.x == 0) a.blockmax[blockIdx.x] = m;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Plain feed pass.
 // ---------------------------------------------------------------------------
-template <bool kNaive, int kPolicy>
+// Reduction of the feed pass: compensated tree, naive float32 tree with one
+// atomic per block, or critical (one atomic per fish, max and sums).
+constexpr int kRedCompensated = 0, kRedNaive = 1, kRedCritical = 2;
+
+template <int kRed, int kPolicy>
 __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArgs s) {
     constexpr bool NT = kPolicy == kStreamAll;
     constexpr bool NTW = kPolicy != kCached;
+    constexpr bool kNaive = kRed != kRedCompensated;
     __shared__ uint32_t M_bits;
-    // M = max over the swim pass's block maxima.
+    // M = max over the swim pass's block maxima (critical mode: the shared word).
     uint32_t mb = 0u;
-    for (uint32_t b = threadIdx.x; b < s.swim_grid; b += kBlock) mb = max(mb, a.blockmax[b]);
-    mb = block_max(mb);
+    if constexpr (kRed == kRedCritical) {
+        mb = a.ctrl->crit_max[s.t & 1u];
+    } else {
+        for (uint32_t b = threadIdx.x; b < s.swim_grid; b += kBlock) mb = max(mb, a.blockmax[b]);
+        mb = block_max(mb);
+    }
     if (threadIdx.x == 0) {
         M_bits = mb;
         if (blockIdx.x == 0) a.ctrl->last_max = mb;
@@ -299,6 +338,18 @@ __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArg
 
     const float wmin = a.wmin, wmax = a.wmax;
     LaneSums<kNaive> ls;
+    float* const acc = a.ctrl->naive_acc[s.t & 1u];
+    // One fish's terms: into the lane's sums, or (critical) straight into the
+    // shared float32 sums.
+    auto add = [&](float nw, float x, float y) {
+        if constexpr (kRed == kRedCritical) {
+            lane_atomic_add(acc + 0, nw);
+            lane_atomic_add(acc + 1, nw * x);
+            lane_atomic_add(acc + 2, nw * y);
+        } else {
+            ls.add(nw, x, y);
+        }
+    };
     const uint64_t n4 = a.n >> 2;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t g0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g0 < n4;
@@ -324,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArg
             for (int k = 0; k < 4; ++k) {
                 const float diff = lane_of(P[u], k) - lane_of(C[u], k);
                 lane_of(nw, k) = feed(lane_of(W[u], k), diff, M, wmin, wmax);
-                ls.add(lane_of(nw, k), lane_of(X[u], k), lane_of(Y[u], k));
+                add(lane_of(nw, k), lane_of(X[u], k), lane_of(Y[u], k));
             }
             stv<NTW>(a.w, g, nw);
         }
@@ -335,10 +386,10 @@ __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArg
             const float diff = a.prev[i] - a.cur[i];
             const float nw = feed(a.w[i], diff, M, wmin, wmax);
             a.w[i] = nw;
-            ls.add(nw, a.x[i], a.y[i]);
+            add(nw, a.x[i], a.y[i]);
         }
     }
-    block_sums<kNaive>(a, ls, s.t);
+    if constexpr (kRed != kRedCritical) block_sums<kNaive>(a, ls, s.t);
 }
 
 // ---------------------------------------------------------------------------
@@ -643,21 +694,24 @@ int plain_policy(uint64_t n) {
     return kStreamAll;
 }
 
-template <bool kInject>
+template <bool kInject, bool kCritical>
 const void* swim_fn(int pol) {
     switch (pol) {
-        case kCached: return reinterpret_cast<const void*>(swim_eval_kernel<kInject, kCached>);
-        case kStreamW: return reinterpret_cast<const void*>(swim_eval_kernel<kInject, kStreamW>);
-        default: return reinterpret_cast<const void*>(swim_eval_kernel<kInject, kStreamAll>);
+        case kCached:
+            return reinterpret_cast<const void*>(swim_eval_kernel<kInject, kCached, kCritical>);
+        case kStreamW:
+            return reinterpret_cast<const void*>(swim_eval_kernel<kInject, kStreamW, kCritical>);
+        default:
+            return reinterpret_cast<const void*>(swim_eval_kernel<kInject, kStreamAll, kCritical>);
     }
 }
 
-template <bool kNaive>
+template <int kRed>
 const void* feed_fn(int pol) {
     switch (pol) {
-        case kCached: return reinterpret_cast<const void*>(feed_bary_kernel<kNaive, kCached>);
-        case kStreamW: return reinterpret_cast<const void*>(feed_bary_kernel<kNaive, kStreamW>);
-        default: return reinterpret_cast<const void*>(feed_bary_kernel<kNaive, kStreamAll>);
+        case kCached: return reinterpret_cast<const void*>(feed_bary_kernel<kRed, kCached>);
+        case kStreamW: return reinterpret_cast<const void*>(feed_bary_kernel<kRed, kStreamW>);
+        default: return reinterpret_cast<const void*>(feed_bary_kernel<kRed, kStreamAll>);
     }
 }
 
@@ -671,13 +725,18 @@ hipError_t launch_plain(const void* fn, uint32_t grid, const SchoolArgs& a, cons
 
 hipError_t launch_swim_eval(const SchoolArgs& a, const StepArgs& s, hipStream_t stream) {
     const int pol = plain_policy(a.n);
-    return launch_plain(s.dx ? swim_fn<true>(pol) : swim_fn<false>(pol), s.swim_grid, a, s, stream);
+    const void* fn = s.critical ? (s.dx ? swim_fn<true, true>(pol) : swim_fn<false, true>(pol))
+                                : (s.dx ? swim_fn<true, false>(pol) : swim_fn<false, false>(pol));
+    return launch_plain(fn, s.swim_grid, a, s, stream);
 }
 
 hipError_t launch_feed_bary(const SchoolArgs& a, const StepArgs& s, uint32_t grid,
                             hipStream_t stream) {
     const int pol = plain_policy(a.n);
-    return launch_plain(s.naive ? feed_fn<true>(pol) : feed_fn<false>(pol), grid, a, s, stream);
+    const void* fn = s.critical ? feed_fn<kRedCritical>(pol)
+                     : s.naive  ? feed_fn<kRedNaive>(pol)
+                                : feed_fn<kRedCompensated>(pol);
+    return launch_plain(fn, grid, a, s, stream);
 }
 
 hipError_t launch_combine(const SchoolArgs& a, uint32_t t, uint32_t grid, uint32_t naive,

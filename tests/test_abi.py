@@ -71,7 +71,7 @@ def test_workspace_bytes_pure_host():
     dict(pond_half=0.0), dict(pond_half=float("nan")), dict(pond_half=-1.0),
     dict(swim_step=-0.1), dict(swim_step=float("inf")),
     dict(w_init_lo=2.0, w_init_hi=1.0), dict(w_min=5.0, w_max=4.0),
-    dict(w_max=float("nan")), dict(reduce_mode=7), dict(history_len=0),
+    dict(w_max=float("nan")), dict(reduce_mode=3), dict(reduce_mode=7), dict(history_len=0),
     dict(n_fish=(1 << 40) + 1)])
 def test_bad_config_rejected(bad):
     rc, _ = ws_bytes(cfg(**bad))
@@ -185,5 +185,18 @@ def test_batch_init_rejects_before_any_hip_call():
     rc = L.fsb_batch_init(ctypes.byref(c), 2, st.ctypes.data, sz.ctypes.data, seeds.ctypes.data,
                           cols(), 16, FAKE + (8 << 20), 64, None, ctypes.byref(h))
     assert rc == _lib.FSB_ERR_INVALID_ARG
+    # the critical reduction is a plain-path ablation: batches refuse it
+    crit = cfg(reduce_mode=_lib.FSB_REDUCE_CRITICAL_F32)
+    rc = L.fsb_batch_init(ctypes.byref(crit), 2, st.ctypes.data, sz.ctypes.data,
+                          seeds.ctypes.data, cols(), 16, FAKE + (8 << 20), 1 << 30, None,
+                          ctypes.byref(h))
+    assert rc == _lib.FSB_ERR_UNSUPPORTED
     assert L.fsb_batch_run(None, 1, None) == _lib.FSB_ERR_INVALID_ARG
     assert L.fsb_batch_destroy(None) == _lib.FSB_ERR_INVALID_ARG
+
+
+def test_every_reduce_mode_has_a_workspace():
+    for mode in (_lib.FSB_REDUCE_COMPENSATED, _lib.FSB_REDUCE_NAIVE_F32,
+                 _lib.FSB_REDUCE_CRITICAL_F32):
+        rc, b = ws_bytes(cfg(reduce_mode=mode))
+        assert rc == 0 and b > 0
