@@ -283,11 +283,51 @@ def ablation_form(sizes, checked_steps: int, budget_s: float = 0.5):
     return out
 
 
-def batched_form(n_schools: int, steps: int, probe_steps: int, baseline_schools: int):
+SCHEDULES = (("static", 0, 0), ("dynamic_1", 1, 1), ("dynamic_4", 1, 4), ("dynamic_16", 1, 16),
+             ("dynamic_64", 1, 64), ("guided_1", 2, 1), ("guided_16", 2, 16))
+
+
+def schedule_form(b, tune, steps: int):
+    """Tile schedules of the batched kernel (Sec. 2.3.2, Experiment 2's
+    static / dynamic / guided and chunk sizes) on the same batch and launch
+    shape: one persistent launch of `steps` iterations each, after an
+    identical untimed launch (table upload, graph capture)."""
+    import torch
+
+    import paper_2507_20173_amd as fsb
+
+    out = {}
+    for name, sched, chunk in SCHEDULES:
+        tu = fsb.tuning(tune.block_size, tune.fish_per_thread, steps, tune.blocks_per_cu,
+                        tune.variant, sched, chunk)
+        b.run(steps, tu)
+        b.sync()
+        fsb.fsb_batch_profile_enable(b.h, 1)
+        fsb.fsb_batch_kernel_times(b.h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(steps, tu)
+        b.sync()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        _, ms = fsb.fsb_batch_kernel_times(b.h)
+        fsb.fsb_batch_profile_enable(b.h, 0)
+        out[name] = {"schedule": sched, "chunk_tiles": chunk, "ms_per_step": wall / steps * 1e3,
+                     "kernel_ms_per_step": ms / steps}
+        log(f"schedule {name}: {ms / steps:.3f} ms per iteration")
+    base = out["static"]["kernel_ms_per_step"]
+    for v in out.values():
+        v["relative_to_static"] = v["kernel_ms_per_step"] / base
+    return out
+
+
+def batched_form(n_schools: int, steps: int, probe_steps: int, baseline_schools: int,
+                 schedule_steps: int):
     """4096 independent schools of log-uniform sizes, each its own seed,
     advanced by graph-replayed persistent launches with an autotuned shape;
     against advancing the same schools one by one with per-iteration launches
-    (on the first `baseline_schools` schools)."""
+    (on the first `baseline_schools` schools); then the tile schedules
+    compared on the same batch."""
     import numpy as np
     import torch
 
@@ -316,6 +356,8 @@ def batched_form(n_schools: int, steps: int, probe_steps: int, baseline_schools:
     wall = time.perf_counter() - t0
     launches, ms = fsb.fsb_batch_kernel_times(b.h)
     xy, sums, mx = b.results()
+    fsb.fsb_batch_profile_enable(b.h, 0)
+    schedules = schedule_form(b, tune, schedule_steps) if schedule_steps else None
     b.close()
     del b
     torch.cuda.empty_cache()
@@ -353,6 +395,7 @@ def batched_form(n_schools: int, steps: int, probe_steps: int, baseline_schools:
         "baseline_per_school_plain": {"schools": baseline_schools, "fish": base_fish,
                                       "value": base, "speedup_of_batched": value / base},
         "mean_max_delta_last_iteration": float(np.mean(mx)),
+        "schedules": schedules,
     }
 
 
@@ -455,6 +498,8 @@ def main() -> int:
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--autotune-steps", type=int, default=16)
     ap.add_argument("--baseline-schools", type=int, default=64)
+    ap.add_argument("--schedule-steps", type=int, default=100,
+                    help="iterations per tile schedule compared in the batched form (0 = skip)")
     ap.add_argument("--ablation-sizes", default="10000,1048576,16777216",
                     help="school sizes of the construct ablation")
     ap.add_argument("--ablation-checked-steps", type=int, default=2)
@@ -523,7 +568,8 @@ def main() -> int:
                                                          args.precision_checked_steps)
     if "batched" in forms:
         line["forms"]["batched_cfg5"] = batched_form(args.schools, args.batch_steps,
-                                                     args.autotune_steps, args.baseline_schools)
+                                                     args.autotune_steps, args.baseline_schools,
+                                                     args.schedule_steps)
     if "ablation" in forms:
         line["forms"]["construct_ablation"] = ablation_form(
             [int(v) for v in args.ablation_sizes.split(",")], args.ablation_checked_steps)

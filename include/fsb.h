@@ -124,6 +124,16 @@ typedef struct fsb_record {
 typedef struct fsb_school fsb_school; /* opaque host-side handle */
 typedef struct fsb_batch fsb_batch;   /* opaque host-side handle */
 
+/* fsb_tuning.schedule: how the tiles of a sweep are shared among the
+ * wavefronts of the persistent batched kernel (the GPU counterpart of the
+ * loop schedules of Sec. 2.3.2, Experiment 2).  Results do not depend on it. */
+#define FSB_SCHED_STATIC 0u  /* tile i to wavefront i mod W, the same in every sweep */
+#define FSB_SCHED_DYNAMIC 1u /* chunks of chunk_tiles consecutive tiles, handed out in order
+                                by one device-scope atomic counter per sweep (one atomic per
+                                chunk) */
+#define FSB_SCHED_GUIDED 2u  /* as dynamic, the chunk starting at tile p spanning
+                                max(chunk_tiles, ceil((n_tiles - p) / W)) tiles */
+
 /* Launch shape of the persistent batched kernel. */
 typedef struct fsb_tuning {
     uint32_t block_size;       /* threads per block: 256 or 1024 */
@@ -134,6 +144,9 @@ typedef struct fsb_tuning {
     uint32_t variant;          /* 0 = chosen by the library, FSB_RUN_FUSED_PREV (x, y, w, prev
                                   live: 32 B/fish per iteration) or FSB_RUN_FUSED_LEAN (x, y, w
                                   live, each swim done twice: 24 B/fish) */
+    uint32_t schedule;         /* FSB_SCHED_* */
+    uint32_t chunk_tiles;      /* dynamic: tiles per chunk; guided: smallest chunk; >= 1
+                                  unless the schedule is static (then ignored) */
 } fsb_tuning;
 
 /* ---- errors ------------------------------------------------------------ */
@@ -266,12 +279,14 @@ int fsb_batch_results(fsb_batch *b, double *out_xy, double *out_sums,
  * iteration must still be in the history ring.  Synchronises. */
 int fsb_batch_history(fsb_batch *b, uint64_t step, fsb_record *out);
 
-/* Time candidate tunings (256 or 1024 threads x 4, 8 or 16 fish per lane,
- * then the two variants, then iterations per launch), each on probe_steps
- * real iterations (the schools advance), keep the fastest as the handle's tuning and copy it to
- * *out.  If the environment variable FSB_AUTOTUNE_CACHE names a file, a
- * tuning recorded there for this device and batch shape is reused without
- * probing, and new results are appended.  Synchronises. */
+/* Time candidate tunings, each on probe_steps real iterations (the schools
+ * advance): 256 or 1024 threads x 4, 8 or 16 fish per lane with the variant
+ * the library would pick; then the other variant; then the dynamic (4, 8, 16
+ * and 64 tiles per chunk) and guided (at least 4) schedules against static;
+ * then iterations per launch.  Keeps the fastest as the handle's tuning and
+ * copies it to *out.  If the environment variable FSB_AUTOTUNE_CACHE names a
+ * file, a tuning recorded there for this device and batch shape is reused
+ * without probing, and new results are appended.  Synchronises. */
 int fsb_autotune(fsb_batch *b, uint64_t probe_steps, fsb_tuning *out);
 
 int fsb_batch_get_tuning(const fsb_batch *b, fsb_tuning *out);

@@ -16,8 +16,8 @@ from . import _lib
 from ._lib import (FSB_KERNEL_FEED_BARY, FSB_KERNEL_FUSED, FSB_KERNEL_INIT,  # noqa: F401
                    FSB_KERNEL_KINDS, FSB_KERNEL_SWIM_EVAL, FSB_REDUCE_COMPENSATED,
                    FSB_REDUCE_CRITICAL_F32, FSB_REDUCE_NAIVE_F32, FSB_RUN_FUSED,
-                   FSB_RUN_FUSED_LEAN, FSB_RUN_FUSED_PREV, FSB_RUN_PLAIN, FsbError, check,
-                   lib)
+                   FSB_RUN_FUSED_LEAN, FSB_RUN_FUSED_PREV, FSB_RUN_PLAIN, FSB_SCHED_DYNAMIC,
+                   FSB_SCHED_GUIDED, FSB_SCHED_STATIC, FsbError, check, lib)
 
 RECORD = np.dtype([("sum_w", "<f8"), ("sum_wx", "<f8"), ("sum_wy", "<f8"),
                    ("max_delta", "<f4"), ("step_lo", "<u4")])
@@ -182,8 +182,10 @@ def fsb_batch_init(common: FsbConfig, starts, sizes, seeds, cols: dict, workspac
     return h
 
 
-def tuning(block_size=1024, fish_per_thread=8, steps_per_launch=100, blocks_per_cu=0, variant=0):
-    return _lib.fsb_tuning(block_size, fish_per_thread, steps_per_launch, blocks_per_cu, variant)
+def tuning(block_size=1024, fish_per_thread=8, steps_per_launch=100, blocks_per_cu=0, variant=0,
+           schedule=FSB_SCHED_STATIC, chunk_tiles=0):
+    return _lib.fsb_tuning(block_size, fish_per_thread, steps_per_launch, blocks_per_cu, variant,
+                           schedule, chunk_tiles)
 
 
 def tuning_dict(t: _lib.fsb_tuning) -> dict:

@@ -21,6 +21,9 @@ FSB_ERR_DEVICE = -5
 FSB_REDUCE_COMPENSATED = 0
 FSB_REDUCE_NAIVE_F32 = 1
 FSB_REDUCE_CRITICAL_F32 = 2
+FSB_SCHED_STATIC = 0
+FSB_SCHED_DYNAMIC = 1
+FSB_SCHED_GUIDED = 2
 FSB_RUN_PLAIN = 0
 FSB_RUN_FUSED = 1
 FSB_RUN_FUSED_PREV = 2
@@ -55,7 +58,9 @@ class fsb_record(ctypes.Structure):
 class fsb_tuning(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_uint32), ("fish_per_thread", ctypes.c_uint32),
                 ("steps_per_launch", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
-                ("variant", ctypes.c_uint32)]
+                ("variant", ctypes.c_uint32),
+                ("schedule", ctypes.c_uint32),
+                ("chunk_tiles", ctypes.c_uint32)]
 
 
 class FsbError(RuntimeError):

@@ -2,9 +2,12 @@
 // by one persistent launch of several iterations.
 //
 // Work is cut into tiles: a tile is one wavefront's share of one school
-// (64 lanes x fish_per_lane fish, the last tile of a school ragged).  Tile tl
-// belongs to wavefront tl mod (waves in the grid) for every sweep, so each
-// fish stays with one lane.  Per iteration every tile
+// (64 lanes x fish_per_lane fish, the last tile of a school ragged).  Under
+// the static schedule tile tl belongs to wavefront tl mod (waves in the grid)
+// for every sweep.  The dynamic and guided schedules cut the tile list into
+// chunks (fixed-size, or shrinking with the tiles left) that wavefronts take
+// from a per-sweep atomic counter, one atomic per chunk.  No result depends
+// on which wavefront runs a tile.  Per iteration every tile
 //   - reads its school's M_s (slot s % 3 of the per-school max ring),
 //   - feeds, accumulates compensated lane sums, swims the next iteration,
 //   - reduces over the wave (butterflies, no LDS): lane 0 stores the tile's
@@ -23,6 +26,41 @@ namespace fsb {
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return __builtin_amdgcn_readfirstlane(v);
+}
+
+// ---------------------------------------------------------------------------
+// Tile schedule of one sweep, for one wavefront (all of its lanes call these
+// together).  `end` is the end of the wavefront's current chunk.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t grab_chunk(const BatchArgs& a, uint32_t* queue,
+                                               uint32_t lane, uint32_t& end) {
+    uint32_t c = 0;
+    if (lane == 0) c = __hip_atomic_fetch_add(queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    c = uniform(c);
+    if (c >= a.n_chunks) {
+        end = 0;
+        return a.n_tiles;
+    }
+    end = a.chunk_start[c + 1];
+    return a.chunk_start[c];
+}
+
+__device__ __forceinline__ uint32_t first_tile(const BatchArgs& a, uint32_t* queue,
+                                               uint32_t lane, uint32_t wave, uint32_t& end) {
+    if (a.n_chunks == 0) return wave;
+    return grab_chunk(a, queue, lane, end);
+}
+
+__device__ __forceinline__ uint32_t next_tile(const BatchArgs& a, uint32_t* queue, uint32_t lane,
+                                              uint32_t tl, uint32_t n_waves, uint32_t& end) {
+    if (a.n_chunks == 0) return tl + n_waves;
+    if (tl + 1 < end) return tl + 1;
+    return grab_chunk(a, queue, lane, end);
+}
+
+// Counter of sweep phase p (0 = prologue, k + 1 = sweep k of the launch).
+__device__ __forceinline__ uint32_t* queue_of(const BatchArgs& a, uint32_t p) {
+    return a.queue + (p & 1u) * kLineWords;
 }
 
 // ---------------------------------------------------------------------------
@@ -70,6 +108,7 @@ __global__ void batch_reset_kernel(BatchArgs a) {
         if (i != kSyncPhase) a.sync[i] = 0u;
     for (uint32_t i = tid; i < 3 * a.n_schools; i += nth) a.school_max[i] = 0u;
     for (uint32_t i = tid; i < 8 * a.n_schools; i += nth) a.school_naive[i] = 0.0f;
+    if (tid < 2) a.queue[tid * kLineWords] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -208,7 +247,10 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
 
     {
         uint32_t* next_max = a.school_max + (size_t)(t0 % 3u) * S;
-        for (uint32_t tl = wave; tl < a.n_tiles; tl += n_waves) {
+        uint32_t* const queue = queue_of(a, 0);
+        uint32_t end = 0;
+        for (uint32_t tl = first_tile(a, queue, lane, wave, end); tl < a.n_tiles;
+             tl = next_tile(a, queue, lane, tl, n_waves, end)) {
             const Tile T = a.tiles[tl];
             const uint32_t best = wave_max_u32(tile_prologue<GPL, kNT, kLean>(a, T, t0, lane));
             if (lane == 0) max_agent(next_max + T.school, best);
@@ -220,9 +262,14 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
         const uint32_t s = t0 + k;
         const bool last = k + 1 == a.steps;
         if (k > 0) combine_schools<kNaive>(a, s - 1u, wave, n_waves, lane);
+        // this sweep takes phase k + 1's counter; phase k + 2's (last used
+        // by phase k, which every wavefront has left) is cleared for it
+        uint32_t* const queue = queue_of(a, k + 1u);
+        if (a.n_chunks && blockIdx.x == 0 && threadIdx.x == 0) st_agent(queue_of(a, k), 0u);
         const uint32_t* cur_max = a.school_max + (size_t)(s % 3u) * S;
         uint32_t* next_max = a.school_max + (size_t)((s + 1u) % 3u) * S;
-        uint32_t tl = wave;
+        uint32_t end = 0;
+        uint32_t tl = first_tile(a, queue, lane, wave, end);
         Tile T{};
         uint32_t Mb = 0u;
         if (tl < a.n_tiles) {
@@ -230,7 +277,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
             Mb = ld_agent(cur_max + T.school);
         }
         while (tl < a.n_tiles) {
-            const uint32_t nx = tl + n_waves;
+            const uint32_t nx = next_tile(a, queue, lane, tl, n_waves, end);
             Tile Tn{};
             if (nx < a.n_tiles) Tn = a.tiles[nx];
             float4 X[GPL], Y[GPL], W[GPL], P[GPL];

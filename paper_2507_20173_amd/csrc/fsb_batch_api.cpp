@@ -34,8 +34,11 @@ struct fsb_batch {
     fsb_tuning tuning;
     uint32_t table_fpl;   // fish per lane of the uploaded tile table (0 = none)
     uint32_t n_tiles;
+    // uploaded chunk table: schedule, chunk size, wavefronts, tile table it cuts
+    uint32_t chunk_sched, chunk_tiles, chunk_waves, chunk_fpl;
     hipGraphExec_t graph;
-    uint32_t graph_steps, graph_grid, graph_block, graph_fpl, graph_lean;
+    uint32_t graph_steps, graph_grid, graph_block, graph_fpl, graph_lean, graph_sched,
+        graph_chunks;
     uint32_t profile_every;  // time every n-th launch (0 = off)
     uint64_t launches;
     Timer timer;
@@ -86,6 +89,11 @@ int check_tuning(const fsb_tuning* t) {
     if (t->steps_per_launch == 0) return fail(FSB_ERR_INVALID_ARG, "steps_per_launch must be >= 1");
     if (t->variant != 0 && t->variant != FSB_RUN_FUSED_PREV && t->variant != FSB_RUN_FUSED_LEAN)
         return fail(FSB_ERR_INVALID_ARG, "variant must be 0, FSB_RUN_FUSED_PREV or FSB_RUN_FUSED_LEAN");
+    if (t->schedule != FSB_SCHED_STATIC && t->schedule != FSB_SCHED_DYNAMIC &&
+        t->schedule != FSB_SCHED_GUIDED)
+        return fail(FSB_ERR_INVALID_ARG, "schedule must be FSB_SCHED_STATIC, _DYNAMIC or _GUIDED");
+    if (t->schedule != FSB_SCHED_STATIC && t->chunk_tiles == 0)
+        return fail(FSB_ERR_INVALID_ARG, "chunk_tiles must be >= 1 for a dynamic or guided schedule");
     return FSB_OK;
 }
 
@@ -139,6 +147,43 @@ int upload_tiles(fsb_batch* b, uint32_t fpl) {
     return FSB_OK;
 }
 
+// Chunk table of the dynamic and guided schedules for a grid of `waves`
+// wavefronts (synchronises when it uploads).  The static schedule needs none.
+int upload_chunks(fsb_batch* b, uint32_t waves) {
+    const fsb_tuning& tu = b->tuning;
+    if (tu.schedule == FSB_SCHED_STATIC) {
+        b->args.n_chunks = 0;
+        return FSB_OK;
+    }
+    if (b->chunk_sched == tu.schedule && b->chunk_tiles == tu.chunk_tiles &&
+        b->chunk_waves == waves && b->chunk_fpl == b->table_fpl)
+        return FSB_OK;
+    std::vector<uint32_t> start;
+    const uint64_t n = b->n_tiles;
+    for (uint64_t p = 0; p < n;) {
+        start.push_back((uint32_t)p);
+        uint64_t len = tu.chunk_tiles;
+        if (tu.schedule == FSB_SCHED_GUIDED) {
+            const uint64_t share = (n - p + waves - 1) / waves;
+            if (share > len) len = share;
+        }
+        p = p + len < n ? p + len : n;
+    }
+    start.push_back((uint32_t)n);
+    if (start.size() > (size_t)b->L.tile_cap + 1)
+        return fail(FSB_ERR_INVALID_ARG, "chunk table exceeds its capacity");
+    char* base = static_cast<char*>(b->ws);
+    FSB_HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    FSB_HIP_TRY(hipMemcpy(base + b->L.chunks, start.data(), start.size() * 4, hipMemcpyHostToDevice),
+                "chunk table upload");
+    b->args.n_chunks = (uint32_t)(start.size() - 1);
+    b->chunk_sched = tu.schedule;
+    b->chunk_tiles = tu.chunk_tiles;
+    b->chunk_waves = waves;
+    b->chunk_fpl = b->table_fpl;
+    return FSB_OK;
+}
+
 int grid_for(fsb_batch* b, const fsb_tuning& tu, uint32_t* grid) {
     const uint32_t naive = b->cfg.reduce_mode == FSB_REDUCE_NAIVE_F32;
     uint32_t g = 0;
@@ -183,7 +228,8 @@ int launch_once(fsb_batch* b, uint32_t steps, uint32_t grid) {
 int ensure_graph(fsb_batch* b, uint32_t steps, uint32_t grid) {
     if (b->graph && b->graph_steps == steps && b->graph_grid == grid &&
         b->graph_block == b->tuning.block_size && b->graph_fpl == b->tuning.fish_per_thread &&
-        b->graph_lean == use_lean(b))
+        b->graph_lean == use_lean(b) && b->graph_sched == b->tuning.schedule &&
+        b->graph_chunks == b->args.n_chunks)
         return FSB_OK;
     if (b->graph) {
         (void)hipGraphExecDestroy(b->graph);
@@ -213,6 +259,8 @@ int ensure_graph(fsb_batch* b, uint32_t steps, uint32_t grid) {
     b->graph_block = b->tuning.block_size;
     b->graph_fpl = b->tuning.fish_per_thread;
     b->graph_lean = use_lean(b);
+    b->graph_sched = b->tuning.schedule;
+    b->graph_chunks = b->args.n_chunks;
     return FSB_OK;
 }
 
@@ -237,6 +285,8 @@ int run(fsb_batch* b, uint64_t n_steps) {
     if (rc) return rc;
     uint32_t grid = 0;
     rc = grid_for(b, b->tuning, &grid);
+    if (rc) return rc;
+    rc = upload_chunks(b, grid * (b->tuning.block_size / 64));
     if (rc) return rc;
     const uint64_t K = b->tuning.steps_per_launch < n_steps ? b->tuning.steps_per_launch : n_steps;
     const uint64_t full = n_steps / K, rest = n_steps % K;
@@ -314,8 +364,9 @@ bool cache_lookup(const std::string& key, fsb_tuning* out) {
     while (std::fgets(line, sizeof(line), f)) {
         char k[300];
         fsb_tuning t;
-        if (std::sscanf(line, "%299s %u %u %u %u %u", k, &t.block_size, &t.fish_per_thread,
-                        &t.steps_per_launch, &t.blocks_per_cu, &t.variant) == 6 &&
+        if (std::sscanf(line, "%299s %u %u %u %u %u %u %u", k, &t.block_size, &t.fish_per_thread,
+                        &t.steps_per_launch, &t.blocks_per_cu, &t.variant, &t.schedule,
+                        &t.chunk_tiles) == 8 &&
             key == k && check_tuning(&t) == FSB_OK) {
             *out = t;
             found = true;
@@ -330,8 +381,8 @@ void cache_store(const std::string& key, const fsb_tuning& t) {
     if (!path || !*path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %u %u %u %u %u\n", key.c_str(), t.block_size, t.fish_per_thread,
-                 t.steps_per_launch, t.blocks_per_cu, t.variant);
+    std::fprintf(f, "%s %u %u %u %u %u %u %u\n", key.c_str(), t.block_size, t.fish_per_thread,
+                 t.steps_per_launch, t.blocks_per_cu, t.variant, t.schedule, t.chunk_tiles);
     std::fclose(f);
 }
 
@@ -412,7 +463,7 @@ int fsb_batch_init(const fsb_config* common, uint32_t n_schools, const uint64_t*
     b->ws_bytes = workspace_bytes;
     b->stream = static_cast<hipStream_t>(stream);
     b->L = L;
-    b->tuning = fsb_tuning{1024, 8, 100, 0, 0};
+    b->tuning = fsb_tuning{1024, 8, 100, 0, 0, FSB_SCHED_STATIC, 0};
 
     char* base = static_cast<char*>(workspace);
     BatchArgs& a = b->args;
@@ -440,6 +491,8 @@ int fsb_batch_init(const fsb_config* common, uint32_t n_schools, const uint64_t*
     a.school_naive = reinterpret_cast<float*>(base + L.school_naive);
     a.rec = reinterpret_cast<fsb_record*>(base + L.rec);
     a.hist_len = common->history_len;
+    a.chunk_start = reinterpret_cast<const uint32_t*>(base + L.chunks);
+    a.queue = reinterpret_cast<uint32_t*>(base + L.queue);
 
     auto cleanup = [&](int code) {
         delete b;
@@ -510,9 +563,12 @@ int fsb_autotune(fsb_batch* b, uint64_t probe_steps, fsb_tuning* out) {
     }
     double best_ms = 1e300;
     best = b->tuning;
+    // shapes with the variant the library would pick, then the other variant
+    const uint32_t lib_variant =
+        b->total_fish * 16ull >= (256ull << 20) ? FSB_RUN_FUSED_LEAN : FSB_RUN_FUSED_PREV;
     for (uint32_t block : kBatchBlocks)
         for (uint32_t fpl : kBatchFishPerLane) {
-            fsb_tuning tu{block, fpl, (uint32_t)probe_steps, 0, 0};
+            fsb_tuning tu{block, fpl, (uint32_t)probe_steps, 0, lib_variant, FSB_SCHED_STATIC, 0};
             double ms = 0.0;
             int rc = probe(b, tu, probe_steps, &ms);
             if (rc == FSB_ERR_UNSUPPORTED) continue;
@@ -522,10 +578,29 @@ int fsb_autotune(fsb_batch* b, uint64_t probe_steps, fsb_tuning* out) {
                 best = tu;
             }
         }
-    // both variants for the best shape
-    for (uint32_t v : {(uint32_t)FSB_RUN_FUSED_PREV, (uint32_t)FSB_RUN_FUSED_LEAN}) {
+    {
         fsb_tuning tu = best;
-        tu.variant = v;
+        tu.variant = lib_variant == FSB_RUN_FUSED_LEAN ? FSB_RUN_FUSED_PREV : FSB_RUN_FUSED_LEAN;
+        double ms = 0.0;
+        int rc = probe(b, tu, probe_steps, &ms);
+        if (rc) return rc;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = tu;
+        }
+    }
+    // work-queue schedules against the static one (one tile per chunk is
+    // left out: at CFG5 scale its one atomic per tile saturates the counter)
+    const fsb_tuning queues[5] = {{0, 0, 0, 0, 0, FSB_SCHED_DYNAMIC, 4},
+                                  {0, 0, 0, 0, 0, FSB_SCHED_DYNAMIC, 8},
+                                  {0, 0, 0, 0, 0, FSB_SCHED_DYNAMIC, 16},
+                                  {0, 0, 0, 0, 0, FSB_SCHED_DYNAMIC, 64},
+                                  {0, 0, 0, 0, 0, FSB_SCHED_GUIDED, 4}};
+    const fsb_tuning shape = best;
+    for (const fsb_tuning& q : queues) {
+        fsb_tuning tu = shape;
+        tu.schedule = q.schedule;
+        tu.chunk_tiles = q.chunk_tiles;
         double ms = 0.0;
         int rc = probe(b, tu, probe_steps, &ms);
         if (rc) return rc;

@@ -154,11 +154,19 @@ struct BatchArgs {
     uint32_t hist_len;
     uint32_t steps;                 // iterations per launch
     uint32_t group_size, groups;    // barrier grouping
+    // Tile schedule.  n_chunks == 0: static, tile tl to wavefront tl mod W.
+    // Otherwise wavefronts take chunk c = [chunk_start[c], chunk_start[c+1])
+    // in the order an atomic counter hands them out; the counter of sweep
+    // phase p is queue[(p & 1) * kLineWords].
+    const uint32_t* chunk_start;    // [n_chunks + 1]
+    uint32_t n_chunks;
+    uint32_t* queue;                // two counters, one 256-byte line each
 };
 
 // Workspace of a batch (offsets in bytes).
 struct BatchLayout {
-    size_t ctrl, sync, tile_begin, tiles, tile_part, school_max, school_naive, rec, total;
+    size_t ctrl, sync, tile_begin, tiles, tile_part, school_max, school_naive, rec, chunks,
+        queue, total;
     uint32_t tile_cap;
 };
 
@@ -174,7 +182,9 @@ inline BatchLayout batch_layout(uint32_t n_schools, uint64_t tile_cap, uint32_t 
     L.school_max = align_up(L.tile_part + 2 * 3 * tile_cap * sizeof(double), kAlign);
     L.school_naive = align_up(L.school_max + 3 * S * 4, kAlign);
     L.rec = align_up(L.school_naive + 2 * S * 4 * sizeof(float), kAlign);
-    L.total = align_up(L.rec + (size_t)history_len * S * sizeof(fsb_record), kAlign);
+    L.chunks = align_up(L.rec + (size_t)history_len * S * sizeof(fsb_record), kAlign);
+    L.queue = align_up(L.chunks + (tile_cap + 1) * sizeof(uint32_t), kAlign);
+    L.total = align_up(L.queue + 2 * kLineWords * sizeof(uint32_t), kAlign);
     return L;
 }
 

@@ -97,6 +97,79 @@ def test_every_launch_shape_gives_identical_state(torch_cuda, block, fpl, varian
     ref.close()
 
 
+SCHEDULES = [(fsb.FSB_SCHED_DYNAMIC, 1), (fsb.FSB_SCHED_DYNAMIC, 3), (fsb.FSB_SCHED_DYNAMIC, 64),
+             (fsb.FSB_SCHED_GUIDED, 1), (fsb.FSB_SCHED_GUIDED, 8)]
+
+
+@pytest.mark.parametrize("variant", [fsb.FSB_RUN_FUSED_PREV, fsb.FSB_RUN_FUSED_LEAN],
+                         ids=["prev", "lean"])
+@pytest.mark.parametrize("sched,chunk", SCHEDULES, ids=[f"s{s}c{c}" for s, c in SCHEDULES])
+def test_work_queue_schedules_give_identical_results(torch_cuda, sched, chunk, variant):
+    """Dynamic and guided schedules move tiles between wavefronts from sweep to
+    sweep; with the same tiles (same fish per lane) the columns, maxima and
+    even the sums (tile partials are combined in tile order) are identical
+    to the static schedule's, bit for bit."""
+    announce(f"schedule {sched} chunk {chunk} variant {variant}")
+    common = fsb.FsbConfig(n_fish=0, history_len=5)
+    seeds = list(range(len(SIZES)))
+    ref = fsb.Batch(common, SIZES, seeds)
+    ref.run(5, fsb.tuning(1024, 4, 5, variant=variant))
+    ref_state = [ref.school_state(i) for i in range(ref.n)]
+    _, ref_sums, ref_max = ref.results()
+    ref.close()
+    for block, k_launch in ((256, 1), (1024, 2), (1024, 5)):
+        b = fsb.Batch(common, SIZES, seeds)
+        b.run(5, fsb.tuning(block, 4, k_launch, variant=variant, schedule=sched, chunk_tiles=chunk))
+        _, sums, mx = b.results()
+        assert np.array_equal(mx, ref_max)
+        assert np.array_equal(sums.view(np.uint64), ref_sums.view(np.uint64)), (sums, ref_sums)
+        for i in range(b.n):
+            got = b.school_state(i)
+            for k in got:
+                assert np.array_equal(got[k].view(np.uint32), ref_state[i][k].view(np.uint32)), (
+                    f"school {i} column {k}, block={block} steps/launch={k_launch}")
+        b.close()
+
+
+def test_dynamic_schedule_matches_oracle(torch_cuda, O):
+    announce("dynamic schedule vs oracle")
+    common = fsb.FsbConfig(n_fish=0, history_len=6)
+    seeds = [29 * i + 1 for i in range(len(SIZES))]
+    b = fsb.Batch(common, SIZES, seeds)
+    b.run(6, fsb.tuning(256, 8, 3, schedule=fsb.FSB_SCHED_DYNAMIC, chunk_tiles=1))
+    check_batch_against_oracle(O, b, 6, what="dynamic")
+    b.close()
+
+
+def test_cfg5_schedules_agree(torch_cuda):
+    """The full 4096-school shape for 3 iterations under the static, dynamic
+    and guided schedules: identical maxima, sums and columns (columns compared
+    on the device)."""
+    import torch
+    sizes = log_uniform_school_sizes(4096)
+    seeds = school_seeds(4096)
+    common = fsb.FsbConfig(n_fish=0)
+    announce(f"cfg5 schedules, {int(sizes.sum())} fish")
+    ref = fsb.Batch(common, sizes, seeds)
+    ref.run(3, fsb.tuning(1024, 16, 3))
+    _, ref_sums, ref_max = ref.results()
+    ref_cols = {k: v.clone() for k, v in ref.cols.items()}
+    ref.close()
+    del ref
+    for sched, chunk in ((fsb.FSB_SCHED_DYNAMIC, 16), (fsb.FSB_SCHED_GUIDED, 4)):
+        b = fsb.Batch(common, sizes, seeds)
+        b.run(3, fsb.tuning(1024, 16, 3, schedule=sched, chunk_tiles=chunk))
+        _, sums, mx = b.results()
+        assert np.array_equal(mx, ref_max)
+        assert np.array_equal(sums.view(np.uint64), ref_sums.view(np.uint64))
+        for k, v in b.cols.items():
+            assert torch.equal(v.view(torch.int32), ref_cols[k].view(torch.int32)), (sched, k)
+        b.close()
+        del b
+    del ref_cols
+    torch.cuda.empty_cache()
+
+
 def test_gaps_between_schools_untouched(torch_cuda):
     announce("gaps")
     sizes = [5, 9, 1, 130]
@@ -165,6 +238,8 @@ def test_autotune_and_cache(torch_cuda, tmp_path):
         assert d["block_size"] in (256, 1024) and d["fish_per_thread"] in (4, 8, 16)
         assert d["steps_per_launch"] >= 1
         assert d["variant"] in (fsb.FSB_RUN_FUSED_PREV, fsb.FSB_RUN_FUSED_LEAN)
+        assert d["schedule"] in (fsb.FSB_SCHED_STATIC, fsb.FSB_SCHED_DYNAMIC,
+                                 fsb.FSB_SCHED_GUIDED)
         assert b.t > t0
         assert fsb.tuning_dict(b.tuning) == d
         assert cache.exists() and cache.read_text().strip()
@@ -185,4 +260,9 @@ def test_batch_errors(torch_cuda):
     assert e.value.code == fsb._lib.FSB_ERR_STATE
     with pytest.raises(fsb.FsbError):
         b.run(1, fsb.tuning(333, 8, 1))
+    with pytest.raises(fsb.FsbError):
+        b.run(1, fsb.tuning(1024, 8, 1, schedule=3, chunk_tiles=1))
+    with pytest.raises(fsb.FsbError):
+        b.run(1, fsb.tuning(1024, 8, 1, schedule=fsb.FSB_SCHED_DYNAMIC, chunk_tiles=0))
+    b.run(1, fsb.tuning(1024, 8, 1, schedule=fsb.FSB_SCHED_STATIC, chunk_tiles=0))
     b.close()
