@@ -283,7 +283,8 @@ def ablation_form(sizes, checked_steps: int, budget_s: float = 0.5):
     return out
 
 
-SCHEDULES = (("static", 0, 0), ("dynamic_1", 1, 1), ("dynamic_4", 1, 4), ("dynamic_16", 1, 16),
+SCHEDULES = (("static", 0, 0), ("static_1", 0, 1), ("static_4", 0, 4), ("static_16", 0, 16),
+             ("dynamic_1", 1, 1), ("dynamic_4", 1, 4), ("dynamic_16", 1, 16),
              ("dynamic_64", 1, 64), ("guided_1", 2, 1), ("guided_16", 2, 16))
 
 

@@ -127,7 +127,9 @@ typedef struct fsb_batch fsb_batch;   /* opaque host-side handle */
 /* fsb_tuning.schedule: how the tiles of a sweep are shared among the
  * wavefronts of the persistent batched kernel (the GPU counterpart of the
  * loop schedules of Sec. 2.3.2, Experiment 2).  Results do not depend on it. */
-#define FSB_SCHED_STATIC 0u  /* tile i to wavefront i mod W, the same in every sweep */
+#define FSB_SCHED_STATIC 0u  /* chunks of chunk_tiles consecutive tiles dealt to the W
+                                wavefronts round robin, the same in every sweep; chunk_tiles
+                                0 = one chunk of ceil(n_tiles / W) tiles per wavefront */
 #define FSB_SCHED_DYNAMIC 1u /* chunks of chunk_tiles consecutive tiles, handed out in order
                                 by one device-scope atomic counter per sweep (one atomic per
                                 chunk) */
@@ -145,8 +147,8 @@ typedef struct fsb_tuning {
                                   live: 32 B/fish per iteration) or FSB_RUN_FUSED_LEAN (x, y, w
                                   live, each swim done twice: 24 B/fish) */
     uint32_t schedule;         /* FSB_SCHED_* */
-    uint32_t chunk_tiles;      /* dynamic: tiles per chunk; guided: smallest chunk; >= 1
-                                  unless the schedule is static (then ignored) */
+    uint32_t chunk_tiles;      /* static: tiles per chunk (0 = n_tiles / W); dynamic: tiles
+                                  per chunk, >= 1; guided: smallest chunk, >= 1 */
 } fsb_tuning;
 
 /* ---- errors ------------------------------------------------------------ */

@@ -2,17 +2,19 @@
 // by one persistent launch of several iterations.
 //
 // Work is cut into tiles: a tile is one wavefront's share of one school
-// (64 lanes x fish_per_lane fish, the last tile of a school ragged).  Under
-// the static schedule tile tl belongs to wavefront tl mod (waves in the grid)
-// for every sweep.  The dynamic and guided schedules cut the tile list into
-// chunks (fixed-size, or shrinking with the tiles left) that wavefronts take
-// from a per-sweep atomic counter, one atomic per chunk.  No result depends
-// on which wavefront runs a tile.  Per iteration every tile
+// (64 lanes x fish_per_lane fish, the last tile of a school ragged).  The
+// static schedule deals chunks of consecutive tiles to the wavefronts round
+// robin, the same way in every sweep (one chunk per wavefront when the chunk
+// size is n_tiles / W).  The dynamic and guided schedules cut the tile list
+// into chunks (fixed-size, or shrinking with the tiles left) that wavefronts
+// take from a per-sweep atomic counter, one atomic per chunk.  No result
+// depends on which wavefront runs a tile.  Per iteration every tile
 //   - reads its school's M_s (slot s % 3 of the per-school max ring),
 //   - feeds, accumulates compensated lane sums, swims the next iteration,
 //   - reduces over the wave (butterflies, no LDS): lane 0 stores the tile's
-//     binary64 partials and folds the tile max into its school's next slot
-//     with one device-scope atomic max.
+//     binary64 partials; the max of a run of consecutive tiles of one school
+//     is folded into the school's next slot with one device-scope atomic max
+//     when the run ends, and M of a school is loaded once per run.
 // The grid barrier (shared with the single-school persistent kernel) then
 // separates iterations.  After it, one wavefront per school folds that
 // school's tile partials in tile order (deterministic) into the school's
@@ -30,8 +32,14 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) {
 
 // ---------------------------------------------------------------------------
 // Tile schedule of one sweep, for one wavefront (all of its lanes call these
-// together).  `end` is the end of the wavefront's current chunk.
+// together; every value here is uniform across the wavefront).
 // ---------------------------------------------------------------------------
+struct Walk {
+    uint32_t tl;     // current tile; n_tiles once this wavefront's share is done
+    uint32_t end;    // end of the current chunk
+    uint32_t chunk;  // static schedule: index of the current chunk
+};
+
 __device__ __forceinline__ uint32_t grab_chunk(const BatchArgs& a, uint32_t* queue,
                                                uint32_t lane, uint32_t& end) {
     uint32_t c = 0;
@@ -45,17 +53,38 @@ __device__ __forceinline__ uint32_t grab_chunk(const BatchArgs& a, uint32_t* que
     return a.chunk_start[c];
 }
 
-__device__ __forceinline__ uint32_t first_tile(const BatchArgs& a, uint32_t* queue,
-                                               uint32_t lane, uint32_t wave, uint32_t& end) {
-    if (a.n_chunks == 0) return wave;
-    return grab_chunk(a, queue, lane, end);
+__device__ __forceinline__ void static_chunk_at(const BatchArgs& a, Walk& w) {
+    const uint64_t b = (uint64_t)w.chunk * a.static_chunk;
+    if (b >= a.n_tiles) {
+        w.tl = a.n_tiles;
+        w.end = 0;
+        return;
+    }
+    const uint64_t e = b + a.static_chunk;
+    w.tl = (uint32_t)b;
+    w.end = e < a.n_tiles ? (uint32_t)e : a.n_tiles;
 }
 
-__device__ __forceinline__ uint32_t next_tile(const BatchArgs& a, uint32_t* queue, uint32_t lane,
-                                              uint32_t tl, uint32_t n_waves, uint32_t& end) {
-    if (a.n_chunks == 0) return tl + n_waves;
-    if (tl + 1 < end) return tl + 1;
-    return grab_chunk(a, queue, lane, end);
+__device__ __forceinline__ Walk first_tile(const BatchArgs& a, uint32_t* queue, uint32_t lane,
+                                           uint32_t wave) {
+    Walk w{a.n_tiles, 0u, wave};
+    if (a.n_chunks) w.tl = grab_chunk(a, queue, lane, w.end);
+    else static_chunk_at(a, w);
+    return w;
+}
+
+__device__ __forceinline__ void next_tile(const BatchArgs& a, uint32_t* queue, uint32_t lane,
+                                          uint32_t n_waves, Walk& w) {
+    if (w.tl + 1 < w.end) {
+        ++w.tl;
+        return;
+    }
+    if (a.n_chunks) {
+        w.tl = grab_chunk(a, queue, lane, w.end);
+        return;
+    }
+    w.chunk += n_waves;
+    static_chunk_at(a, w);
 }
 
 // Counter of sweep phase p (0 = prologue, k + 1 = sweep k of the launch).
@@ -124,7 +153,23 @@ __device__ void combine_schools(const BatchArgs& a, uint32_t s, uint32_t wave, u
         if constexpr (!kNaive) {
             const uint32_t tb = a.tile_begin[c], te = a.tile_begin[c + 1];
             const double* part = a.tile_part + (size_t)(s & 1u) * 3 * a.tile_cap;
-            for (uint32_t i = tb + lane; i < te; i += kWave)
+            // Lane l adds tiles tb + l, tb + l + 64, ... in that order.  Up to
+            // kBatchLoads of them are loaded before any is added, so a large
+            // school's fold waits on memory once per batch, not once per tile.
+            constexpr uint32_t kBatchLoads = 8;
+            uint32_t i = tb + lane;
+            for (; i + (kBatchLoads - 1) * kWave < te; i += kBatchLoads * kWave) {
+                double v[3][kBatchLoads];
+#pragma unroll
+                for (uint32_t j = 0; j < kBatchLoads; ++j)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) v[k][j] = part[(size_t)k * a.tile_cap + i + j * kWave];
+#pragma unroll
+                for (uint32_t j = 0; j < kBatchLoads; ++j)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) acc[k] += v[k][j];
+            }
+            for (; i < te; i += kWave)
                 for (int k = 0; k < 3; ++k) acc[k] += part[(size_t)k * a.tile_cap + i];
             for (int k = 0; k < 3; ++k) acc[k] = wave_sum_f64(acc[k]);
         }
@@ -248,13 +293,20 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
     {
         uint32_t* next_max = a.school_max + (size_t)(t0 % 3u) * S;
         uint32_t* const queue = queue_of(a, 0);
-        uint32_t end = 0;
-        for (uint32_t tl = first_tile(a, queue, lane, wave, end); tl < a.n_tiles;
-             tl = next_tile(a, queue, lane, tl, n_waves, end)) {
-            const Tile T = a.tiles[tl];
-            const uint32_t best = wave_max_u32(tile_prologue<GPL, kNT, kLean>(a, T, t0, lane));
-            if (lane == 0) max_agent(next_max + T.school, best);
+        uint32_t best = 0u, run_school = 0u;
+        for (Walk w = first_tile(a, queue, lane, wave); w.tl < a.n_tiles;
+             next_tile(a, queue, lane, n_waves, w)) {
+            const Tile T = a.tiles[w.tl];
+            if (T.school != run_school) {  // a run of one school's tiles ends
+                best = wave_max_u32(best);
+                if (lane == 0 && best) max_agent(next_max + run_school, best);
+                best = 0u;
+                run_school = T.school;
+            }
+            best = max(best, tile_prologue<GPL, kNT, kLean>(a, T, t0, lane));
         }
+        best = wave_max_u32(best);
+        if (lane == 0 && best) max_agent(next_max + run_school, best);
     }
     if (!barrier_max(bar, 0u, 0u, phase, &M_sh)) return;
 
@@ -268,16 +320,21 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
         if (a.n_chunks && blockIdx.x == 0 && threadIdx.x == 0) st_agent(queue_of(a, k), 0u);
         const uint32_t* cur_max = a.school_max + (size_t)(s % 3u) * S;
         uint32_t* next_max = a.school_max + (size_t)((s + 1u) % 3u) * S;
-        uint32_t end = 0;
-        uint32_t tl = first_tile(a, queue, lane, wave, end);
+        // M of a school is final once the barrier is passed and nobody writes
+        // its slot during this sweep, so a plain load is coherent here; it is
+        // loaded once per run of consecutive tiles of one school.
+        Walk w = first_tile(a, queue, lane, wave);
         Tile T{};
         uint32_t Mb = 0u;
-        if (tl < a.n_tiles) {
-            T = a.tiles[tl];
-            Mb = ld_agent(cur_max + T.school);
+        if (w.tl < a.n_tiles) {
+            T = a.tiles[w.tl];
+            Mb = cur_max[T.school];
         }
-        while (tl < a.n_tiles) {
-            const uint32_t nx = next_tile(a, queue, lane, tl, n_waves, end);
+        uint32_t best = 0u;  // lane max over the current run of one school's tiles
+        while (w.tl < a.n_tiles) {
+            Walk wn = w;
+            next_tile(a, queue, lane, n_waves, wn);
+            const uint32_t nx = wn.tl;
             Tile Tn{};
             if (nx < a.n_tiles) Tn = a.tiles[nx];
             float4 X[GPL], Y[GPL], W[GPL], P[GPL];
@@ -291,10 +348,10 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
                     if constexpr (!kLean) P[q] = ldv<kNT>(a.prev, T.col4 + j);
                 }
             }
-            const uint32_t Mn = nx < a.n_tiles ? ld_agent(cur_max + Tn.school) : 0u;
+            const bool run_ends = nx >= a.n_tiles || Tn.school != T.school;
+            const uint32_t Mn = nx >= a.n_tiles ? 0u : run_ends ? cur_max[Tn.school] : Mb;
             const float M = __uint_as_float(Mb);
             LaneSums<kNaive> ls;
-            uint32_t best = 0u;
 #pragma unroll
             for (int q = 0; q < GPL; ++q) {
                 const uint32_t j = lane + q * kWave;
@@ -381,14 +438,15 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
                     }
                 }
             }
-            tile_sums<kNaive>(a, ls, s, tl, T.school, lane);
-            if (!last) {
+            tile_sums<kNaive>(a, ls, s, w.tl, T.school, lane);
+            if (!last && run_ends) {
                 best = wave_max_u32(best);
-                if (lane == 0) max_agent(next_max + T.school, best);
+                if (lane == 0 && best) max_agent(next_max + T.school, best);
+                best = 0u;
             }
             T = Tn;
             Mb = Mn;
-            tl = nx;
+            w = wn;
         }
         if (!barrier_max(bar, 0u, 0u, phase, &M_sh)) return;
     }

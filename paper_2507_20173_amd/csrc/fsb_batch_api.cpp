@@ -38,7 +38,7 @@ struct fsb_batch {
     uint32_t chunk_sched, chunk_tiles, chunk_waves, chunk_fpl;
     hipGraphExec_t graph;
     uint32_t graph_steps, graph_grid, graph_block, graph_fpl, graph_lean, graph_sched,
-        graph_chunks;
+        graph_chunks, graph_static;
     uint32_t profile_every;  // time every n-th launch (0 = off)
     uint64_t launches;
     Timer timer;
@@ -147,12 +147,16 @@ int upload_tiles(fsb_batch* b, uint32_t fpl) {
     return FSB_OK;
 }
 
-// Chunk table of the dynamic and guided schedules for a grid of `waves`
-// wavefronts (synchronises when it uploads).  The static schedule needs none.
-int upload_chunks(fsb_batch* b, uint32_t waves) {
+// Schedule of a grid of `waves` wavefronts: the static chunk size, or the
+// chunk table of the dynamic and guided schedules (synchronises when it
+// uploads one).
+int set_schedule(fsb_batch* b, uint32_t waves) {
     const fsb_tuning& tu = b->tuning;
     if (tu.schedule == FSB_SCHED_STATIC) {
         b->args.n_chunks = 0;
+        b->args.static_chunk =
+            tu.chunk_tiles ? tu.chunk_tiles : (b->n_tiles + waves - 1) / waves;
+        if (b->args.static_chunk == 0) b->args.static_chunk = 1;
         return FSB_OK;
     }
     if (b->chunk_sched == tu.schedule && b->chunk_tiles == tu.chunk_tiles &&
@@ -229,7 +233,7 @@ int ensure_graph(fsb_batch* b, uint32_t steps, uint32_t grid) {
     if (b->graph && b->graph_steps == steps && b->graph_grid == grid &&
         b->graph_block == b->tuning.block_size && b->graph_fpl == b->tuning.fish_per_thread &&
         b->graph_lean == use_lean(b) && b->graph_sched == b->tuning.schedule &&
-        b->graph_chunks == b->args.n_chunks)
+        b->graph_chunks == b->args.n_chunks && b->graph_static == b->args.static_chunk)
         return FSB_OK;
     if (b->graph) {
         (void)hipGraphExecDestroy(b->graph);
@@ -261,6 +265,7 @@ int ensure_graph(fsb_batch* b, uint32_t steps, uint32_t grid) {
     b->graph_lean = use_lean(b);
     b->graph_sched = b->tuning.schedule;
     b->graph_chunks = b->args.n_chunks;
+    b->graph_static = b->args.static_chunk;
     return FSB_OK;
 }
 
@@ -286,7 +291,7 @@ int run(fsb_batch* b, uint64_t n_steps) {
     uint32_t grid = 0;
     rc = grid_for(b, b->tuning, &grid);
     if (rc) return rc;
-    rc = upload_chunks(b, grid * (b->tuning.block_size / 64));
+    rc = set_schedule(b, grid * (b->tuning.block_size / 64));
     if (rc) return rc;
     const uint64_t K = b->tuning.steps_per_launch < n_steps ? b->tuning.steps_per_launch : n_steps;
     const uint64_t full = n_steps / K, rest = n_steps % K;

@@ -154,10 +154,12 @@ struct BatchArgs {
     uint32_t hist_len;
     uint32_t steps;                 // iterations per launch
     uint32_t group_size, groups;    // barrier grouping
-    // Tile schedule.  n_chunks == 0: static, tile tl to wavefront tl mod W.
-    // Otherwise wavefronts take chunk c = [chunk_start[c], chunk_start[c+1])
-    // in the order an atomic counter hands them out; the counter of sweep
-    // phase p is queue[(p & 1) * kLineWords].
+    // Tile schedule.  n_chunks == 0: static, chunk c = tiles [c * static_chunk,
+    // (c + 1) * static_chunk) to wavefront c mod W.  Otherwise wavefronts take
+    // chunk c = [chunk_start[c], chunk_start[c+1]) in the order an atomic
+    // counter hands them out; the counter of sweep phase p is
+    // queue[(p & 1) * kLineWords].
+    uint32_t static_chunk;          // >= 1
     const uint32_t* chunk_start;    // [n_chunks + 1]
     uint32_t n_chunks;
     uint32_t* queue;                // two counters, one 256-byte line each

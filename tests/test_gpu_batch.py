@@ -97,7 +97,8 @@ def test_every_launch_shape_gives_identical_state(torch_cuda, block, fpl, varian
     ref.close()
 
 
-SCHEDULES = [(fsb.FSB_SCHED_DYNAMIC, 1), (fsb.FSB_SCHED_DYNAMIC, 3), (fsb.FSB_SCHED_DYNAMIC, 64),
+SCHEDULES = [(fsb.FSB_SCHED_STATIC, 1), (fsb.FSB_SCHED_STATIC, 3),
+             (fsb.FSB_SCHED_DYNAMIC, 1), (fsb.FSB_SCHED_DYNAMIC, 3), (fsb.FSB_SCHED_DYNAMIC, 64),
              (fsb.FSB_SCHED_GUIDED, 1), (fsb.FSB_SCHED_GUIDED, 8)]
 
 
@@ -105,10 +106,11 @@ SCHEDULES = [(fsb.FSB_SCHED_DYNAMIC, 1), (fsb.FSB_SCHED_DYNAMIC, 3), (fsb.FSB_SC
                          ids=["prev", "lean"])
 @pytest.mark.parametrize("sched,chunk", SCHEDULES, ids=[f"s{s}c{c}" for s, c in SCHEDULES])
 def test_work_queue_schedules_give_identical_results(torch_cuda, sched, chunk, variant):
-    """Dynamic and guided schedules move tiles between wavefronts from sweep to
-    sweep; with the same tiles (same fish per lane) the columns, maxima and
-    even the sums (tile partials are combined in tile order) are identical
-    to the static schedule's, bit for bit."""
+    """Round-robin static chunks, and dynamic and guided schedules that move
+    tiles between wavefronts from sweep to sweep: with the same tiles (same
+    fish per lane) the columns, maxima and even the sums (tile partials are
+    combined in tile order) are identical to the contiguous static
+    schedule's, bit for bit."""
     announce(f"schedule {sched} chunk {chunk} variant {variant}")
     common = fsb.FsbConfig(n_fish=0, history_len=5)
     seeds = list(range(len(SIZES)))
