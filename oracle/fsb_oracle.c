@@ -132,13 +132,28 @@ void oracle_init(const Config *cfg, Fish *school)
     }
 }
 
-/* Move one fish by (dx, dy) inside the pond and re-evaluate its objective. */
-static void swim_fish(Fish *f, float dx, float dy, float H)
+/* Move one fish by (dx, dy) inside the pond and re-evaluate its objective.
+ * Weighted rule: the fish's weight affects its mobility (Sec. 2.1.1), read
+ * as a step scaled by weightMin / weight.  Greedy rule: the movement is
+ * influenced by the objective (Sec. 2.1.2), read as keeping a move only if
+ * the new position is strictly closer to the pond centre. */
+static void swim_fish(const Config *cfg, Fish *f, float dx, float dy)
 {
-    f->x = clampf(f->x + dx, -H, H);
-    f->y = clampf(f->y + dy, -H, H);
+    const float H = cfg->pondHalf;
+    if (cfg->swimRule & ORACLE_SWIM_WEIGHTED) {
+        float mobility = cfg->weightMin / f->weight;
+        dx = dx * mobility;
+        dy = dy * mobility;
+    }
+    float x = clampf(f->x + dx, -H, H);
+    float y = clampf(f->y + dy, -H, H);
+    float c = objective(x, y);
     f->prevObjective = f->currentObjective;
-    f->currentObjective = objective(f->x, f->y);
+    if (!(cfg->swimRule & ORACLE_SWIM_GREEDY) || c < f->currentObjective) {
+        f->x = x;
+        f->y = y;
+        f->currentObjective = c;
+    }
 }
 
 static void swim_drawn(const Config *cfg, Fish *f, uint64_t fish, uint64_t t)
@@ -147,7 +162,7 @@ static void swim_drawn(const Config *cfg, Fish *f, uint64_t fish, uint64_t t)
     oracle_fish_words(cfg->seed, fish, (uint32_t)t, ORACLE_DOMAIN_SWIM, &a, &b);
     float dx = cfg->swimStep * oracle_signed_unit(a);
     float dy = cfg->swimStep * oracle_signed_unit(b);
-    swim_fish(f, dx, dy, cfg->pondHalf);
+    swim_fish(cfg, f, dx, dy);
 }
 
 /* eat(): the school-wide max of |prevObjective - currentObjective|, then the
@@ -243,7 +258,7 @@ void oracle_step_displaced(const Config *cfg, Fish *school, const float *dx,
                            double absSums[3])
 {
     for (uint64_t i = 0; i < cfg->numFish; ++i)
-        swim_fish(&school[i], dx[i], dy[i], cfg->pondHalf);
+        swim_fish(cfg, &school[i], dx[i], dy[i]);
     finish_step(cfg, school, maxDiff, sums, absSums);
 }
 
@@ -255,11 +270,14 @@ void oracle_run(const Config *cfg, Fish *school, uint64_t t0, uint64_t nSteps,
                     sums ? sums + 3 * k : 0, absSums ? absSums + 3 * k : 0);
 }
 
-void oracle_follow_fish(const Config *cfg, uint64_t fish, uint64_t t0,
-                        uint64_t t1, Fish *f)
+int oracle_follow_fish(const Config *cfg, uint64_t fish, uint64_t t0,
+                       uint64_t t1, Fish *f)
 {
+    if (cfg->swimRule & ORACLE_SWIM_WEIGHTED)
+        return -1;
     for (uint64_t t = t0; t < t1; ++t)
         swim_drawn(cfg, f, fish, t);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -295,12 +313,23 @@ void oracle_init_f64(const Config *cfg, FishD *school)
     }
 }
 
-static void swim_fish_f64(FishD *f, double dx, double dy, double H)
+static void swim_fish_f64(const Config *cfg, FishD *f, double dx, double dy)
 {
-    f->x = clampd(f->x + dx, -H, H);
-    f->y = clampd(f->y + dy, -H, H);
+    const double H = cfg->pondHalf;
+    if (cfg->swimRule & ORACLE_SWIM_WEIGHTED) {
+        double mobility = (double)cfg->weightMin / f->weight;
+        dx = dx * mobility;
+        dy = dy * mobility;
+    }
+    double x = clampd(f->x + dx, -H, H);
+    double y = clampd(f->y + dy, -H, H);
+    double c = sqrt(x * x + y * y);
     f->prevObjective = f->currentObjective;
-    f->currentObjective = sqrt(f->x * f->x + f->y * f->y);
+    if (!(cfg->swimRule & ORACLE_SWIM_GREEDY) || c < f->currentObjective) {
+        f->x = x;
+        f->y = y;
+        f->currentObjective = c;
+    }
 }
 
 static void finish_step_f64(const Config *cfg, FishD *school, double *maxDiff,
@@ -338,13 +367,13 @@ static void finish_step_f64(const Config *cfg, FishD *school, double *maxDiff,
 void oracle_step_f64(const Config *cfg, FishD *school, uint64_t t,
                      double *maxDiff, double sums[3])
 {
-    const double S = cfg->swimStep, H = cfg->pondHalf;
+    const double S = cfg->swimStep;
 #pragma omp parallel for schedule(static)
     for (uint64_t i = 0; i < cfg->numFish; ++i) {
         uint32_t a, b;
         oracle_fish_words(cfg->seed, i, (uint32_t)t, ORACLE_DOMAIN_SWIM, &a, &b);
-        swim_fish_f64(&school[i], S * (2.0 * unit_f64(a) - 1.0),
-                      S * (2.0 * unit_f64(b) - 1.0), H);
+        swim_fish_f64(cfg, &school[i], S * (2.0 * unit_f64(a) - 1.0),
+                      S * (2.0 * unit_f64(b) - 1.0));
     }
     finish_step_f64(cfg, school, maxDiff, sums);
 }
@@ -354,7 +383,7 @@ void oracle_step_displaced_f64(const Config *cfg, FishD *school,
                                double *maxDiff, double sums[3])
 {
     for (uint64_t i = 0; i < cfg->numFish; ++i)
-        swim_fish_f64(&school[i], dx[i], dy[i], cfg->pondHalf);
+        swim_fish_f64(cfg, &school[i], dx[i], dy[i]);
     finish_step_f64(cfg, school, maxDiff, sums);
 }
 

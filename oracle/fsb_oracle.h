@@ -21,7 +21,15 @@
  * The paper leaves the swim rule, the feeding formula, the weight limits and
  * the random generator unstated; the readings taken here are:
  *   swim      d = S * v, v uniform on [-1,1) per axis, position clamped to
- *             [-H, H];
+ *             [-H, H]; two optional rules read the paper's remarks that a
+ *             fish's weight affects its mobility (Sec. 2.1.1) and that its
+ *             movement is influenced by its weight and objective
+ *             (Sec. 2.1.2):
+ *               weighted: d is scaled by weightMin / weight, so heavier fish
+ *                         take shorter steps;
+ *               greedy:   the move is kept only if it brings the fish
+ *                         strictly closer to the pond centre; otherwise the
+ *                         fish stays where it was (its diff is then 0);
  *   normaliser maxDiff = max_i |diff_i| (a magnitude, so that feeding keeps
  *             its sign even when every fish moved away from the centre);
  *   feeding   if maxDiff > 0: weight = clamp(weight + diff / maxDiff,
@@ -74,7 +82,12 @@ typedef struct Config {
     float initWeightHi;
     float weightMin;    /* weight limits applied by feeding */
     float weightMax;
+    uint32_t swimRule;  /* ORACLE_SWIM_* flags */
 } Config;
+
+/* Swim rules (flags; 0 = the plain random swim). */
+#define ORACLE_SWIM_GREEDY 1u
+#define ORACLE_SWIM_WEIGHTED 2u
 
 /* Random-stream domains (the fourth counter word). */
 #define ORACLE_DOMAIN_SWIM 0u
@@ -110,10 +123,12 @@ void oracle_step_displaced(const Config *cfg, Fish *school, const float *dx,
 void oracle_run(const Config *cfg, Fish *school, uint64_t t0, uint64_t nSteps,
                 float *maxDiff, double *sums, double *absSums);
 /* Position and objectives of a single fish over iterations t0 .. t1-1.
- * Swimming does not depend on weights or on other fish, so one fish can be
- * followed on its own.  f holds the fish's state at the start of t0. */
-void oracle_follow_fish(const Config *cfg, uint64_t fish, uint64_t t0,
-                        uint64_t t1, Fish *f);
+ * Unless the weighted rule is on, swimming depends neither on weights nor on
+ * other fish, so one fish can be followed on its own (under the weighted rule
+ * this does nothing and returns -1; otherwise 0).  f holds the fish's state
+ * at the start of t0. */
+int oracle_follow_fish(const Config *cfg, uint64_t fish, uint64_t t0,
+                       uint64_t t1, Fish *f);
 /* Exact-as-possible reference sums: each product of two binary32 values is
  * exact in binary64, summed with Neumaier's compensated summation. */
 void oracle_barycentre_sums(const Fish *school, uint64_t n, double sums[3],

@@ -45,7 +45,13 @@ class _Config(ctypes.Structure):
     _fields_ = [("numFish", ctypes.c_uint64), ("seed", ctypes.c_uint64),
                 ("pondHalf", ctypes.c_float), ("swimStep", ctypes.c_float),
                 ("initWeightLo", ctypes.c_float), ("initWeightHi", ctypes.c_float),
-                ("weightMin", ctypes.c_float), ("weightMax", ctypes.c_float)]
+                ("weightMin", ctypes.c_float), ("weightMax", ctypes.c_float),
+                ("swimRule", ctypes.c_uint32)]
+
+
+# Swim rules (flags; 0 = the plain random swim)
+SWIM_GREEDY = 1    # keep a move only if it brings the fish closer to the centre
+SWIM_WEIGHTED = 2  # step scaled by weightMin / weight
 
 
 @dataclasses.dataclass
@@ -59,11 +65,12 @@ class Config:
     initWeightHi: float = 2.0
     weightMin: float = 1.0
     weightMax: float = 4.0
+    swimRule: int = 0            # SWIM_* flags
 
     def c(self) -> _Config:
         return _Config(self.numFish, self.seed, self.pondHalf, self.swimStep,
                        self.initWeightLo, self.initWeightHi, self.weightMin,
-                       self.weightMax)
+                       self.weightMax, self.swimRule)
 
 
 _P = ctypes.c_void_p
@@ -98,6 +105,7 @@ class Oracle:
         lib.oracle_step_displaced.argtypes = [_P, _P, _P, _P, _P, _P, _P]
         lib.oracle_run.argtypes = [_P, _P, u64, u64, _P, _P, _P]
         lib.oracle_follow_fish.argtypes = [_P, u64, u64, u64, _P]
+        lib.oracle_follow_fish.restype = ctypes.c_int
         lib.oracle_barycentre_sums.argtypes = [_P, u64, _P, _P]
         lib.oracle_init_f64.argtypes = [_P, _P]
         lib.oracle_step_f64.argtypes = [_P, _P, u64, _P, _P]
@@ -179,7 +187,8 @@ class Oracle:
         its record ``state`` (a FISH scalar or 1-element array) at t0."""
         f = np.array(state, dtype=FISH).reshape(1).copy()
         c = cfg.c()
-        self._lib.oracle_follow_fish(ctypes.byref(c), fish, t0, t1, _ptr(f))
+        if self._lib.oracle_follow_fish(ctypes.byref(c), fish, t0, t1, _ptr(f)) != 0:
+            raise ValueError("under the weighted swim rule a fish cannot be followed alone")
         return f[0]
 
     def barycentre_sums(self, school: np.ndarray):

@@ -27,7 +27,8 @@ import tempfile
 
 import numpy as np
 
-from oracle.oracle import DOMAIN_INIT, DOMAIN_SWIM, FISH, FISH_F64, Config
+from oracle.oracle import (DOMAIN_INIT, DOMAIN_SWIM, FISH, FISH_F64, SWIM_GREEDY, SWIM_WEIGHTED,
+                           Config)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 GOLDEN = os.path.join(HERE, "golden")
@@ -163,11 +164,15 @@ def golden_config(fx: dict) -> Config:
     c = fx["config"]
     return Config(numFish=len(fx["before"]), pondHalf=c["pondHalf"],
                   swimStep=c["swimStep"], weightMin=c["weightMin"],
-                  weightMax=c["weightMax"])
+                  weightMax=c["weightMax"], swimRule=c.get("swimRule", 0))
+
+
+WORKED_EXAMPLES = ("worked_example_4fish.json", "worked_example_division.json",
+                   "worked_example_greedy.json", "worked_example_weighted.json")
 
 
 def pin_worked_examples(O):
-    for name in ("worked_example_4fish.json", "worked_example_division.json"):
+    for name in WORKED_EXAMPLES:
         fx = load_golden(name)
         cfg = golden_config(fx)
         school = golden_school(fx, "before")
@@ -402,10 +407,51 @@ def pin_composition(O):
             assert f[k] == a[i][k], f"follow_fish {i} {k}"
 
 
+def pin_swim_rules(O):
+    """The greedy and weighted swim rules on random schools: the step
+    invariants hold under every rule; greedy diffs are never negative and a
+    fish moves exactly when its objective drops; greedy swimming still does
+    not depend on weights (one fish followed alone equals the school's); and
+    with every weight pinned at weightMin the weighted rule's mobility is
+    exactly 1, so the school evolves bit for bit as under the plain rule."""
+    for rule in (SWIM_GREEDY, SWIM_WEIGHTED, SWIM_GREEDY | SWIM_WEIGHTED):
+        cfg = Config(numFish=2000, seed=17, swimStep=2.0, swimRule=rule)
+        school = O.init(cfg)
+        start = school.copy()
+        for t in range(6):
+            before = school.copy()
+            m, s, a = O.step(cfg, school, t)
+            check_step_invariants(cfg, before, school, m, s, a)
+            if rule & SWIM_GREEDY:
+                diff = school["prevObjective"] - school["currentObjective"]
+                assert (diff >= 0).all(), "greedy diff < 0"
+                moved = (school["x"] != before["x"]) | (school["y"] != before["y"])
+                assert np.array_equal(moved, diff > 0), "greedy moved without improving"
+        if rule == SWIM_GREEDY:
+            for i in (0, 1, 1000, 1999):
+                f = O.follow_fish(cfg, i, 0, 6, start[i])
+                for k in ("x", "y", "prevObjective", "currentObjective"):
+                    assert f[k] == school[i][k], f"greedy follow_fish {i} {k}"
+        else:
+            try:
+                O.follow_fish(cfg, 0, 0, 1, start[0])
+            except ValueError:
+                pass
+            else:
+                raise AssertionError("follow_fish accepted the weighted rule")
+    fixed = dict(numFish=999, seed=23, initWeightLo=1.0, initWeightHi=1.0, weightMin=1.0,
+                 weightMax=1.0, swimStep=0.7)
+    a = O.init(Config(**fixed))
+    b = a.copy()
+    O.run(Config(**fixed), a, 0, 5)
+    O.run(Config(**fixed, swimRule=SWIM_WEIGHTED), b, 0, 5)
+    assert a.tobytes() == b.tobytes(), "weighted rule with mobility 1 differs from the plain swim"
+
+
 ALL_PINS = (pin_philox_matches_aten, pin_fish_word_layout, pin_unit_map_exhaustive,
             pin_philox_statistics, pin_worked_examples, pin_zero_swim,
             pin_uniform_weights_mean, pin_symmetric_school_exact, pin_init_stream,
-            pin_swim_stream, pin_invariants, pin_exact_sums, pin_composition)
+            pin_swim_stream, pin_invariants, pin_exact_sums, pin_composition, pin_swim_rules)
 
 
 def run_all(O) -> list[str]:

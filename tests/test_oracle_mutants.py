@@ -25,10 +25,28 @@ MUTANTS = [
      "(uint32_t)(t + 1), ORACLE_DOMAIN_SWIM, &a, &b);\n    float dx"),
     ("swim_in_init_domain", "(uint32_t)t, ORACLE_DOMAIN_SWIM, &a, &b);\n    float dx",
      "(uint32_t)t, ORACLE_DOMAIN_INIT, &a, &b);\n    float dx"),
-    ("no_pond_clamp", "f->x = clampf(f->x + dx, -H, H);", "f->x = f->x + dx;"),
+    ("no_pond_clamp", "float x = clampf(f->x + dx, -H, H);", "float x = f->x + dx;"),
     ("objective_wrong_term", "return sqrtf(x * x + y * y);", "return sqrtf(x * x + y * x);"),
-    ("prev_not_kept", "    f->prevObjective = f->currentObjective;\n    f->currentObjective = objective(f->x, f->y);\n}",
-     "    f->currentObjective = objective(f->x, f->y);\n}"),
+    ("prev_not_kept", "    float c = objective(x, y);\n    f->prevObjective = f->currentObjective;\n",
+     "    float c = objective(x, y);\n"),
+    ("greedy_accepts_ties", "    float c = objective(x, y);\n    f->prevObjective = f->currentObjective;\n"
+     "    if (!(cfg->swimRule & ORACLE_SWIM_GREEDY) || c < f->currentObjective) {",
+     "    float c = objective(x, y);\n    f->prevObjective = f->currentObjective;\n"
+     "    if (!(cfg->swimRule & ORACLE_SWIM_GREEDY) || c <= f->currentObjective) {"),
+    ("greedy_ignored", "    float c = objective(x, y);\n    f->prevObjective = f->currentObjective;\n"
+     "    if (!(cfg->swimRule & ORACLE_SWIM_GREEDY) || c < f->currentObjective) {",
+     "    float c = objective(x, y);\n    f->prevObjective = f->currentObjective;\n"
+     "    if (1) {"),
+    ("greedy_prev_only_on_accept", "    float c = objective(x, y);\n    f->prevObjective = f->currentObjective;\n"
+     "    if (!(cfg->swimRule & ORACLE_SWIM_GREEDY) || c < f->currentObjective) {\n",
+     "    float c = objective(x, y);\n"
+     "    if (!(cfg->swimRule & ORACLE_SWIM_GREEDY) || c < f->currentObjective) {\n"
+     "        f->prevObjective = f->currentObjective;\n"),
+    ("weighted_inverted", "float mobility = cfg->weightMin / f->weight;",
+     "float mobility = f->weight / cfg->weightMin;"),
+    ("weighted_ignored", "        dx = dx * mobility;\n        dy = dy * mobility;\n    }\n    float x",
+     "    }\n    float x"),
+    ("weighted_one_axis", "        dy = dy * mobility;\n    }\n    float x", "    }\n    float x"),
     ("signed_max", "float mag = fabsf(diff);", "float mag = diff;"),
     ("no_zero_guard", "if (maxDiff > 0.0f) {", "{"),
     ("feed_sign_flip", "float diff = f->prevObjective - f->currentObjective;\n            f->weight",
