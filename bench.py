@@ -92,14 +92,14 @@ def plain_run(n: int, steps: int, warmup: int):
     return wall, kernels, xy
 
 
-def run_form(n: int, steps: int, mode: int, warmup: int = 2):
+def run_form(n: int, steps: int, mode: int, warmup: int = 2, swim_rule: int = 0):
     """Wall time of `steps` iterations of one school in the given mode, plus
     the kernels' event-timed durations."""
     import torch
 
     import paper_2507_20173_amd as fsb
 
-    cfg = fsb.FsbConfig(n_fish=n, seed=0, history_len=1)
+    cfg = fsb.FsbConfig(n_fish=n, seed=0, history_len=1, swim_rule=swim_rule)
     sch = fsb.School(cfg)
     sch.run(warmup, mode)
     sch.sync()
@@ -280,6 +280,25 @@ def ablation_form(sizes, checked_steps: int, budget_s: float = 0.5):
         out[f"n={n}"] = row
         log(f"ablation n={n}: " + ", ".join(f"{k} {v['ms_per_step']:.4f} ms"
                                             for k, v in row.items()))
+    return out
+
+
+def rules_form(n: int, steps: int):
+    """Cost of the swim rules (greedy, weighted, both) against the plain
+    random swim on one school, per-iteration launches and the persistent form
+    (the variant FSB_RUN_FUSED picks)."""
+    import paper_2507_20173_amd as fsb
+
+    out = {"workload": f"swim rules: N=2^{n.bit_length() - 1} fish, {steps} iterations"}
+    for name, rule in (("plain_swim", 0), ("greedy", fsb.FSB_SWIM_GREEDY),
+                       ("weighted", fsb.FSB_SWIM_WEIGHTED),
+                       ("greedy_weighted", fsb.FSB_SWIM_GREEDY | fsb.FSB_SWIM_WEIGHTED)):
+        row = {}
+        for form, mode in (("per_iteration", fsb.FSB_RUN_PLAIN), ("persistent", fsb.FSB_RUN_FUSED)):
+            wall, _, _ = run_form(n, steps, mode, swim_rule=rule)
+            row[form] = {"ms_per_step": wall / steps * 1e3, "value": n * steps / wall}
+        out[name] = row
+        log(f"rule {name}: " + ", ".join(f"{k} {v['ms_per_step']:.4f} ms" for k, v in row.items()))
     return out
 
 
@@ -490,7 +509,7 @@ def main() -> int:
     ap.add_argument("--n-fish", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-only", action="store_true", help="skip the other forms")
-    ap.add_argument("--forms", default="fused,precision,batched,ablation",
+    ap.add_argument("--forms", default="fused,precision,batched,ablation,rules",
                     help="comma list of the forms to measure beside the headline")
     ap.add_argument("--fused-steps", type=int, default=2000)
     ap.add_argument("--precision-steps", type=int, default=200)
@@ -504,6 +523,7 @@ def main() -> int:
     ap.add_argument("--ablation-sizes", default="10000,1048576,16777216",
                     help="school sizes of the construct ablation")
     ap.add_argument("--ablation-checked-steps", type=int, default=2)
+    ap.add_argument("--rules-steps", type=int, default=300)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run known-size device copies first (for counter scaling)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -571,6 +591,8 @@ def main() -> int:
         line["forms"]["batched_cfg5"] = batched_form(args.schools, args.batch_steps,
                                                      args.autotune_steps, args.baseline_schools,
                                                      args.schedule_steps)
+    if "rules" in forms:
+        line["forms"]["swim_rules"] = rules_form(n, args.rules_steps)
     if "ablation" in forms:
         line["forms"]["construct_ablation"] = ablation_form(
             [int(v) for v in args.ablation_sizes.split(",")], args.ablation_checked_steps)

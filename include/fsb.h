@@ -80,6 +80,15 @@ extern "C" {
                                       modes and batches return FSB_ERR_UNSUPPORTED.  The sums are
                                       not deterministic (atomic order). */
 
+/* fsb_config.swim_rule: flags; 0 is the plain random swim.  Readings of the
+ * paper's remarks that a fish's weight affects its mobility (Sec. 2.1.1) and
+ * that its movement is influenced by its weight and objective (Sec. 2.1.2). */
+#define FSB_SWIM_GREEDY 1u   /* a move is kept only if the objective strictly decreases;
+                                otherwise the fish stays and its diff is 0 */
+#define FSB_SWIM_WEIGHTED 2u /* the displacement is scaled by w_min / w, w being the weight
+                                the fish has when it swims; needs w_min > 0 and
+                                w_init_lo > 0 */
+
 /* fsb_run modes. */
 #define FSB_RUN_PLAIN 0u      /* one fsb_step (two kernels) per iteration */
 #define FSB_RUN_FUSED 1u      /* one persistent launch with a grid barrier per iteration;
@@ -99,6 +108,7 @@ typedef struct fsb_config {
     float w_max;
     uint32_t reduce_mode; /* FSB_REDUCE_* */
     uint32_t history_len; /* per-iteration records kept, >= 1 (a ring) */
+    uint32_t swim_rule;   /* FSB_SWIM_* flags, 0 = plain random swim */
 } fsb_config;
 
 /* The school's state: five float32 columns of n_fish (caller-owned device

@@ -17,7 +17,8 @@ from ._lib import (FSB_KERNEL_FEED_BARY, FSB_KERNEL_FUSED, FSB_KERNEL_INIT,  # n
                    FSB_KERNEL_KINDS, FSB_KERNEL_SWIM_EVAL, FSB_REDUCE_COMPENSATED,
                    FSB_REDUCE_CRITICAL_F32, FSB_REDUCE_NAIVE_F32, FSB_RUN_FUSED,
                    FSB_RUN_FUSED_LEAN, FSB_RUN_FUSED_PREV, FSB_RUN_PLAIN, FSB_SCHED_DYNAMIC,
-                   FSB_SCHED_GUIDED, FSB_SCHED_STATIC, FsbError, check, lib)
+                   FSB_SCHED_GUIDED, FSB_SCHED_STATIC, FSB_SWIM_GREEDY, FSB_SWIM_WEIGHTED,
+                   FsbError, check, lib)
 
 RECORD = np.dtype([("sum_w", "<f8"), ("sum_wx", "<f8"), ("sum_wy", "<f8"),
                    ("max_delta", "<f4"), ("step_lo", "<u4")])
@@ -38,11 +39,12 @@ class FsbConfig:
     w_max: float = 4.0
     reduce_mode: int = FSB_REDUCE_COMPENSATED
     history_len: int = 1
+    swim_rule: int = 0
 
     def c(self) -> _lib.fsb_config:
         return _lib.fsb_config(self.n_fish, self.seed, self.pond_half, self.swim_step,
                                self.w_init_lo, self.w_init_hi, self.w_min, self.w_max,
-                               self.reduce_mode, self.history_len)
+                               self.reduce_mode, self.history_len, self.swim_rule)
 
 
 def _ptr(t) -> int:

@@ -21,6 +21,8 @@ FSB_ERR_DEVICE = -5
 FSB_REDUCE_COMPENSATED = 0
 FSB_REDUCE_NAIVE_F32 = 1
 FSB_REDUCE_CRITICAL_F32 = 2
+FSB_SWIM_GREEDY = 1
+FSB_SWIM_WEIGHTED = 2
 FSB_SCHED_STATIC = 0
 FSB_SCHED_DYNAMIC = 1
 FSB_SCHED_GUIDED = 2
@@ -41,7 +43,8 @@ class fsb_config(ctypes.Structure):
                 ("pond_half", ctypes.c_float), ("swim_step", ctypes.c_float),
                 ("w_init_lo", ctypes.c_float), ("w_init_hi", ctypes.c_float),
                 ("w_min", ctypes.c_float), ("w_max", ctypes.c_float),
-                ("reduce_mode", ctypes.c_uint32), ("history_len", ctypes.c_uint32)]
+                ("reduce_mode", ctypes.c_uint32), ("history_len", ctypes.c_uint32),
+                ("swim_rule", ctypes.c_uint32)]
 
 
 class fsb_state(ctypes.Structure):

@@ -66,6 +66,7 @@ SchoolArgs make_args(const fsb_config& c, const fsb_state& st, void* ws, const L
     a.S = c.swim_step;
     a.wmin = c.w_min;
     a.wmax = c.w_max;
+    a.rule = c.swim_rule;
     a.ctrl = reinterpret_cast<Ctrl*>(base + L.ctrl);
     a.hist = reinterpret_cast<fsb_record*>(base + L.hist);
     a.hist_len = c.history_len;

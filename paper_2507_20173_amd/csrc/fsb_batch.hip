@@ -228,6 +228,7 @@ template <int GPL, bool kNT, bool kLean>
 __device__ __forceinline__ uint32_t tile_prologue(const BatchArgs& a, const Tile& T, uint32_t t0,
                                                   uint32_t lane) {
     const float H = a.H, Sw = a.S;
+    const SwimRule rule{a.rule, a.wmin};
     uint32_t best = 0u;
 #pragma unroll
     for (int q = 0; q < GPL; ++q) {
@@ -244,11 +245,13 @@ __device__ __forceinline__ uint32_t tile_prologue(const BatchArgs& a, const Tile
             } else {
                 C = ldv<kNT>(a.cur, c4);
             }
+            float4 Wt = swim_weights<kNT>(rule, a.w, c4);
             float dx[4], dy[4];
             group_draws(Sw, T.k0, T.k1, g, t0, dx, dy);
 #pragma unroll
             for (int f = 0; f < 4; ++f) {
-                const float nc = swim(lane_of(X, f), lane_of(Y, f), dx[f], dy[f], H);
+                const float nc = swim(rule, lane_of(X, f), lane_of(Y, f), dx[f], dy[f], H,
+                                      lane_of(C, f), lane_of(Wt, f));
                 best = max(best, mag_bits(lane_of(C, f) - nc));
             }
             if constexpr (!kLean) {
@@ -263,7 +266,8 @@ __device__ __forceinline__ uint32_t tile_prologue(const BatchArgs& a, const Tile
                 fish_draw(Sw, T.k0, T.k1, 4 * g + f, t0, dx, dy);
                 float x = a.x[o], y = a.y[o];
                 const float c = kLean ? distance(x, y) : a.cur[o];
-                const float nc = swim(x, y, dx, dy, H);
+                const float wt = (rule.flags & kSwimWeighted) ? a.w[o] : 1.0f;
+                const float nc = swim(rule, x, y, dx, dy, H, c, wt);
                 best = max(best, mag_bits(c - nc));
                 if constexpr (!kLean) {
                     a.x[o] = x;
@@ -285,6 +289,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
     const uint32_t n_waves = gridDim.x * WPB;
     const uint32_t S = a.n_schools;
     const float H = a.H, Sw = a.S, wmin = a.wmin, wmax = a.wmax;
+    const SwimRule rule{a.rule, a.wmin};
     const Barrier bar{a.sync, a.ctrl, a.group_size, a.groups};
     uint32_t phase = 0;
     if (threadIdx.x == 0) phase = ld_agent(a.sync + kSyncPhase);
@@ -367,7 +372,8 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
 #pragma unroll
                         for (int f = 0; f < 4; ++f) {
                             lane_of(P[q], f) = distance(lane_of(X[q], f), lane_of(Y[q], f));
-                            lane_of(C, f) = swim(lane_of(X[q], f), lane_of(Y[q], f), dx[f], dy[f], H);
+                            lane_of(C, f) = swim(rule, lane_of(X[q], f), lane_of(Y[q], f), dx[f],
+                                                 dy[f], H, lane_of(P[q], f), lane_of(W[q], f));
                         }
                     } else {
 #pragma unroll
@@ -393,8 +399,8 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
                         float4 nx = X[q], ny = Y[q];
 #pragma unroll
                         for (int f = 0; f < 4; ++f) {
-                            const float nc =
-                                swim(lane_of(nx, f), lane_of(ny, f), dx[f], dy[f], H);
+                            const float nc = swim(rule, lane_of(nx, f), lane_of(ny, f), dx[f],
+                                                  dy[f], H, lane_of(C, f), lane_of(W[q], f));
                             best = max(best, mag_bits(lane_of(C, f) - nc));
                         }
                         if constexpr (!kLean) {
@@ -407,19 +413,20 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
                     for (uint32_t f = 0; 4 * j + f < T.n_fish; ++f) {
                         const uint64_t o = 4 * c4 + f;
                         float x = a.x[o], y = a.y[o];
+                        const float w0 = a.w[o];
                         float pv, c;
                         float dx, dy;
                         if constexpr (kLean) {
                             fish_draw(Sw, T.k0, T.k1, 4 * g + f, s, dx, dy);
                             pv = distance(x, y);
-                            c = swim(x, y, dx, dy, H);
+                            c = swim(rule, x, y, dx, dy, H, pv, w0);
                             a.x[o] = x;
                             a.y[o] = y;
                         } else {
                             pv = a.prev[o];
                             c = distance(x, y);
                         }
-                        const float nw = feed(a.w[o], pv - c, M, wmin, wmax);
+                        const float nw = feed(w0, pv - c, M, wmin, wmax);
                         a.w[o] = nw;
                         ls.add(nw, x, y);
                         if (last) {
@@ -427,7 +434,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
                             a.cur[o] = c;
                         } else {
                             fish_draw(Sw, T.k0, T.k1, 4 * g + f, s + 1u, dx, dy);
-                            const float nc = swim(x, y, dx, dy, H);
+                            const float nc = swim(rule, x, y, dx, dy, H, c, nw);
                             best = max(best, mag_bits(c - nc));
                             if constexpr (!kLean) {
                                 a.x[o] = x;

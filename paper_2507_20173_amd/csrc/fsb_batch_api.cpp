@@ -487,6 +487,7 @@ int fsb_batch_init(const fsb_config* common, uint32_t n_schools, const uint64_t*
     a.wmax = common->w_max;
     a.wlo = common->w_init_lo;
     a.whi = common->w_init_hi;
+    a.rule = common->swim_rule;
     a.ctrl = reinterpret_cast<Ctrl*>(base + L.ctrl);
     a.sync = reinterpret_cast<uint32_t*>(base + L.sync);
     a.step = &a.ctrl->step;

@@ -77,12 +77,34 @@ __device__ __forceinline__ float distance(float x, float y) {
     return sqrtf(xx + yy);
 }
 
-// One fish's swim: move by (dx, dy) inside [-H, H]^2 and re-evaluate.  Returns
-// the new objective; x, y are updated in place.
-__device__ __forceinline__ float swim(float& x, float& y, float dx, float dy, float H) {
-    x = clamp_to(x + dx, -H, H);
-    y = clamp_to(y + dy, -H, H);
-    return distance(x, y);
+// Swim rules (flags; 0 = the plain random swim).  Weighted: the
+// displacement is scaled by wmin / w, w being the weight the fish has when it
+// swims (weight affects mobility).  Greedy: a move is kept only if the
+// objective strictly decreases; otherwise the fish stays where it was.
+constexpr uint32_t kSwimGreedy = 1u, kSwimWeighted = 2u;
+
+struct SwimRule {
+    uint32_t flags;  // uniform across a launch
+    float wmin;
+};
+
+// One fish's swim from objective c: move by (dx, dy) under the rule, inside
+// [-H, H]^2, and re-evaluate.  Returns the new objective; x, y are updated in
+// place.  w is read only under the weighted rule.
+__device__ __forceinline__ float swim(const SwimRule& r, float& x, float& y, float dx, float dy,
+                                      float H, float c, float w) {
+    if (r.flags & kSwimWeighted) {
+        const float m = r.wmin / w;
+        dx = dx * m;
+        dy = dy * m;
+    }
+    const float nx = clamp_to(x + dx, -H, H);
+    const float ny = clamp_to(y + dy, -H, H);
+    const float nc = distance(nx, ny);
+    if ((r.flags & kSwimGreedy) && !(nc < c)) return c;
+    x = nx;
+    y = ny;
+    return nc;
 }
 
 // Feeding: w + diff / M, kept inside [wmin, wmax]; M == 0 leaves w alone.

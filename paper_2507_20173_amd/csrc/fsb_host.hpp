@@ -57,6 +57,10 @@ inline int check_config(const fsb_config* c, bool need_fish) {
         return fail(FSB_ERR_INVALID_ARG, "unknown reduce_mode");
     if (c->history_len == 0 || c->history_len > kMaxHistory)
         return fail(FSB_ERR_INVALID_ARG, "history_len must be in [1, 2^24]");
+    if (c->swim_rule & ~(FSB_SWIM_GREEDY | FSB_SWIM_WEIGHTED))
+        return fail(FSB_ERR_INVALID_ARG, "unknown swim_rule flags");
+    if ((c->swim_rule & FSB_SWIM_WEIGHTED) && !(c->w_min > 0.0f && c->w_init_lo > 0.0f))
+        return fail(FSB_ERR_INVALID_ARG, "the weighted swim rule needs w_min > 0 and w_init_lo > 0");
     return FSB_OK;
 }
 

@@ -65,6 +65,7 @@ struct SchoolArgs {
     uint64_t n;           // fish
     uint32_t k0, k1;      // Philox key (seed lo, hi)
     float H, S, wmin, wmax;
+    uint32_t rule;        // swim rule flags (FSB_SWIM_*)
     Ctrl *ctrl;
     fsb_record *hist;
     uint32_t hist_len;
@@ -143,6 +144,7 @@ struct BatchArgs {
     uint32_t n_tiles;
     uint32_t n_schools;
     float H, S, wmin, wmax, wlo, whi;
+    uint32_t rule;                  // swim rule flags (FSB_SWIM_*)
     Ctrl* ctrl;
     uint32_t* sync;                 // barrier words
     uint32_t* step;                 // device iteration counter (advanced by each launch)

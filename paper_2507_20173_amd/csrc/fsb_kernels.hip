@@ -239,12 +239,13 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
         combine_block(a, s.prev_t, s.prev_grid, s.naive, a.ctrl->last_max);
 
     const float H = a.H;
+    const SwimRule rule{a.rule, a.wmin};
     const uint64_t n4 = a.n >> 2;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     uint32_t best = 0u;
     for (uint64_t g0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g0 < n4;
          g0 += kUnroll * stride) {
-        float4 X[kUnroll], Y[kUnroll], C[kUnroll];
+        float4 X[kUnroll], Y[kUnroll], C[kUnroll], Wt[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const uint64_t g = g0 + u * stride;
@@ -252,6 +253,7 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
                 X[u] = ldv<NT>(a.x, g);
                 Y[u] = ldv<NT>(a.y, g);
                 C[u] = ldv<NT>(a.cur, g);
+                Wt[u] = swim_weights<NT>(rule, a.w, g);
             }
         }
 #pragma unroll
@@ -269,7 +271,8 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
             float4 nx = X[u], ny = Y[u], nc;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                lane_of(nc, k) = swim(lane_of(nx, k), lane_of(ny, k), dx[k], dy[k], H);
+                lane_of(nc, k) = swim(rule, lane_of(nx, k), lane_of(ny, k), dx[k], dy[k], H,
+                                      lane_of(C[u], k), lane_of(Wt[u], k));
                 const uint32_t d = mag_bits(lane_of(C[u], k) - lane_of(nc, k));
                 if constexpr (kCritical) lane_atomic_max(crit, d);
                 else best = max(best, d);
@@ -292,7 +295,8 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
             }
             float x = a.x[i], y = a.y[i];
             const float c = a.cur[i];
-            const float nc = swim(x, y, dx, dy, H);
+            const float wt = (rule.flags & kSwimWeighted) ? a.w[i] : 1.0f;
+            const float nc = swim(rule, x, y, dx, dy, H, c, wt);
             const uint32_t d = mag_bits(c - nc);
             if constexpr (kCritical) lane_atomic_max(crit, d);
             else best = max(best, d);
@@ -403,6 +407,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
     constexpr int B = kFusedBlock;
     __shared__ uint32_t M_sh;
     const float H = a.H, wmin = a.wmin, wmax = a.wmax;
+    const SwimRule rule{a.rule, a.wmin};
     const uint32_t grid = gridDim.x;
     const uint64_t n4 = a.n >> 2;
     const uint64_t stride = (uint64_t)grid * B;
@@ -418,11 +423,13 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
         uint32_t best = 0u;
         for (uint64_t g = gbase; g < n4; g += stride) {
             float4 X = ldv<kNT>(a.x, g), Y = ldv<kNT>(a.y, g), C = ldv<kNT>(a.cur, g);
+            float4 Wt = swim_weights<kNT>(rule, a.w, g);
             float dx[4], dy[4];
             group_draws(a.S, a.k0, a.k1, g, f.t0, dx, dy);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const float nc = swim(lane_of(X, q), lane_of(Y, q), dx[q], dy[q], H);
+                const float nc = swim(rule, lane_of(X, q), lane_of(Y, q), dx[q], dy[q], H,
+                                      lane_of(C, q), lane_of(Wt, q));
                 best = max(best, mag_bits(lane_of(C, q) - nc));
             }
             stv<kNT>(a.x, g, X);
@@ -434,7 +441,8 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
             fish_draw(a.S, a.k0, a.k1, tail_i, f.t0, dx, dy);
             float x = a.x[tail_i], y = a.y[tail_i];
             const float c = a.cur[tail_i];
-            const float nc = swim(x, y, dx, dy, H);
+            const float wt = (rule.flags & kSwimWeighted) ? a.w[tail_i] : 1.0f;
+            const float nc = swim(rule, x, y, dx, dy, H, c, wt);
             best = max(best, mag_bits(c - nc));
             a.x[tail_i] = x;
             a.y[tail_i] = y;
@@ -486,8 +494,8 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
                     group_draws(a.S, a.k0, a.k1, g, s + 1u, dx, dy);
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const float nc =
-                            swim(lane_of(X[u], q), lane_of(Y[u], q), dx[q], dy[q], H);
+                        const float nc = swim(rule, lane_of(X[u], q), lane_of(Y[u], q), dx[q],
+                                              dy[q], H, lane_of(C, q), lane_of(W[u], q));
                         best = max(best, mag_bits(lane_of(C, q) - nc));
                     }
                     stv<kNT>(a.x, g, X[u]);
@@ -507,7 +515,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
             } else {
                 float dx, dy;
                 fish_draw(a.S, a.k0, a.k1, tail_i, s + 1u, dx, dy);
-                const float nc = swim(x, y, dx, dy, H);
+                const float nc = swim(rule, x, y, dx, dy, H, c, nw);
                 best = max(best, mag_bits(c - nc));
                 a.x[tail_i] = x;
                 a.y[tail_i] = y;
@@ -537,6 +545,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, F
     constexpr int B = kFusedBlock;
     __shared__ uint32_t M_sh;
     const float H = a.H, wmin = a.wmin, wmax = a.wmax;
+    const SwimRule rule{a.rule, a.wmin};
     const uint32_t grid = gridDim.x;
     const uint64_t n4 = a.n >> 2;
     const uint64_t stride = (uint64_t)grid * B;
@@ -552,13 +561,15 @@ __global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, F
         uint32_t best = 0u;
         for (uint64_t g = gbase; g < n4; g += stride) {
             const float4 X = ldv<kNT>(a.x, g), Y = ldv<kNT>(a.y, g);
+            float4 Wt = swim_weights<kNT>(rule, a.w, g);
             float dx[4], dy[4];
             group_draws(a.S, a.k0, a.k1, g, f.t0, dx, dy);
             float4 nx = X, ny = Y;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const float c = distance(lane_of(nx, q), lane_of(ny, q));
-                const float nc = swim(lane_of(nx, q), lane_of(ny, q), dx[q], dy[q], H);
+                const float nc = swim(rule, lane_of(nx, q), lane_of(ny, q), dx[q], dy[q], H, c,
+                                      lane_of(Wt, q));
                 best = max(best, mag_bits(c - nc));
             }
         }
@@ -567,7 +578,8 @@ __global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, F
             fish_draw(a.S, a.k0, a.k1, tail_i, f.t0, dx, dy);
             float x = a.x[tail_i], y = a.y[tail_i];
             const float c = distance(x, y);
-            const float nc = swim(x, y, dx, dy, H);
+            const float wt = (rule.flags & kSwimWeighted) ? a.w[tail_i] : 1.0f;
+            const float nc = swim(rule, x, y, dx, dy, H, c, wt);
             best = max(best, mag_bits(c - nc));
         }
         const uint32_t m = block_max<B>(best);
@@ -604,7 +616,8 @@ __global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, F
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     lane_of(C0, q) = distance(lane_of(X[u], q), lane_of(Y[u], q));
-                    lane_of(C1, q) = swim(lane_of(X[u], q), lane_of(Y[u], q), dx[q], dy[q], H);
+                    lane_of(C1, q) = swim(rule, lane_of(X[u], q), lane_of(Y[u], q), dx[q], dy[q],
+                                          H, lane_of(C0, q), lane_of(W[u], q));
                     const float diff = lane_of(C0, q) - lane_of(C1, q);
                     lane_of(W[u], q) = feed(lane_of(W[u], q), diff, M, wmin, wmax);
                     ls.add(lane_of(W[u], q), lane_of(X[u], q), lane_of(Y[u], q));
@@ -620,7 +633,8 @@ __global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, F
                     float4 nx = X[u], ny = Y[u];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const float nc = swim(lane_of(nx, q), lane_of(ny, q), dx[q], dy[q], H);
+                        const float nc = swim(rule, lane_of(nx, q), lane_of(ny, q), dx[q], dy[q],
+                                              H, lane_of(C1, q), lane_of(W[u], q));
                         best = max(best, mag_bits(lane_of(C1, q) - nc));
                     }
                 }
@@ -630,9 +644,10 @@ __global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, F
             float dx, dy;
             fish_draw(a.S, a.k0, a.k1, tail_i, s, dx, dy);
             float x = a.x[tail_i], y = a.y[tail_i];
+            const float w0 = a.w[tail_i];
             const float c0 = distance(x, y);
-            const float c1 = swim(x, y, dx, dy, H);
-            const float nw = feed(a.w[tail_i], c0 - c1, M, wmin, wmax);
+            const float c1 = swim(rule, x, y, dx, dy, H, c0, w0);
+            const float nw = feed(w0, c0 - c1, M, wmin, wmax);
             a.x[tail_i] = x;
             a.y[tail_i] = y;
             a.w[tail_i] = nw;
@@ -642,7 +657,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, F
                 a.cur[tail_i] = c1;
             } else {
                 fish_draw(a.S, a.k0, a.k1, tail_i, s + 1u, dx, dy);
-                const float nc = swim(x, y, dx, dy, H);
+                const float nc = swim(rule, x, y, dx, dy, H, c1, nw);
                 best = max(best, mag_bits(c1 - nc));
             }
         }

@@ -40,6 +40,14 @@ __device__ __forceinline__ void stv(float* p, uint64_t g, float4 v) {
     }
 }
 
+// Weights a swim of group g reads: the w column under the weighted rule
+// (otherwise they are not used).
+template <bool kNT>
+__device__ __forceinline__ float4 swim_weights(const SwimRule& r, const float* w, uint64_t g) {
+    if (r.flags & kSwimWeighted) return ldv<kNT>(w, g);
+    return make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+}
+
 // Swim displacements of the four fish of group g (fish 4g..4g+3 of a school
 // with key (k0, k1)) at iteration t: pairs 2g and 2g+1.
 __device__ __forceinline__ void group_draws(float S, uint32_t k0, uint32_t k1, uint64_t g,

@@ -20,7 +20,8 @@ REL_TOL = 1e-6
 def oracle_config(cfg) -> Config:
     return Config(numFish=cfg.n_fish, seed=cfg.seed, pondHalf=cfg.pond_half,
                   swimStep=cfg.swim_step, initWeightLo=cfg.w_init_lo,
-                  initWeightHi=cfg.w_init_hi, weightMin=cfg.w_min, weightMax=cfg.w_max)
+                  initWeightHi=cfg.w_init_hi, weightMin=cfg.w_min, weightMax=cfg.w_max,
+                  swimRule=cfg.swim_rule)
 
 
 def columns_of(school: np.ndarray) -> dict:

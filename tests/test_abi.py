@@ -49,7 +49,7 @@ def test_abi_version_and_strerror():
 
 def cfg(**kw):
     base = dict(n_fish=1000, seed=0, pond_half=100.0, swim_step=0.1, w_init_lo=1.0,
-                w_init_hi=2.0, w_min=1.0, w_max=4.0, reduce_mode=0, history_len=1)
+                w_init_hi=2.0, w_min=1.0, w_max=4.0, reduce_mode=0, history_len=1, swim_rule=0)
     base.update(kw)
     return _lib.fsb_config(*base.values())
 
@@ -72,6 +72,8 @@ def test_workspace_bytes_pure_host():
     dict(swim_step=-0.1), dict(swim_step=float("inf")),
     dict(w_init_lo=2.0, w_init_hi=1.0), dict(w_min=5.0, w_max=4.0),
     dict(w_max=float("nan")), dict(reduce_mode=3), dict(reduce_mode=7), dict(history_len=0),
+    dict(swim_rule=4), dict(swim_rule=2, w_min=0.0), dict(swim_rule=3, w_init_lo=0.0, w_min=0.0),
+    dict(swim_rule=2, w_init_lo=-1.0),
     dict(n_fish=(1 << 40) + 1)])
 def test_bad_config_rejected(bad):
     rc, _ = ws_bytes(cfg(**bad))
@@ -193,6 +195,12 @@ def test_batch_init_rejects_before_any_hip_call():
     assert rc == _lib.FSB_ERR_UNSUPPORTED
     assert L.fsb_batch_run(None, 1, None) == _lib.FSB_ERR_INVALID_ARG
     assert L.fsb_batch_destroy(None) == _lib.FSB_ERR_INVALID_ARG
+
+
+def test_every_swim_rule_is_accepted():
+    for rule in range(4):
+        rc, b = ws_bytes(cfg(swim_rule=rule))
+        assert rc == 0 and b > 0, rule
 
 
 def test_every_reduce_mode_has_a_workspace():

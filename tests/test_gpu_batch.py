@@ -37,7 +37,7 @@ def oracle_school(O, size, seed, steps, common=None):
     ocfg = oracle_config(fsb.FsbConfig(n_fish=size, seed=int(seed), pond_half=cfg.pond_half,
                                        swim_step=cfg.swim_step, w_init_lo=cfg.w_init_lo,
                                        w_init_hi=cfg.w_init_hi, w_min=cfg.w_min,
-                                       w_max=cfg.w_max))
+                                       w_max=cfg.w_max, swim_rule=cfg.swim_rule))
     school = O.init(ocfg)
     m, s, a = O.run(ocfg, school, 0, steps)
     return school, m, s, a
