@@ -185,6 +185,7 @@ int run_fused(fsb_school* h, uint64_t n_steps, uint32_t mode) {
     f.t0 = (uint32_t)h->t;
     f.steps = (uint32_t)n_steps;
     f.naive = naive;
+    f.spin_limit = barrier_spin_limit();
     fused_groups(grid, &f.group_size, &f.groups);
     // Non-temporal streaming once the four live columns outgrow the 256 MB
     // last-level cache (below that, keeping lines cached is faster).

@@ -290,7 +290,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
     const uint32_t S = a.n_schools;
     const float H = a.H, Sw = a.S, wmin = a.wmin, wmax = a.wmax;
     const SwimRule rule{a.rule, a.wmin};
-    const Barrier bar{a.sync, a.ctrl, a.group_size, a.groups};
+    const Barrier bar{a.sync, a.ctrl, a.group_size, a.groups, a.spin_limit};
     uint32_t phase = 0;
     if (threadIdx.x == 0) phase = ld_agent(a.sync + kSyncPhase);
     const uint32_t t0 = uniform(ld_agent(a.step));

@@ -28,6 +28,13 @@ static_assert(sizeof(Ctrl) == 256, "Ctrl is one aligned block");
 
 constexpr uint32_t kErrBarrierTimeout = 1u;
 
+// Polls of a persistent kernel's barrier wait before it gives up (with
+// 2-cycle-group sleeps, well over a second).  The environment variable
+// FSB_BARRIER_SPIN_LIMIT (read once) overrides it, so that tests can force
+// the time-out path from the host; every wait still ends.
+constexpr uint32_t kBarrierSpinLimit = 1u << 22;
+uint32_t barrier_spin_limit();
+
 // Synchronisation words of the persistent kernel's two-level grid barrier,
 // each on its own 256-byte line (word offsets into the sync area).
 constexpr uint32_t kLineWords = 64;
@@ -95,6 +102,7 @@ struct FusedArgs {
     uint32_t group_size;  // blocks per barrier group
     uint32_t groups;      // barrier groups (<= kMaxGroups)
     uint32_t streaming;   // non-temporal loads/stores (state larger than the last-level cache)
+    uint32_t spin_limit;  // barrier polls before giving up
     uint32_t lean;        // keep (x, y, w) live and redo each swim (24 B/fish) instead of
                           // keeping (x, y, w, prev) (32 B/fish)
 };
@@ -156,6 +164,7 @@ struct BatchArgs {
     uint32_t hist_len;
     uint32_t steps;                 // iterations per launch
     uint32_t group_size, groups;    // barrier grouping
+    uint32_t spin_limit;            // barrier polls before giving up
     // Tile schedule.  n_chunks == 0: static, chunk c = tiles [c * static_chunk,
     // (c + 1) * static_chunk) to wavefront c mod W.  Otherwise wavefronts take
     // chunk c = [chunk_start[c], chunk_start[c+1]) in the order an atomic

@@ -414,7 +414,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
     const uint64_t gbase = (uint64_t)blockIdx.x * B + threadIdx.x;
     const uint64_t tail_i = 4 * n4 + threadIdx.x;
     const bool has_tail = blockIdx.x == grid - 1 && tail_i < a.n;
-    const Barrier bar{a.sync, a.ctrl, f.group_size, f.groups};
+    const Barrier bar{a.sync, a.ctrl, f.group_size, f.groups, f.spin_limit};
     uint32_t phase = 0;
     if (threadIdx.x == 0) phase = ld_agent(a.sync + kSyncPhase);
 
@@ -552,7 +552,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, F
     const uint64_t gbase = (uint64_t)blockIdx.x * B + threadIdx.x;
     const uint64_t tail_i = 4 * n4 + threadIdx.x;
     const bool has_tail = blockIdx.x == grid - 1 && tail_i < a.n;
-    const Barrier bar{a.sync, a.ctrl, f.group_size, f.groups};
+    const Barrier bar{a.sync, a.ctrl, f.group_size, f.groups, f.spin_limit};
     uint32_t phase = 0;
     if (threadIdx.x == 0) phase = ld_agent(a.sync + kSyncPhase);
 
@@ -805,6 +805,16 @@ void fused_groups(uint32_t grid, uint32_t* group_size, uint32_t* groups) {
     while ((grid + gs - 1) / gs > kMaxGroups) gs *= 2;
     *group_size = gs;
     *groups = (grid + gs - 1) / gs;
+}
+
+uint32_t barrier_spin_limit() {
+    static const uint32_t limit = [] {
+        const char* v = std::getenv("FSB_BARRIER_SPIN_LIMIT");
+        if (!v || !*v) return kBarrierSpinLimit;
+        const unsigned long x = std::strtoul(v, nullptr, 10);
+        return x >= 1 && x <= kBarrierSpinLimit ? (uint32_t)x : kBarrierSpinLimit;
+    }();
+    return limit;
 }
 
 hipError_t launch_persistent(const void* fn, dim3 grid, dim3 block, void** args,

@@ -103,13 +103,12 @@ struct LaneSums {
 // an error, every block leaves the kernel and the host reports
 // FSB_ERR_DEVICE.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kBarrierSpinLimit = 1u << 22;
-
 struct Barrier {
     uint32_t* sync;       // kSyncWords words, zeroed (except the phase) before the launch
     Ctrl* ctrl;           // error flags
     uint32_t group_size;  // blocks per group
     uint32_t groups;      // number of groups
+    uint32_t spin_limit;  // polls before a wait gives up (kBarrierSpinLimit unless overridden)
 };
 
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
@@ -173,7 +172,7 @@ __device__ __forceinline__ bool barrier_max(const Barrier& b, uint32_t m, uint32
                     ok = 0;
                     break;
                 }
-                if (++spins > kBarrierSpinLimit) {
+                if (++spins > b.spin_limit) {
                     __hip_atomic_fetch_or(&b.ctrl->error, kErrBarrierTimeout, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
                     ok = 0;

@@ -170,3 +170,49 @@ def test_regular_launch_matches_cooperative(torch_cuda, tmp_path):
                                            for k in fsb.COLUMNS]
     for i, w in enumerate(want):
         assert np.array_equal(got[f"arr_{i}"].view(np.uint32), w.view(np.uint32)), i
+
+
+CHILD_TIMEOUT = r"""
+import sys
+sys.path.insert(0, sys.argv[1])
+import paper_2507_20173_amd as fsb
+out = []
+s = fsb.School(fsb.FsbConfig(n_fish=1 << 20, seed=1))
+s.run(20, fsb.FSB_RUN_FUSED)
+try:
+    s.sync()
+    out.append("fused ok")
+except fsb.FsbError as e:
+    out.append(f"fused {e.code} {e}")
+b = fsb.Batch(fsb.FsbConfig(n_fish=0), [1000] * 64, list(range(64)))
+b.run(20, fsb.tuning(1024, 8, 20))
+try:
+    b.sync()
+    out.append("batch ok")
+except fsb.FsbError as e:
+    out.append(f"batch {e.code} {e}")
+print("|".join(out), flush=True)
+"""
+
+
+def test_barrier_timeout_is_reported(torch_cuda):
+    """The persistent kernels' bounded barrier wait, forced to give up from
+    the host (FSB_BARRIER_SPIN_LIMIT=1 in a child process): every block
+    leaves its kernel normally and the host reports FSB_ERR_DEVICE naming the
+    time-out, for one school and for a batch.  The child launches the
+    persistent kernels ordinarily (a cooperative launch from a second process
+    while this one holds the GPU was refused with hipErrorIllegalState); the
+    time-out path is the same either way."""
+    import os
+    import subprocess
+    import sys
+    announce("forced barrier time-out in a child process")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, FSB_BARRIER_SPIN_LIMIT="1", FSB_PERSISTENT_LAUNCH="regular")
+    r = subprocess.run([sys.executable, "-c", CHILD_TIMEOUT, root], env=env, capture_output=True,
+                       text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    fused, batch = r.stdout.strip().splitlines()[-1].split("|")
+    code = str(fsb._lib.FSB_ERR_DEVICE)
+    assert fused.startswith(f"fused {code}") and "timed out" in fused, fused
+    assert batch.startswith(f"batch {code}") and "timed out" in batch, batch
