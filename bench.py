@@ -131,6 +131,11 @@ def fused_vs_plain(n: int, steps: int, label: str):
     import paper_2507_20173_amd as fsb
 
     out = {"workload": label, "n_fish": n, "iterations": steps}
+    probe = fsb.School(fsb.FsbConfig(n_fish=n, seed=0, history_len=1))
+    us, _ = fsb.fsb_barrier_probe(probe.h, 0, 2000)
+    probe.close()
+    del probe
+    out["barrier_us"] = us
     for key, mode in (("fused", fsb.FSB_RUN_FUSED), ("fused_prev", fsb.FSB_RUN_FUSED_PREV),
                       ("fused_lean", fsb.FSB_RUN_FUSED_LEAN)):
         wall, counts, ms = run_form(n, steps, mode)
@@ -144,7 +149,8 @@ def fused_vs_plain(n: int, steps: int, label: str):
                     "launches": int(counts[fsb.FSB_KERNEL_FUSED]),
                     "algorithmic_bytes_per_fish_step": 24 if variant == "lean" else 32,
                     "kernel_achieved_GBs": nbytes / kernel_s / 1e9,
-                    "kernel_hbm_frac": nbytes / kernel_s / 1e9 / HBM_PEAK_GBS}
+                    "kernel_hbm_frac": nbytes / kernel_s / 1e9 / HBM_PEAK_GBS,
+                    "barrier_share": us * 1e-3 / (wall / steps * 1e3)}
     wp, cp, mp = run_form(n, steps, fsb.FSB_RUN_PLAIN)
     out["plain"] = {"value": n * steps / wp, "ms_per_step": wp / steps * 1e3,
                     "algorithmic_bytes_per_fish_step": 52,

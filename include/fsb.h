@@ -328,6 +328,20 @@ int fsb_kernel_times(fsb_school *h, uint64_t counts[FSB_KERNEL_KINDS],
 int fsb_batch_profile_enable(fsb_batch *b, int every);
 int fsb_batch_kernel_times(fsb_batch *b, uint64_t *count, double *ms);
 
+/* Synchronisation cost of the persistent form: one persistent launch of
+ * `grid` blocks of 1024 threads (0 = the grid fsb_run(FSB_RUN_FUSED) uses for
+ * this school) that does n_barriers >= 1 of its grid barriers and nothing
+ * else.  Each barrier carries the school-wide max, the dependency of eat()
+ * (Sec. 2.3.2): barrier k folds max(block index + k) over the grid.  Writes
+ * the average microseconds per barrier (HIP events around the launch, so a
+ * launch's own overhead is spread over n_barriers) and, if out_max is
+ * non-NULL, the max of the last barrier (grid - 1 + n_barriers - 1).  Uses
+ * the handle's workspace and stream, touches no fish; finishes a pending
+ * record first; synchronises.  FSB_ERR_INVALID_ARG if grid exceeds the
+ * co-resident maximum. */
+int fsb_barrier_probe(fsb_school *h, uint32_t grid, uint32_t n_barriers, double *out_us,
+                      uint32_t *out_max);
+
 #ifdef __cplusplus
 }
 #endif

@@ -239,6 +239,16 @@ def fsb_batch_destroy(b) -> None:
     check(lib().fsb_batch_destroy(b))
 
 
+def fsb_barrier_probe(h, grid: int = 0, n_barriers: int = 1000) -> tuple[float, int]:
+    """Microseconds per grid barrier of the persistent kind (grid 0 = the grid
+    fsb_run(FSB_RUN_FUSED) uses for this school), and the max the last
+    barrier published."""
+    us = ctypes.c_double()
+    mx = ctypes.c_uint32()
+    check(lib().fsb_barrier_probe(h, grid, n_barriers, ctypes.byref(us), ctypes.byref(mx)))
+    return us.value, mx.value
+
+
 def fsb_batch_profile_enable(b, every: int = 1) -> None:
     """Time every `every`-th launch (0 = off)."""
     check(lib().fsb_batch_profile_enable(b, int(every)))

@@ -383,6 +383,53 @@ int fsb_profile_enable(fsb_school* h, int every) {
     return FSB_OK;
 }
 
+int fsb_barrier_probe(fsb_school* h, uint32_t grid, uint32_t n_barriers, double* out_us,
+                      uint32_t* out_max) {
+    if (!h || !out_us) return fail(FSB_ERR_INVALID_ARG, "NULL argument");
+    if (n_barriers == 0) return fail(FSB_ERR_INVALID_ARG, "n_barriers must be >= 1");
+    if (h->resident[0] == 0)
+        FSB_HIP_TRY(fused_resident_grid(0, &h->resident[0]), "occupancy query");
+    if (h->resident[0] == 0)
+        return fail(FSB_ERR_UNSUPPORTED, "the persistent kernel cannot be resident on this device");
+    if (grid == 0) grid = fused_grid(h->cfg.n_fish, h->resident[0]);
+    if (grid > h->resident[0])
+        return fail(FSB_ERR_INVALID_ARG, "grid exceeds the co-resident maximum (" +
+                                             std::to_string(h->resident[0]) + " blocks)");
+    int rc = finish_pending(h);
+    if (rc) return rc;
+    FusedArgs f{};
+    f.steps = n_barriers;
+    f.spin_limit = barrier_spin_limit();
+    fused_groups(grid, &f.group_size, &f.groups);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+    if (e == hipSuccess) {
+        e = launch_barrier_probe(h->args, f, grid, h->stream);
+        if (e == hipErrorCooperativeLaunchTooLarge) rc = fail(FSB_ERR_UNSUPPORTED, "probe grid cannot be co-resident");
+        else if (e != hipSuccess) rc = hip_fail(e, "barrier probe launch");
+    } else {
+        rc = hip_fail(e, "hipEvent");
+    }
+    float ms = 0.0f;
+    if (!rc && (e = hipEventRecord(e1, h->stream)) != hipSuccess) rc = hip_fail(e, "hipEventRecord");
+    if (!rc && (e = hipEventSynchronize(e1)) != hipSuccess) rc = hip_fail(e, "hipEventSynchronize");
+    if (!rc && (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) rc = hip_fail(e, "hipEventElapsedTime");
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    rc = check_device_error(h);
+    if (rc) return rc;
+    if (out_max) {
+        FSB_HIP_TRY(hipMemcpyDtoH(out_max, reinterpret_cast<hipDeviceptr_t>(&h->args.ctrl->probe_max),
+                                  sizeof(uint32_t)),
+                    "hipMemcpyDtoH");
+    }
+    *out_us = ms * 1e3 / (double)n_barriers;
+    return FSB_OK;
+}
+
 int fsb_kernel_times(fsb_school* h, uint64_t counts[FSB_KERNEL_KINDS], double ms[FSB_KERNEL_KINDS]) {
     if (!h || !counts || !ms) return fail(FSB_ERR_INVALID_ARG, "NULL argument");
     FSB_HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");

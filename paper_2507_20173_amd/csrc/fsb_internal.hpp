@@ -19,7 +19,7 @@ struct Ctrl {
     uint32_t last_max;        // bits of M of the last iteration whose record is pending
     uint32_t error;           // kernel-reported failure flags (kErr*)
     uint32_t step;            // batches: next iteration (advanced by each launch)
-    uint32_t reserved0;
+    uint32_t probe_max;       // M of the last barrier of a barrier probe
     float naive_acc[2][4];    // float32 atomic sums of the naive and critical modes, slot t & 1
     uint32_t crit_max[2];     // critical mode: max |diff| bits by per-fish atomics, slot t & 1
     uint32_t pad[50];
@@ -125,6 +125,9 @@ uint32_t fused_grid(uint64_t n, uint32_t resident);
 void fused_groups(uint32_t grid, uint32_t* group_size, uint32_t* groups);
 hipError_t launch_fused(const SchoolArgs& a, const FusedArgs& f, uint32_t grid,
                         hipStream_t stream);
+// f.steps grid barriers of the persistent kind and nothing else (instrumentation).
+hipError_t launch_barrier_probe(const SchoolArgs& a, const FusedArgs& f, uint32_t grid,
+                                hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // Batches of independent schools.

@@ -671,6 +671,20 @@ __global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, F
     }
 }
 
+// Instrumentation: f.steps barriers of the persistent kernels' kind with no
+// other work, each folding max(block index + k) over the grid, so the
+// synchronisation a persistent iteration adds can be timed on its own (and
+// its max checked: grid - 1 + f.steps - 1 after the last one).
+__global__ __launch_bounds__(kFusedBlock) void barrier_probe_kernel(SchoolArgs a, FusedArgs f) {
+    __shared__ uint32_t M_sh;
+    const Barrier bar{a.sync, a.ctrl, f.group_size, f.groups, f.spin_limit};
+    uint32_t phase = 0;
+    if (threadIdx.x == 0) phase = ld_agent(a.sync + kSyncPhase);
+    for (uint32_t k = 0; k < f.steps; ++k)
+        if (!barrier_max(bar, blockIdx.x + k, k & 1u, phase, &M_sh)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->probe_max = M_sh;
+}
+
 // Clears the barrier's counters and maxima before a persistent launch (the
 // phase word only ever advances).
 __global__ void reset_sync_kernel(uint32_t* sync) {
@@ -825,6 +839,18 @@ hipError_t launch_persistent(const void* fn, dim3 grid, dim3 block, void** args,
     }();
     if (regular) return hipLaunchKernel(fn, grid, block, args, 0, stream);
     return hipLaunchCooperativeKernel(fn, grid, block, args, 0, stream);
+}
+
+hipError_t launch_barrier_probe(const SchoolArgs& a, const FusedArgs& f, uint32_t grid,
+                                hipStream_t stream) {
+    hipLaunchKernelGGL(reset_sync_kernel, dim3(1), dim3(256), 0, stream, a.sync);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    SchoolArgs sa = a;
+    FusedArgs fa = f;
+    void* args[] = {&sa, &fa};
+    return launch_persistent(reinterpret_cast<const void*>(barrier_probe_kernel), dim3(grid),
+                             dim3(kFusedBlock), args, stream);
 }
 
 hipError_t launch_fused(const SchoolArgs& a, const FusedArgs& f, uint32_t grid,

@@ -216,3 +216,30 @@ def test_barrier_timeout_is_reported(torch_cuda):
     code = str(fsb._lib.FSB_ERR_DEVICE)
     assert fused.startswith(f"fused {code}") and "timed out" in fused, fused
     assert batch.startswith(f"batch {code}") and "timed out" in batch, batch
+
+
+@pytest.mark.parametrize("grid", [1, 2, 16, 17, 100, 0])
+def test_barrier_probe(torch_cuda, O, grid):
+    """The barrier-only probe: each barrier publishes max(block + k) over the
+    grid, so the last of n carries (grid - 1) + (n - 1); the school is left
+    untouched (its next iterations still match the oracle)."""
+    n, k = (1 << 20) + 3, 200
+    announce(f"barrier probe grid={grid}")
+    cfg = fsb.FsbConfig(n_fish=n, seed=13, history_len=3)
+    sch = fsb.School(cfg)
+    sch.run(1, FUSED)
+    us, mx = fsb.fsb_barrier_probe(sch.h, grid, k)
+    g = grid or 256
+    assert mx == (g - 1) + (k - 1), (mx, g)
+    assert 0.0 < us < 1000.0
+    sch.run(2, FUSED)
+    ocfg = oracle_config(cfg)
+    school = O.init(ocfg)
+    m, s, a = O.run(ocfg, school, 0, 3)
+    h = sch.history(0, 3)
+    assert np.array_equal(h["max_delta"], m)
+    assert_columns_equal(sch.state(), school, "after probe")
+    with pytest.raises(fsb.FsbError) as e:
+        fsb.fsb_barrier_probe(sch.h, 1 << 20, 10)
+    assert e.value.code == fsb._lib.FSB_ERR_INVALID_ARG
+    sch.close()
