@@ -24,8 +24,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per fish of each plain kernel (float32 columns).
 BYTES_PER_FISH = {
-    "swim_eval": 12 + 16,  # reads x, y, cur; writes x, y, prev, cur
-    "feed_bary": 20 + 4,   # reads prev, cur, w, x, y; writes w
+    "swim_eval": 8 + 16,   # reads x, y; writes x, y, prev, cur
+    "feed_bary": 16 + 4,   # reads prev, w, x, y; writes w
 }
 # Every PROFILE_EVERY-th launch of each kernel is bracketed by HIP events
 # inside the timed region (sampling keeps the event packets off the others).
@@ -153,8 +153,8 @@ def fused_vs_plain(n: int, steps: int, label: str):
                     "barrier_share": us * 1e-3 / (wall / steps * 1e3)}
     wp, cp, mp = run_form(n, steps, fsb.FSB_RUN_PLAIN)
     out["plain"] = {"value": n * steps / wp, "ms_per_step": wp / steps * 1e3,
-                    "algorithmic_bytes_per_fish_step": 52,
-                    "hbm_frac": 52 * n * steps / wp / 1e9 / HBM_PEAK_GBS}
+                    "algorithmic_bytes_per_fish_step": sum(BYTES_PER_FISH.values()),
+                    "hbm_frac": sum(BYTES_PER_FISH.values()) * n * steps / wp / 1e9 / HBM_PEAK_GBS}
     out["fused_speedup"] = out["fused"]["value"] / out["plain"]["value"]
     return out
 

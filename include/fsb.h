@@ -187,9 +187,11 @@ int fsb_init(const fsb_config *cfg, fsb_state state, void *workspace,
              size_t workspace_bytes, void *stream, fsb_school **out);
 
 /* Wrap existing state (resume from a checkpoint, or a hand-made school) at
- * iteration `t`, without writing the columns.  cur should equal
- * sqrtf(x*x + y*y) and prev the objective before the last swim, as after
- * fsb_step.  Clears the control words.  Asynchronous. */
+ * iteration `t`, without writing the columns.  The state must be one an
+ * iteration could leave: cur == sqrtf(x*x + y*y) in binary32 (each operation
+ * rounded on its own), since the kernels recompute a fish's objective from
+ * its position rather than read cur; prev is the objective before the last
+ * swim.  Clears the control words.  Asynchronous. */
 int fsb_attach(const fsb_config *cfg, fsb_state state, void *workspace,
                size_t workspace_bytes, void *stream, uint64_t t,
                fsb_school **out);

@@ -221,8 +221,8 @@ __device__ __forceinline__ void tile_sums(const BatchArgs& a, LaneSums<kNaive>& 
 // its school's max fetched while the current tile streams.
 // ---------------------------------------------------------------------------
 
-// Prologue work of one tile.  32-byte variant: swim t0 from (x, y, cur),
-// keep (x, y, prev).  Lean variant: a look-ahead swim of t0 for the max only,
+// Prologue work of one tile.  32-byte variant: swim t0 from (x, y), keep
+// (x, y, prev).  Lean variant: a look-ahead swim of t0 for the max only,
 // nothing stored.
 template <int GPL, bool kNT, bool kLean>
 __device__ __forceinline__ uint32_t tile_prologue(const BatchArgs& a, const Tile& T, uint32_t t0,
@@ -239,12 +239,8 @@ __device__ __forceinline__ uint32_t tile_prologue(const BatchArgs& a, const Tile
         if (4 * j + 4 <= T.n_fish) {
             float4 X = ldv<kNT>(a.x, c4), Y = ldv<kNT>(a.y, c4);
             float4 C;
-            if constexpr (kLean) {
 #pragma unroll
-                for (int f = 0; f < 4; ++f) lane_of(C, f) = distance(lane_of(X, f), lane_of(Y, f));
-            } else {
-                C = ldv<kNT>(a.cur, c4);
-            }
+            for (int f = 0; f < 4; ++f) lane_of(C, f) = distance(lane_of(X, f), lane_of(Y, f));
             float4 Wt = swim_weights<kNT>(rule, a.w, c4);
             float dx[4], dy[4];
             group_draws(Sw, T.k0, T.k1, g, t0, dx, dy);
@@ -265,7 +261,7 @@ __device__ __forceinline__ uint32_t tile_prologue(const BatchArgs& a, const Tile
                 float dx, dy;
                 fish_draw(Sw, T.k0, T.k1, 4 * g + f, t0, dx, dy);
                 float x = a.x[o], y = a.y[o];
-                const float c = kLean ? distance(x, y) : a.cur[o];
+                const float c = distance(x, y);
                 const float wt = (rule.flags & kSwimWeighted) ? a.w[o] : 1.0f;
                 const float nc = swim(rule, x, y, dx, dy, H, c, wt);
                 best = max(best, mag_bits(c - nc));

@@ -1,19 +1,19 @@
 // fsb_kernels.hip -- HIP kernels of the FSB iteration for gfx950 (MI355X).
 //
 // Plain iteration t = two streaming passes over the SoA columns:
-//   swim pass  (reads x, y, cur; writes x, y, prev, cur; 28 B/fish)
+//   swim pass  (reads x, y; writes x, y, prev, cur; 24 B/fish)
 //     draws, swim + pond clamp, objective, |diff|; each block stores its max
 //     |diff| bit pattern (non-negative floats order like their bits, so the
 //     max is exact and independent of order).  Block 0 first writes the
 //     pending record of the previous iteration from its block partials.
-//   feed pass  (reads prev, cur, w, x, y; writes w; 24 B/fish)
+//   feed pass  (reads prev, w, x, y; writes w; 20 B/fish)
 //     every block reduces the swim pass's block maxima to M, feeds, and
 //     accumulates sum w, sum w*x, sum w*y per lane in compensated float32,
 //     merges lanes with TwoSum and waves in binary64: one binary64 partial
 //     per block.
 // Persistent iteration (one cooperative launch for many iterations, one grid
 // barrier per iteration; 32 B/fish per iteration):
-//   prologue   swim t0 from (x, y, cur), keep (x, y, prev), block max -> M_t0
+//   prologue   swim t0 from (x, y), keep (x, y, prev), block max -> M_t0
 //   sweep s    read (x, y, w, prev); cur = |p| recomputed; feed with M_s;
 //              partial sums of s; then swim s+1 and its max -> M_{s+1};
 //              write (x, y, w, prev); grid barrier.  The last sweep writes
@@ -23,6 +23,10 @@
 // folds its |diff| into one shared max word and its three terms into three
 // shared float32 sums with its own device-scope atomic, the way a critical
 // section entered once per fish serialises the update; no tree at all.
+// No kernel reads cur: a fish's objective is the distance of its position,
+// so it is recomputed from (x, y) with the same binary32 operations that
+// produced the stored value (the state after every iteration satisfies
+// cur == sqrtf(x*x + y*y)); cur is only written.
 // Records are combined in a fixed order, so every sum is deterministic for a
 // given launch shape.  Each thread handles groups of four consecutive fish
 // (one float4 per column): two Philox calls, for fish pairs 2g and 2g+1.
@@ -225,10 +229,11 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(SchoolArgs a, uint32_t 
 // ---------------------------------------------------------------------------
 // Plain swim pass.
 // ---------------------------------------------------------------------------
-// Cache policy of the plain passes (chosen on the host from the footprint):
-// kCached keeps every column in the last-level cache, kStreamW streams only
-// w (touched by the feed pass alone) so x, y, prev, cur stay resident, and
-// kStreamAll streams every column once even four of them cannot fit.
+// Cache policy of the plain passes (chosen on the host from the footprint).
+// cur is write-only and always streamed.  kCached keeps x, y, prev and w in
+// the last-level cache, kStreamW streams w too (touched by the feed pass
+// alone) so x, y, prev stay resident, and kStreamAll streams every column
+// once even those three cannot fit.
 constexpr int kCached = 0, kStreamW = 1, kStreamAll = 2;
 
 template <bool kInject, int kPolicy, bool kCritical>
@@ -245,14 +250,13 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
     uint32_t best = 0u;
     for (uint64_t g0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g0 < n4;
          g0 += kUnroll * stride) {
-        float4 X[kUnroll], Y[kUnroll], C[kUnroll], Wt[kUnroll];
+        float4 X[kUnroll], Y[kUnroll], Wt[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const uint64_t g = g0 + u * stride;
             if (g < n4) {
                 X[u] = ldv<NT>(a.x, g);
                 Y[u] = ldv<NT>(a.y, g);
-                C[u] = ldv<NT>(a.cur, g);
                 Wt[u] = swim_weights<NT>(rule, a.w, g);
             }
         }
@@ -268,19 +272,20 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
             } else {
                 group_draws(a.S, a.k0, a.k1, g, s.t, dx, dy);
             }
-            float4 nx = X[u], ny = Y[u], nc;
+            float4 nx = X[u], ny = Y[u], c, nc;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
+                lane_of(c, k) = distance(lane_of(nx, k), lane_of(ny, k));
                 lane_of(nc, k) = swim(rule, lane_of(nx, k), lane_of(ny, k), dx[k], dy[k], H,
-                                      lane_of(C[u], k), lane_of(Wt[u], k));
-                const uint32_t d = mag_bits(lane_of(C[u], k) - lane_of(nc, k));
+                                      lane_of(c, k), lane_of(Wt[u], k));
+                const uint32_t d = mag_bits(lane_of(c, k) - lane_of(nc, k));
                 if constexpr (kCritical) lane_atomic_max(crit, d);
                 else best = max(best, d);
             }
             stv<NT>(a.x, g, nx);
             stv<NT>(a.y, g, ny);
-            stv<NT>(a.prev, g, C[u]);
-            stv<NT>(a.cur, g, nc);
+            stv<NT>(a.prev, g, c);
+            stv<true>(a.cur, g, nc);
         }
     }
     if (blockIdx.x == gridDim.x - 1) {
@@ -294,7 +299,7 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
                 fish_draw(a.S, a.k0, a.k1, i, s.t, dx, dy);
             }
             float x = a.x[i], y = a.y[i];
-            const float c = a.cur[i];
+            const float c = distance(x, y);
             const float wt = (rule.flags & kSwimWeighted) ? a.w[i] : 1.0f;
             const float nc = swim(rule, x, y, dx, dy, H, c, wt);
             const uint32_t d = mag_bits(c - nc);
@@ -358,13 +363,12 @@ __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArg
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t g0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g0 < n4;
          g0 += kUnroll * stride) {
-        float4 P[kUnroll], C[kUnroll], W[kUnroll], X[kUnroll], Y[kUnroll];
+        float4 P[kUnroll], W[kUnroll], X[kUnroll], Y[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const uint64_t g = g0 + u * stride;
             if (g < n4) {
                 P[u] = ldv<NT>(a.prev, g);
-                C[u] = ldv<NT>(a.cur, g);
                 W[u] = ldv<NTW>(a.w, g);
                 X[u] = ldv<NT>(a.x, g);
                 Y[u] = ldv<NT>(a.y, g);
@@ -377,7 +381,8 @@ __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArg
             float4 nw;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const float diff = lane_of(P[u], k) - lane_of(C[u], k);
+                const float c = distance(lane_of(X[u], k), lane_of(Y[u], k));
+                const float diff = lane_of(P[u], k) - c;
                 lane_of(nw, k) = feed(lane_of(W[u], k), diff, M, wmin, wmax);
                 add(lane_of(nw, k), lane_of(X[u], k), lane_of(Y[u], k));
             }
@@ -387,10 +392,11 @@ __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArg
     if (blockIdx.x == gridDim.x - 1) {
         const uint64_t i = 4 * n4 + threadIdx.x;
         if (i < a.n) {
-            const float diff = a.prev[i] - a.cur[i];
+            const float x = a.x[i], y = a.y[i];
+            const float diff = a.prev[i] - distance(x, y);
             const float nw = feed(a.w[i], diff, M, wmin, wmax);
             a.w[i] = nw;
-            add(nw, a.x[i], a.y[i]);
+            add(nw, x, y);
         }
     }
     if constexpr (kRed != kRedCritical) block_sums<kNaive>(a, ls, s.t);
@@ -422,12 +428,13 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
     {
         uint32_t best = 0u;
         for (uint64_t g = gbase; g < n4; g += stride) {
-            float4 X = ldv<kNT>(a.x, g), Y = ldv<kNT>(a.y, g), C = ldv<kNT>(a.cur, g);
+            float4 X = ldv<kNT>(a.x, g), Y = ldv<kNT>(a.y, g), C;
             float4 Wt = swim_weights<kNT>(rule, a.w, g);
             float dx[4], dy[4];
             group_draws(a.S, a.k0, a.k1, g, f.t0, dx, dy);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
+                lane_of(C, q) = distance(lane_of(X, q), lane_of(Y, q));
                 const float nc = swim(rule, lane_of(X, q), lane_of(Y, q), dx[q], dy[q], H,
                                       lane_of(C, q), lane_of(Wt, q));
                 best = max(best, mag_bits(lane_of(C, q) - nc));
@@ -440,7 +447,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
             float dx, dy;
             fish_draw(a.S, a.k0, a.k1, tail_i, f.t0, dx, dy);
             float x = a.x[tail_i], y = a.y[tail_i];
-            const float c = a.cur[tail_i];
+            const float c = distance(x, y);
             const float wt = (rule.flags & kSwimWeighted) ? a.w[tail_i] : 1.0f;
             const float nc = swim(rule, x, y, dx, dy, H, c, wt);
             best = max(best, mag_bits(c - nc));
@@ -718,8 +725,8 @@ hipError_t launch_init(const SchoolArgs& a, float wlo, float whi, hipStream_t st
 constexpr uint64_t kLastLevelCache = 256ull << 20;
 
 int plain_policy(uint64_t n) {
-    if (n * 20ull <= kLastLevelCache) return kCached;
-    if (n * 16ull <= kLastLevelCache) return kStreamW;
+    if (n * 16ull <= kLastLevelCache) return kCached;
+    if (n * 12ull <= kLastLevelCache) return kStreamW;
     return kStreamAll;
 }
 
