@@ -148,13 +148,13 @@ int do_step(fsb_school* h, const float* dx, const float* dy) {
                    [&] { return launch_swim_eval(h->args, s, h->stream); });
     if (rc) return rc;
     h->pending = false;
-    const uint32_t feed_grid = plain_grid(h->cfg.n_fish);
+    const uint32_t fgrid = feed_grid(h->cfg.n_fish);
     rc = timed(h, FSB_KERNEL_FEED_BARY, "feed pass launch",
-               [&] { return launch_feed_bary(h->args, s, feed_grid, h->stream); });
+               [&] { return launch_feed_bary(h->args, s, fgrid, h->stream); });
     if (rc) return rc;
     h->pending = true;
     h->pending_t = (uint32_t)h->t;
-    h->pending_grid = feed_grid;
+    h->pending_grid = fgrid;
     h->t += 1;
     h->has_result = true;
     return FSB_OK;

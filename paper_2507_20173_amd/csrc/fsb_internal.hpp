@@ -109,7 +109,8 @@ struct FusedArgs {
 
 // Launchers (fsb_kernels.hip).  All enqueue on `stream` and return the HIP
 // status of the launch.
-uint32_t plain_grid(uint64_t n);
+uint32_t plain_grid(uint64_t n);  // swim pass (and init)
+uint32_t feed_grid(uint64_t n);   // feed pass
 hipError_t launch_reset(const SchoolArgs& a, hipStream_t stream);
 hipError_t launch_init(const SchoolArgs& a, float wlo, float whi, hipStream_t stream);
 hipError_t launch_swim_eval(const SchoolArgs& a, const StepArgs& s, hipStream_t stream);

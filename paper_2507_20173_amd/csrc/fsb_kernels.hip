@@ -40,8 +40,15 @@
 namespace fsb {
 
 constexpr int kBlock = 256;
-constexpr uint32_t kPlainGridCap = 2048;  // 8 blocks of 4 waves per CU x 256 CUs
-constexpr int kUnroll = 2;                // groups in flight per thread
+constexpr int kUnroll = 2;  // groups in flight per thread (persistent kernels)
+// Plain passes: grid caps and groups in flight per thread, measured at
+// N = 2^24 (swim caps 2048-8192 within 1.5%; feed best at 512-768 blocks,
+// 20% slower at 256, 5% at 1024-2048: each of its blocks first reads every
+// swim block's max).
+constexpr uint32_t kSwimGridCap = 4096;
+constexpr uint32_t kFeedGridCap = 512;
+constexpr int kSwimUnroll = 2;
+constexpr int kFeedUnroll = 1;
 
 __device__ __forceinline__ double* partial_slot(const SchoolArgs& a, uint32_t t, int k) {
     return a.partials + ((size_t)(t & 1u) * 3 + k) * kMaxGrid;
@@ -249,10 +256,10 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     uint32_t best = 0u;
     for (uint64_t g0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g0 < n4;
-         g0 += kUnroll * stride) {
-        float4 X[kUnroll], Y[kUnroll], Wt[kUnroll];
+         g0 += kSwimUnroll * stride) {
+        float4 X[kSwimUnroll], Y[kSwimUnroll], Wt[kSwimUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < kSwimUnroll; ++u) {
             const uint64_t g = g0 + u * stride;
             if (g < n4) {
                 X[u] = ldv<NT>(a.x, g);
@@ -261,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
             }
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < kSwimUnroll; ++u) {
             const uint64_t g = g0 + u * stride;
             if (g >= n4) break;
             float dx[4], dy[4];
@@ -335,7 +342,21 @@ __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArg
     if constexpr (kRed == kRedCritical) {
         mb = a.ctrl->crit_max[s.t & 1u];
     } else {
-        for (uint32_t b = threadIdx.x; b < s.swim_grid; b += kBlock) mb = max(mb, a.blockmax[b]);
+        // every block reads the swim pass's block maxima: four per load, all
+        // loads of a thread issued before any is used
+        const uint32_t n_vec = s.swim_grid / 4;
+        const uint4* bm4 = reinterpret_cast<const uint4*>(a.blockmax);
+        constexpr uint32_t kPer = kMaxGrid / 4 / kBlock;  // vector loads per thread, at most
+        uint4 v[kPer];
+#pragma unroll
+        for (uint32_t j = 0; j < kPer; ++j) {
+            const uint32_t i = threadIdx.x + j * kBlock;
+            v[j] = i < n_vec ? bm4[i] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kPer; ++j) mb = max(mb, max(max(v[j].x, v[j].y), max(v[j].z, v[j].w)));
+        for (uint32_t b = 4 * n_vec + threadIdx.x; b < s.swim_grid; b += kBlock)
+            mb = max(mb, a.blockmax[b]);
         mb = block_max(mb);
     }
     if (threadIdx.x == 0) {
@@ -362,10 +383,10 @@ __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArg
     const uint64_t n4 = a.n >> 2;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t g0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g0 < n4;
-         g0 += kUnroll * stride) {
-        float4 P[kUnroll], W[kUnroll], X[kUnroll], Y[kUnroll];
+         g0 += kFeedUnroll * stride) {
+        float4 P[kFeedUnroll], W[kFeedUnroll], X[kFeedUnroll], Y[kFeedUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < kFeedUnroll; ++u) {
             const uint64_t g = g0 + u * stride;
             if (g < n4) {
                 P[u] = ldv<NT>(a.prev, g);
@@ -375,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArg
             }
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < kFeedUnroll; ++u) {
             const uint64_t g = g0 + u * stride;
             if (g >= n4) break;
             float4 nw;
@@ -702,13 +723,16 @@ __global__ void reset_sync_kernel(uint32_t* sync) {
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-uint32_t plain_grid(uint64_t n) {
+static uint32_t capped_grid(uint64_t n, uint32_t cap) {
     const uint64_t groups = n >> 2;
     uint64_t g = (groups + kBlock - 1) / kBlock;
     if (g < 1) g = 1;
-    if (g > kPlainGridCap) g = kPlainGridCap;
+    if (g > cap) g = cap;
     return (uint32_t)g;
 }
+
+uint32_t plain_grid(uint64_t n) { return capped_grid(n, kSwimGridCap); }
+uint32_t feed_grid(uint64_t n) { return capped_grid(n, kFeedGridCap); }
 
 hipError_t launch_reset(const SchoolArgs& a, hipStream_t stream) {
     hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, stream, a.ctrl);
