@@ -122,7 +122,7 @@ def persistent_bytes(variant: str, n: int, steps: int) -> int:
     """Algorithmic bytes of one persistent launch of `steps` iterations."""
     if variant == "lean":  # prologue reads x, y; sweeps 24 B; the last also writes prev, cur
         return n * (8 + 24 * steps + 8)
-    return n * (24 + 32 * (steps - 1) + 24)  # prologue 24 B, sweeps 32 B, last sweep 24 B
+    return n * (20 + 32 * (steps - 1) + 24)  # prologue 20 B, sweeps 32 B, last sweep 24 B
 
 
 def fused_vs_plain(n: int, steps: int, label: str):
@@ -390,7 +390,7 @@ def batched_form(n_schools: int, steps: int, probe_steps: int, baseline_schools:
     K = min(tune.steps_per_launch, steps)
     lean = tune.variant == fsb.FSB_RUN_FUSED_LEAN
     bytes_total = (total * (8 * launches + 24 * steps + 8 * launches) if lean
-                   else total * (24 * launches + 32 * (steps - launches) + 24 * launches))
+                   else total * (20 * launches + 32 * (steps - launches) + 24 * launches))
 
     # baseline: the first schools one by one, fsb_step per iteration
     base_fish, base_wall = 0, 0.0
