@@ -101,7 +101,8 @@ typedef struct fsb_config {
     uint64_t n_fish;      /* fish in the school, >= 1 */
     uint64_t seed;        /* Philox key */
     float pond_half;      /* H > 0: the pond is [-H, H]^2 (Sec. 2.1.2: 200x200 -> 100) */
-    float swim_step;      /* S >= 0: per-axis displacement in [-S, S); 0 = zero swim */
+    float swim_step;      /* S: per-axis displacement in [-S, S); 0 (zero swim) or
+                             >= 2^-103 (so that S * 2^-23 is exact) */
     float w_init_lo;      /* initial weights in [lo, hi], lo <= hi */
     float w_init_hi;
     float w_min;          /* weight limits applied by feeding, w_min <= w_max */

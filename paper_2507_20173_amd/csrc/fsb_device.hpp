@@ -20,7 +20,9 @@ constexpr int kWave = 64;
 // lo(A*c0)); the key moves on by the two Weyl constants after each round.
 // Each product is written as one 32x32->64 multiply, which gfx950 does in a
 // single v_mad_u64_u32 (measured 1.44x the throughput of separate mul_lo /
-// mul_hi).  The key is uniform across a launch, so its schedule lives in
+// mul_hi), and each three-way XOR is one v_bitop3_b32 (truth table 0x96:
+// set for an odd number of set inputs), where the compiler would emit two
+// v_xor_b32.  The key is uniform across a launch, so its schedule lives in
 // SGPRs.
 // ---------------------------------------------------------------------------
 struct Words {
@@ -35,9 +37,9 @@ __device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     for (int round = 0; round < 10; ++round) {
         const uint64_t pA = (uint64_t)A * c0;
         const uint64_t pB = (uint64_t)B * c2;
-        c0 = (uint32_t)(pB >> 32) ^ c1 ^ k0;
+        c0 = __builtin_amdgcn_bitop3_b32((uint32_t)(pB >> 32), c1, k0, 0x96);
         c1 = (uint32_t)pB;
-        c2 = (uint32_t)(pA >> 32) ^ c3 ^ k1;
+        c2 = __builtin_amdgcn_bitop3_b32((uint32_t)(pA >> 32), c3, k1, 0x96);
         c3 = (uint32_t)pA;
         k0 += WA;
         k1 += WB;
@@ -66,8 +68,20 @@ __device__ __forceinline__ float unit(uint32_t r) {
     return (float)(r >> 8) * 0x1p-24f;
 }
 
+// A swim displacement S (x) v(r) in one fused multiply-add.  With
+// S23 = S * 2^-23 (exact: the host requires S = 0 or S >= 2^-103) and
+// k = r >> 8 (exact in binary32), S23 * k - S equals S * v(r) as a real
+// number, and the fma rounds it once, as the product S (x) v(r) does: the
+// same binary32 value in three instructions instead of five.
+__device__ __forceinline__ float swim_delta(float S23, float negS, uint32_t r) {
+    return __builtin_fmaf(S23, (float)(r >> 8), negS);
+}
+
+// min(max(v, lo), hi) as one v_med3_f32: the median of (v, lo, hi) is that
+// clamp whenever lo <= hi (the host checks every pair of limits) and v is not
+// a NaN (positions and weights are finite).
 __device__ __forceinline__ float clamp_to(float v, float lo, float hi) {
-    return fminf(fmaxf(v, lo), hi);
+    return __builtin_amdgcn_fmed3f(v, lo, hi);
 }
 
 // Euclidean distance from the pond centre; each op rounded on its own.

@@ -48,6 +48,8 @@ inline int check_config(const fsb_config* c, bool need_fish) {
         return fail(FSB_ERR_INVALID_ARG, "pond_half must be finite and > 0");
     if (!(std::isfinite(c->swim_step) && c->swim_step >= 0.0f))
         return fail(FSB_ERR_INVALID_ARG, "swim_step must be finite and >= 0");
+    if (c->swim_step != 0.0f && c->swim_step < 0x1p-103f)
+        return fail(FSB_ERR_INVALID_ARG, "swim_step must be 0 or at least 2^-103");
     if (!(std::isfinite(c->w_init_lo) && std::isfinite(c->w_init_hi) && c->w_init_lo <= c->w_init_hi))
         return fail(FSB_ERR_INVALID_ARG, "need finite w_init_lo <= w_init_hi");
     if (!(std::isfinite(c->w_min) && std::isfinite(c->w_max) && c->w_min <= c->w_max))

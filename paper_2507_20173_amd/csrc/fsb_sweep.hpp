@@ -54,10 +54,11 @@ __device__ __forceinline__ void group_draws(float S, uint32_t k0, uint32_t k1, u
                                             uint32_t t, float dx[4], float dy[4]) {
     const Words p0 = pair_words(2 * g, t, kDomainSwim, k0, k1);
     const Words p1 = pair_words(2 * g + 1, t, kDomainSwim, k0, k1);
-    dx[0] = S * signed_unit(p0.r0); dy[0] = S * signed_unit(p0.r1);
-    dx[1] = S * signed_unit(p0.r2); dy[1] = S * signed_unit(p0.r3);
-    dx[2] = S * signed_unit(p1.r0); dy[2] = S * signed_unit(p1.r1);
-    dx[3] = S * signed_unit(p1.r2); dy[3] = S * signed_unit(p1.r3);
+    const float S23 = S * 0x1p-23f, nS = -S;
+    dx[0] = swim_delta(S23, nS, p0.r0); dy[0] = swim_delta(S23, nS, p0.r1);
+    dx[1] = swim_delta(S23, nS, p0.r2); dy[1] = swim_delta(S23, nS, p0.r3);
+    dx[2] = swim_delta(S23, nS, p1.r0); dy[2] = swim_delta(S23, nS, p1.r1);
+    dx[3] = swim_delta(S23, nS, p1.r2); dy[3] = swim_delta(S23, nS, p1.r3);
 }
 
 // Swim displacement of fish i of a school at iteration t.
@@ -65,8 +66,9 @@ __device__ __forceinline__ void fish_draw(float S, uint32_t k0, uint32_t k1, uin
                                           uint32_t t, float& dx, float& dy) {
     const Words p = pair_words(i >> 1, t, kDomainSwim, k0, k1);
     const bool odd = i & 1;
-    dx = S * signed_unit(odd ? p.r2 : p.r0);
-    dy = S * signed_unit(odd ? p.r3 : p.r1);
+    const float S23 = S * 0x1p-23f, nS = -S;
+    dx = swim_delta(S23, nS, odd ? p.r2 : p.r0);
+    dy = swim_delta(S23, nS, odd ? p.r3 : p.r1);
 }
 
 // Per-lane sums of the barycentre: compensated (TwoSum) or plain float32.

@@ -69,7 +69,7 @@ def test_workspace_bytes_pure_host():
 
 @pytest.mark.parametrize("bad", [
     dict(pond_half=0.0), dict(pond_half=float("nan")), dict(pond_half=-1.0),
-    dict(swim_step=-0.1), dict(swim_step=float("inf")),
+    dict(swim_step=-0.1), dict(swim_step=float("inf")), dict(swim_step=1e-35),
     dict(w_init_lo=2.0, w_init_hi=1.0), dict(w_min=5.0, w_max=4.0),
     dict(w_max=float("nan")), dict(reduce_mode=3), dict(reduce_mode=7), dict(history_len=0),
     dict(swim_rule=4), dict(swim_rule=2, w_min=0.0), dict(swim_rule=3, w_init_lo=0.0, w_min=0.0),

@@ -1,7 +1,10 @@
 """Our own gfx950 assembly keeps the binary32 contract: the only fused
 multiply-adds in any kernel are those inside the correctly rounded sqrtf
 (two residual checks per v_sqrt_f32) and division (five per
-v_div_fixup_f32) expansions, and no packed-FP32 instruction is emitted."""
+v_div_fixup_f32) expansions, plus the swim displacements' explicit
+fma(S * 2^-23, r >> 8, -S), which rounds once exactly as S * v(r) does (its
+addend is the uniform -S, a negated SGPR); and no packed-FP32 instruction is
+emitted."""
 import re
 
 import pytest
@@ -36,13 +39,21 @@ def test_kernels_found(kernels):
         assert k in names
 
 
+DRAW_FMA = r"\bv_fma_f32\s+v\d+,\s*v\d+,\s*v\d+,\s*-s\d+"
+
+
 def test_no_contraction_outside_sqrt_and_div(kernels):
+    draws_seen = 0
     for name, body in kernels.items():
         fma = count(body, r"\bv_(fma|fmac|mac|mad)_f32|\bv_fma_mix")
+        draws = count(body, DRAW_FMA)
         sqrt = count(body, r"\bv_sqrt_f32")
         div = count(body, r"\bv_div_fixup_f32")
-        assert fma == 2 * sqrt + 5 * div, (
-            f"{name}: {fma} fused ops vs {sqrt} sqrt and {div} div expansions")
+        assert fma - draws == 2 * sqrt + 5 * div, (
+            f"{name}: {fma} fused ops ({draws} draws) vs {sqrt} sqrt and {div} div expansions")
+        assert draws % 2 == 0, f"{name}: draws come in (dx, dy) pairs"
+        draws_seen += draws
+    assert draws_seen > 0
 
 
 def test_no_packed_fp32(kernels):
