@@ -345,6 +345,14 @@ int fsb_batch_kernel_times(fsb_batch *b, uint64_t *count, double *ms);
 int fsb_barrier_probe(fsb_school *h, uint32_t grid, uint32_t n_barriers, double *out_us,
                       uint32_t *out_max);
 
+/* out[i] = the square root every kernel uses for the objective (Sec. 2.1.1:
+ * Euclidean distance), i < n: a correctly rounded binary32 sqrt built from
+ * the hardware estimate and one residual correction, with the general
+ * expansion below 2^-96.  in and out are device arrays of n floats, 4-byte
+ * aligned (caller-owned); enqueued on `stream`, asynchronous.  For testing
+ * it against IEEE sqrt. */
+int fsb_eval_sqrt(const float *in, float *out, uint64_t n, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

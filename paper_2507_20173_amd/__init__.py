@@ -249,6 +249,16 @@ def fsb_barrier_probe(h, grid: int = 0, n_barriers: int = 1000) -> tuple[float, 
     return us.value, mx.value
 
 
+def fsb_eval_sqrt(inp, out, stream=None) -> None:
+    """out = the kernels' binary32 square root of inp (device float32 tensors
+    of equal length)."""
+    import torch
+    assert inp.dtype == torch.float32 and out.dtype == torch.float32
+    assert inp.numel() == out.numel() and inp.is_contiguous() and out.is_contiguous()
+    s = torch.cuda.current_stream().cuda_stream if stream is None else stream
+    check(lib().fsb_eval_sqrt(_ptr(inp), _ptr(out), inp.numel(), s))
+
+
 def fsb_batch_profile_enable(b, every: int = 1) -> None:
     """Time every `every`-th launch (0 = off)."""
     check(lib().fsb_batch_profile_enable(b, int(every)))

@@ -112,6 +112,7 @@ PROTOTYPES = {
     "fsb_batch_destroy": (_I, [_P]),
     "fsb_batch_profile_enable": (_I, [_P, _I]),
     "fsb_barrier_probe": (_I, [_P, _U32, _U32, _DP, ctypes.POINTER(_U32)]),
+    "fsb_eval_sqrt": (_I, [_P, _P, _U64, _P]),
     "fsb_batch_kernel_times": (_I, [_P, ctypes.POINTER(_U64), _DP]),
 }
 

@@ -430,6 +430,14 @@ int fsb_barrier_probe(fsb_school* h, uint32_t grid, uint32_t n_barriers, double*
     return FSB_OK;
 }
 
+int fsb_eval_sqrt(const float* in, float* out, uint64_t n, void* stream) {
+    if (n == 0) return FSB_OK;
+    if (!in || !out) return fail(FSB_ERR_INVALID_ARG, "NULL array");
+    if (!aligned(in, 4) || !aligned(out, 4)) return fail(FSB_ERR_INVALID_ARG, "arrays must be 4-byte aligned");
+    FSB_HIP_TRY(launch_eval_sqrt(in, out, n, static_cast<hipStream_t>(stream)), "sqrt launch");
+    return FSB_OK;
+}
+
 int fsb_kernel_times(fsb_school* h, uint64_t counts[FSB_KERNEL_KINDS], double ms[FSB_KERNEL_KINDS]) {
     if (!h || !counts || !ms) return fail(FSB_ERR_INVALID_ARG, "NULL argument");
     FSB_HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");

@@ -126,6 +126,8 @@ uint32_t fused_grid(uint64_t n, uint32_t resident);
 void fused_groups(uint32_t grid, uint32_t* group_size, uint32_t* groups);
 hipError_t launch_fused(const SchoolArgs& a, const FusedArgs& f, uint32_t grid,
                         hipStream_t stream);
+// out[i] = the kernels' square root of in[i] (instrumentation).
+hipError_t launch_eval_sqrt(const float* in, float* out, uint64_t n, hipStream_t stream);
 // f.steps grid barriers of the persistent kind and nothing else (instrumentation).
 hipError_t launch_barrier_probe(const SchoolArgs& a, const FusedArgs& f, uint32_t grid,
                                 hipStream_t stream);

@@ -713,6 +713,14 @@ __global__ __launch_bounds__(kFusedBlock) void barrier_probe_kernel(SchoolArgs a
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->probe_max = M_sh;
 }
 
+// The kernels' square root over an array (instrumentation and tests).
+__global__ __launch_bounds__(kBlock) void eval_sqrt_kernel(const float* in, float* out,
+                                                            uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+        out[i] = sqrt_rn(in[i]);
+}
+
 // Clears the barrier's counters and maxima before a persistent launch (the
 // phase word only ever advances).
 __global__ void reset_sync_kernel(uint32_t* sync) {
@@ -870,6 +878,14 @@ hipError_t launch_persistent(const void* fn, dim3 grid, dim3 block, void** args,
     }();
     if (regular) return hipLaunchKernel(fn, grid, block, args, 0, stream);
     return hipLaunchCooperativeKernel(fn, grid, block, args, 0, stream);
+}
+
+hipError_t launch_eval_sqrt(const float* in, float* out, uint64_t n, hipStream_t stream) {
+    uint64_t blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(eval_sqrt_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, in, out, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_barrier_probe(const SchoolArgs& a, const FusedArgs& f, uint32_t grid,
