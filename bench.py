@@ -46,11 +46,11 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, n_fish: int):
+def measured_traffic(kernel: str, n_fish: int, path: str = TRAFFIC_FILE):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
     if it was taken from the current kernel sources."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             t = json.load(fh)
     except OSError:
         return None
@@ -472,7 +472,7 @@ def _counter_rows(directory: str, counter: str):
     return rows
 
 
-def ingest_counters(fetch_dir: str, write_dir: str, n_fish: int) -> dict:
+def ingest_counters(fetch_dir: str, write_dir: str, n_fish: int, out_path: str = TRAFFIC_FILE) -> dict:
     """Per-launch HBM bytes of the plain kernels from a FETCH_SIZE run and a
     WRITE_SIZE run (KiB per dispatch), each scaled by what the same counter
     reads for the calibration copy of known size."""
@@ -502,7 +502,7 @@ def ingest_counters(fetch_dir: str, write_dir: str, n_fish: int) -> dict:
             out["kernels"][key] = {"fetch_bytes_per_launch": rd, "write_bytes_per_launch": wr,
                                    "bytes_per_launch": rd + wr,
                                    "algorithmic_bytes_per_launch": BYTES_PER_FISH[key] * n_fish}
-    with open(TRAFFIC_FILE, "w") as fh:
+    with open(out_path, "w") as fh:
         json.dump(out, fh, indent=1)
     return out
 
@@ -532,12 +532,17 @@ def main() -> int:
     ap.add_argument("--rules-steps", type=int, default=300)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run known-size device copies first (for counter scaling)")
+    ap.add_argument("--traffic-out", default=TRAFFIC_FILE,
+                    help="where --ingest-counters writes the per-launch traffic")
+    ap.add_argument("--cpu-baseline-seconds", type=float, default=12.0,
+                    help="budget of the oracle's timed sample")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the plain kernels' measured HBM traffic from two rocprofv3 "
                          "--pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
     args = ap.parse_args()
     if args.ingest_counters:
-        print(json.dumps(ingest_counters(*args.ingest_counters, args.n_fish), indent=1))
+        print(json.dumps(ingest_counters(*args.ingest_counters, args.n_fish, args.traffic_out),
+                         indent=1))
         return 0
     if args.gpus != 1:
         log(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -603,7 +608,7 @@ def main() -> int:
         line["forms"]["construct_ablation"] = ablation_form(
             [int(v) for v in args.ablation_sizes.split(",")], args.ablation_checked_steps)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(n)
+        line["cpu_baseline"] = cpu_baseline(n, args.cpu_baseline_seconds)
     print(json.dumps(line), flush=True)
     return 0
 

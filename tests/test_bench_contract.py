@@ -1,0 +1,93 @@
+"""bench.py's host logic: the one-GPU refusal, the counter ingestion that
+scales rocprofv3 FETCH_SIZE / WRITE_SIZE by a known-size copy, the digest
+that voids stale traffic figures, and (on a GPU) the shape of the JSON
+line."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def _counter_csv(path, counter, rows):
+    os.makedirs(path, exist_ok=True)
+    with open(os.path.join(path, "x_counter_collection.csv"), "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for k, v in rows:
+            w.writerow({"Kernel_Name": k, "Counter_Name": counter, "Counter_Value": v})
+
+
+def test_counter_ingestion_scales_by_the_copy(tmp_path):
+    n = 1 << 20
+    copy_kib = bench.COPY_REPS * bench.COPY_FLOATS * 4 / 1024
+    # FETCH_SIZE reads half of the copy's bytes, WRITE_SIZE all of them (as
+    # measured on MI355X); the library's own small read-back is ignored
+    fetch = [("__amd_rocclr_copyBuffer", copy_kib / 2 / bench.COPY_REPS)] * bench.COPY_REPS
+    fetch += [("__amd_rocclr_copyBuffer", 0.5)]
+    fetch += [("void fsb::swim_eval_kernel<false, 0, false>(...)", 8 * n / 1024 / 2)] * 3
+    fetch += [("void fsb::feed_bary_kernel<0, 0>(...)", 16 * n / 1024 / 2)] * 3
+    write = [("__amd_rocclr_copyBuffer", copy_kib / bench.COPY_REPS)] * bench.COPY_REPS
+    write += [("void fsb::swim_eval_kernel<false, 0, false>(...)", 16 * n / 1024)] * 3
+    write += [("void fsb::feed_bary_kernel<0, 0>(...)", 4 * n / 1024)] * 3
+    _counter_csv(tmp_path / "f", "FETCH_SIZE", fetch)
+    _counter_csv(tmp_path / "w", "WRITE_SIZE", write)
+    out = tmp_path / "traffic.json"
+    t = bench.ingest_counters(str(tmp_path / "f"), str(tmp_path / "w"), n, str(out))
+    assert t["copy_scale"]["FETCH_SIZE"] == pytest.approx(2.0)
+    assert t["copy_scale"]["WRITE_SIZE"] == pytest.approx(1.0)
+    for k, per_fish in (("swim_eval", 24), ("feed_bary", 20)):
+        assert t["kernels"][k]["bytes_per_launch"] == pytest.approx(per_fish * n)
+        assert t["kernels"][k]["algorithmic_bytes_per_launch"] == per_fish * n
+    assert json.loads(out.read_text())["source_digest"] == bench.source_digest()
+    assert bench.measured_traffic("swim_eval", n, str(out)) == pytest.approx(24 * n)
+    assert bench.measured_traffic("swim_eval", 2 * n, str(out)) is None
+    stale = json.loads(out.read_text())
+    stale["source_digest"] = "0" * 16
+    out.write_text(json.dumps(stale))
+    assert bench.measured_traffic("swim_eval", n, str(out)) is None
+
+
+def test_persistent_bytes_accounting():
+    n = 1000
+    assert bench.persistent_bytes("lean", n, 10) == n * (8 + 24 * 10 + 8)
+    assert bench.persistent_bytes("prev", n, 10) == n * (20 + 32 * 9 + 24)
+    assert sum(bench.BYTES_PER_FISH.values()) == 44
+
+
+@pytest.mark.gpu
+def test_json_line_contract():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--forms", "",
+                        "--steps", "20", "--warmup", "2", "--cpu-baseline-seconds", "1"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [ln for ln in r.stdout.splitlines() if ln.strip()]
+    assert len(lines) == 1
+    d = json.loads(lines[0])
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+              "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config",
+              "roofline", "cpu_baseline"):
+        assert k in d, k
+    assert d["n_gpus"] == 1 and d["steps"] == 20 and d["warmup"] == 2
+    assert d["value"] > 0 and d["higher_is_better"] is True and d["vs_baseline"] is None
+    assert d["dtype"] == "f32" and d["data"] == "synthetic"
+    assert "workload" in d["config"]
+    rl = d["roofline"]
+    assert rl["bound"] == "hbm" and rl["unit"] == "GB/s" and rl["peak"] == 8000.0
+    assert rl["frac"] == pytest.approx(rl["achieved"] / rl["peak"])
+    cb = d["cpu_baseline"]
+    assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0 and cb["sample"]
