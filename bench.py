@@ -431,6 +431,7 @@ def cpu_baseline(n: int, budget_s: float = 12.0, max_steps: int = 400):
     from oracle.oracle import Config, default
 
     O = default()
+    cores = O.max_threads()
     cfg = Config(numFish=n, seed=0)
     school = O.init(cfg)
     done, t0 = 0, time.perf_counter()
@@ -438,10 +439,20 @@ def cpu_baseline(n: int, budget_s: float = 12.0, max_steps: int = 400):
         O.step(cfg, school, done)
         done += 1
     el = time.perf_counter() - t0
-    return {"value": n * done / el, "unit": "fish-updates/s", "cores": O.max_threads(),
+    # the same oracle on one thread, for the next iterations (a quarter of the budget)
+    O.set_threads(1)
+    one, t1 = 0, time.perf_counter()
+    while one < max_steps and time.perf_counter() - t1 < budget_s / 4:
+        O.step(cfg, school, done + one)
+        one += 1
+    el1 = time.perf_counter() - t1
+    O.set_threads(cores)
+    return {"value": n * done / el, "unit": "fish-updates/s", "cores": cores,
             "kind": "oracle",
             "sample": f"first {done} iterations of the same school (N={n}, seed 0), binary32 "
-                      f"oracle with binary64 reference sums, {el:.1f} s"}
+                      f"oracle with binary64 reference sums, {el:.1f} s on {cores} threads",
+            "single_thread": {"value": n * one / el1,
+                              "sample": f"iterations {done}..{done + one - 1}, {el1:.1f} s"}}
 
 
 COPY_FLOATS = 1 << 26  # calibration copy: 256 MiB read + 256 MiB written
