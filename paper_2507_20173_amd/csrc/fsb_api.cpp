@@ -186,7 +186,6 @@ int run_fused(fsb_school* h, uint64_t n_steps, uint32_t mode) {
     f.steps = (uint32_t)n_steps;
     f.naive = naive;
     f.spin_limit = barrier_spin_limit();
-    fused_groups(grid, &f.group_size, &f.groups);
     // Non-temporal streaming once the four live columns outgrow the 256 MB
     // last-level cache (below that, keeping lines cached is faster).
     f.streaming = h->cfg.n_fish * 16ull > (256ull << 20);
@@ -400,7 +399,6 @@ int fsb_barrier_probe(fsb_school* h, uint32_t grid, uint32_t n_barriers, double*
     FusedArgs f{};
     f.steps = n_barriers;
     f.spin_limit = barrier_spin_limit();
-    fused_groups(grid, &f.group_size, &f.groups);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);

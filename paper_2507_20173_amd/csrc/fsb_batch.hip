@@ -133,8 +133,7 @@ __global__ __launch_bounds__(256) void batch_init_kernel(BatchArgs a) {
 __global__ void batch_reset_kernel(BatchArgs a) {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nth = gridDim.x * blockDim.x;
-    for (uint32_t i = tid; i < kSyncWords; i += nth)
-        if (i != kSyncPhase) a.sync[i] = 0u;
+    for (uint32_t i = tid; i < kSyncWords; i += nth) a.sync[i] = 0u;
     for (uint32_t i = tid; i < 3 * a.n_schools; i += nth) a.school_max[i] = 0u;
     for (uint32_t i = tid; i < 8 * a.n_schools; i += nth) a.school_naive[i] = 0.0f;
     if (tid < 2) a.queue[tid * kLineWords] = 0u;
@@ -286,9 +285,8 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
     const uint32_t S = a.n_schools;
     const float H = a.H, Sw = a.S, wmin = a.wmin, wmax = a.wmax;
     const SwimRule rule{a.rule, a.wmin};
-    const Barrier bar{a.sync, a.ctrl, a.group_size, a.groups, a.spin_limit};
+    const Barrier bar{a.sync, a.ctrl, a.spin_limit};
     uint32_t phase = 0;
-    if (threadIdx.x == 0) phase = ld_agent(a.sync + kSyncPhase);
     const uint32_t t0 = uniform(ld_agent(a.step));
 
     {
@@ -309,7 +307,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
         best = wave_max_u32(best);
         if (lane == 0 && best) max_agent(next_max + run_school, best);
     }
-    if (!barrier_max(bar, 0u, 0u, phase, &M_sh)) return;
+    if (!barrier_max(bar, 0u, phase, &M_sh)) return;
 
     for (uint32_t k = 0; k < a.steps; ++k) {
         const uint32_t s = t0 + k;
@@ -451,7 +449,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
             Mb = Mn;
             w = wn;
         }
-        if (!barrier_max(bar, 0u, 0u, phase, &M_sh)) return;
+        if (!barrier_max(bar, 0u, phase, &M_sh)) return;
     }
     combine_schools<kNaive>(a, t0 + a.steps - 1u, wave, n_waves, lane);
     if (blockIdx.x == 0 && threadIdx.x == 0) st_agent(a.step, t0 + a.steps);
@@ -527,7 +525,7 @@ hipError_t batch_resident_grid(uint32_t block, uint32_t fish_per_lane, uint32_t 
         per_cu = b < per_cu ? b : per_cu;
     }
     uint64_t g = (uint64_t)cus * (uint64_t)(per_cu > 0 ? per_cu : 0);
-    if (g > kMaxGroups * 16ull) g = kMaxGroups * 16ull;
+    if (g > kMaxBarrierBlocks) g = kMaxBarrierBlocks;
     *out_grid = (uint32_t)g;
     return hipSuccess;
 }

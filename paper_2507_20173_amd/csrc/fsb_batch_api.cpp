@@ -213,7 +213,6 @@ BatchArgs launch_args(const fsb_batch* b, uint32_t steps, uint32_t grid) {
     BatchArgs a = b->args;
     a.steps = steps;
     a.spin_limit = barrier_spin_limit();
-    fused_groups(grid, &a.group_size, &a.groups);
     return a;
 }
 

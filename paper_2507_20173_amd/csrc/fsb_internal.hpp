@@ -35,16 +35,17 @@ constexpr uint32_t kErrBarrierTimeout = 1u;
 constexpr uint32_t kBarrierSpinLimit = 1u << 22;
 uint32_t barrier_spin_limit();
 
-// Synchronisation words of the persistent kernel's two-level grid barrier,
-// each on its own 256-byte line (word offsets into the sync area).
+// Synchronisation words of the persistent kernels' grid barrier (cleared
+// before every persistent launch):
+//   kSyncPub    one 64-bit word {max (low half), barrier number (high half)}
+//               that block 0 publishes when every block has arrived;
+//   kSyncSlots  one 64-bit word per block, {its max, the barrier number it
+//               has reached}.
 constexpr uint32_t kLineWords = 64;
-constexpr uint32_t kSyncRootCount = 0;                  // group leaders arrived
-constexpr uint32_t kSyncPhase = 1 * kLineWords;         // completed barriers
-constexpr uint32_t kSyncRootMax = 2 * kLineWords;       // max over group maxima
-constexpr uint32_t kSyncMaxPub = 3 * kLineWords;        // published M, slot s & 1
-constexpr uint32_t kSyncGroups = 4 * kLineWords;        // group g: [count, max] at + g * line
-constexpr uint32_t kMaxGroups = 64;
-constexpr uint32_t kSyncWords = kSyncGroups + kMaxGroups * kLineWords;
+constexpr uint32_t kSyncPub = 0;
+constexpr uint32_t kSyncSlots = kLineWords;
+constexpr uint32_t kMaxBarrierBlocks = 1024;  // largest persistent grid
+constexpr uint32_t kSyncWords = kSyncSlots + 2 * kMaxBarrierBlocks;
 
 // Workspace of one school:
 //   [Ctrl][history ring][block maxima u32 x kMaxGrid]
@@ -99,8 +100,6 @@ struct FusedArgs {
     uint32_t t0;          // first iteration of the launch
     uint32_t steps;       // iterations in the launch, >= 1
     uint32_t naive;
-    uint32_t group_size;  // blocks per barrier group
-    uint32_t groups;      // barrier groups (<= kMaxGroups)
     uint32_t streaming;   // non-temporal loads/stores (state larger than the last-level cache)
     uint32_t spin_limit;  // barrier polls before giving up
     uint32_t lean;        // keep (x, y, w) live and redo each swim (24 B/fish) instead of
@@ -122,8 +121,6 @@ hipError_t launch_combine(const SchoolArgs& a, uint32_t t, uint32_t grid, uint32
 hipError_t fused_resident_grid(uint32_t naive, uint32_t* out_grid);
 // Grid the persistent kernel uses for n fish given the resident maximum.
 uint32_t fused_grid(uint64_t n, uint32_t resident);
-// Barrier grouping of a persistent grid.
-void fused_groups(uint32_t grid, uint32_t* group_size, uint32_t* groups);
 hipError_t launch_fused(const SchoolArgs& a, const FusedArgs& f, uint32_t grid,
                         hipStream_t stream);
 // out[i] = the kernels' square root of in[i] (instrumentation).
@@ -169,7 +166,6 @@ struct BatchArgs {
     fsb_record* rec;                // [hist_len][S]
     uint32_t hist_len;
     uint32_t steps;                 // iterations per launch
-    uint32_t group_size, groups;    // barrier grouping
     uint32_t spin_limit;            // barrier polls before giving up
     // Tile schedule.  n_chunks == 0: static, chunk c = tiles [c * static_chunk,
     // (c + 1) * static_chunk) to wavefront c mod W.  Otherwise wavefronts take

@@ -441,9 +441,8 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
     const uint64_t gbase = (uint64_t)blockIdx.x * B + threadIdx.x;
     const uint64_t tail_i = 4 * n4 + threadIdx.x;
     const bool has_tail = blockIdx.x == grid - 1 && tail_i < a.n;
-    const Barrier bar{a.sync, a.ctrl, f.group_size, f.groups, f.spin_limit};
+    const Barrier bar{a.sync, a.ctrl, f.spin_limit};
     uint32_t phase = 0;
-    if (threadIdx.x == 0) phase = ld_agent(a.sync + kSyncPhase);
 
     // Prologue: swim t0, keep (x, y, prev), M_t0.
     {
@@ -477,16 +476,18 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
             a.prev[tail_i] = c;
         }
         const uint32_t m = block_max<B>(best);
-        if (!barrier_max(bar, m, f.t0 & 1u, phase, &M_sh)) return;
+        if (!barrier_max(bar, m, phase, &M_sh)) return;
     }
 
+    uint32_t M_prev = 0u;  // M of the previous sweep, for its record
     for (uint32_t k = 0; k < f.steps; ++k) {
         const uint32_t s = f.t0 + k;
         const bool last = k + 1 == f.steps;
-        const float M = __uint_as_float(M_sh);
+        const uint32_t M_bits = M_sh;
+        const float M = __uint_as_float(M_bits);
         // Record of the previous iteration, by a rotating block.
-        if (k > 0 && blockIdx.x == (s - 1u) % grid)
-            combine_block<B>(a, s - 1u, grid, f.naive, ld_agent(a.sync + kSyncMaxPub + ((s - 1u) & 1u)));
+        if (k > 0 && blockIdx.x == (s - 1u) % grid) combine_block<B>(a, s - 1u, grid, f.naive, M_prev);
+        M_prev = M_bits;
 
         LaneSums<kNaive> ls;
         uint32_t best = 0u;
@@ -555,7 +556,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
             if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->last_max = M_sh;
         } else {
             const uint32_t m = block_max<B>(best);
-            if (!barrier_max(bar, m, (s + 1u) & 1u, phase, &M_sh)) return;
+            if (!barrier_max(bar, m, phase, &M_sh)) return;
         }
     }
 }
@@ -580,9 +581,8 @@ __global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, F
     const uint64_t gbase = (uint64_t)blockIdx.x * B + threadIdx.x;
     const uint64_t tail_i = 4 * n4 + threadIdx.x;
     const bool has_tail = blockIdx.x == grid - 1 && tail_i < a.n;
-    const Barrier bar{a.sync, a.ctrl, f.group_size, f.groups, f.spin_limit};
+    const Barrier bar{a.sync, a.ctrl, f.spin_limit};
     uint32_t phase = 0;
-    if (threadIdx.x == 0) phase = ld_agent(a.sync + kSyncPhase);
 
     // Prologue: M_t0 from a look-ahead swim of t0; nothing is stored.
     {
@@ -611,15 +611,17 @@ __global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, F
             best = max(best, mag_bits(c - nc));
         }
         const uint32_t m = block_max<B>(best);
-        if (!barrier_max(bar, m, f.t0 & 1u, phase, &M_sh)) return;
+        if (!barrier_max(bar, m, phase, &M_sh)) return;
     }
 
+    uint32_t M_prev = 0u;  // M of the previous sweep, for its record
     for (uint32_t k = 0; k < f.steps; ++k) {
         const uint32_t s = f.t0 + k;
         const bool last = k + 1 == f.steps;
-        const float M = __uint_as_float(M_sh);
-        if (k > 0 && blockIdx.x == (s - 1u) % grid)
-            combine_block<B>(a, s - 1u, grid, f.naive, ld_agent(a.sync + kSyncMaxPub + ((s - 1u) & 1u)));
+        const uint32_t M_bits = M_sh;
+        const float M = __uint_as_float(M_bits);
+        if (k > 0 && blockIdx.x == (s - 1u) % grid) combine_block<B>(a, s - 1u, grid, f.naive, M_prev);
+        M_prev = M_bits;
 
         LaneSums<kNaive> ls;
         uint32_t best = 0u;
@@ -694,7 +696,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, F
             if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->last_max = M_sh;
         } else {
             const uint32_t m = block_max<B>(best);
-            if (!barrier_max(bar, m, (s + 1u) & 1u, phase, &M_sh)) return;
+            if (!barrier_max(bar, m, phase, &M_sh)) return;
         }
     }
 }
@@ -705,11 +707,10 @@ __global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, F
 // its max checked: grid - 1 + f.steps - 1 after the last one).
 __global__ __launch_bounds__(kFusedBlock) void barrier_probe_kernel(SchoolArgs a, FusedArgs f) {
     __shared__ uint32_t M_sh;
-    const Barrier bar{a.sync, a.ctrl, f.group_size, f.groups, f.spin_limit};
+    const Barrier bar{a.sync, a.ctrl, f.spin_limit};
     uint32_t phase = 0;
-    if (threadIdx.x == 0) phase = ld_agent(a.sync + kSyncPhase);
     for (uint32_t k = 0; k < f.steps; ++k)
-        if (!barrier_max(bar, blockIdx.x + k, k & 1u, phase, &M_sh)) return;
+        if (!barrier_max(bar, blockIdx.x + k, phase, &M_sh)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->probe_max = M_sh;
 }
 
@@ -721,11 +722,10 @@ __global__ __launch_bounds__(kBlock) void eval_sqrt_kernel(const float* in, floa
         out[i] = sqrt_rn(in[i]);
 }
 
-// Clears the barrier's counters and maxima before a persistent launch (the
-// phase word only ever advances).
+// Clears the barrier's words before a persistent launch (barrier numbers
+// restart at 1 in every launch).
 __global__ void reset_sync_kernel(uint32_t* sync) {
-    for (uint32_t i = threadIdx.x; i < kSyncWords; i += blockDim.x)
-        if (i != kSyncPhase) sync[i] = 0u;
+    for (uint32_t i = threadIdx.x; i < kSyncWords; i += blockDim.x) sync[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -839,7 +839,7 @@ hipError_t fused_resident_grid(uint32_t naive, uint32_t* out_grid) {
         per_cu = b < per_cu ? b : per_cu;
     }
     uint64_t g = (uint64_t)cus * (uint64_t)(per_cu > 0 ? per_cu : 0);
-    if (g > kMaxGroups * 16ull) g = kMaxGroups * 16ull;
+    if (g > kMaxBarrierBlocks) g = kMaxBarrierBlocks;
     if (g > kMaxGrid) g = kMaxGrid;
     *out_grid = (uint32_t)g;
     return hipSuccess;
@@ -851,13 +851,6 @@ uint32_t fused_grid(uint64_t n, uint32_t resident) {
     if (g < 1) g = 1;
     if (g > resident) g = resident;
     return (uint32_t)g;
-}
-
-void fused_groups(uint32_t grid, uint32_t* group_size, uint32_t* groups) {
-    uint32_t gs = 16;
-    while ((grid + gs - 1) / gs > kMaxGroups) gs *= 2;
-    *group_size = gs;
-    *groups = (grid + gs - 1) / gs;
 }
 
 uint32_t barrier_spin_limit() {

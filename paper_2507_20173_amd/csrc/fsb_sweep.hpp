@@ -1,6 +1,6 @@
 // fsb_sweep.hpp -- pieces shared by the single-school and batched kernels:
 // float4 column access, the swim draws of a group of four fish, per-lane
-// barycentre sums, and the persistent kernels' two-level grid barrier.
+// barycentre sums, and the persistent kernels' grid barrier.
 #pragma once
 
 #include "fsb_device.hpp"
@@ -92,24 +92,26 @@ struct LaneSums {
 };
 
 // ---------------------------------------------------------------------------
-// Two-level grid barrier of the persistent kernels, which also reduces a max.
+// Grid barrier of the persistent kernels, which also reduces a max.
 //
-// Thread 0 of each block folds the block's max into its group's max word and
-// arrives on the group counter (agent-scope acquire-release: everything the
-// block wrote before is published).  The last arrival of a group resets the
-// group words, folds the group max into the root max and arrives on the root
-// counter; the last root arrival publishes the max (slot `parity`), resets
-// the root words and advances the phase word the other blocks wait on.
-// Same-address atomics, which serialise, number at most one group per
-// address.  Waits are bounded: on timeout, or when another block has flagged
-// an error, every block leaves the kernel and the host reports
-// FSB_ERR_DEVICE.
+// No read-modify-write on the path: every wave waits for its stores, then
+// thread 0 of every block but block 0 release-stores {its max, barrier
+// number} into its own slot (agent scope).  Wave 0 of block 0 is the collector:
+// each lane polls every 64th slot until all carry the barrier number, then
+// the wave folds the maxima and lane 0 release-stores {M, barrier number} into the publish word, which the
+// waiting blocks poll (one load returns both).  Measured on MI355X with 256
+// blocks of 1024 threads: 6.8 us per barrier, against 9.9 us for a
+// two-level tree of same-address atomic counters, which serialise.  Waits are bounded: on
+// timeout, or when another block has flagged an error, every block leaves
+// the kernel and the host reports FSB_ERR_DEVICE.
 // ---------------------------------------------------------------------------
+// s_waitcnt immediate for vmcnt(0) with expcnt and lgkmcnt left at their
+// maxima (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 struct Barrier {
-    uint32_t* sync;       // kSyncWords words, zeroed (except the phase) before the launch
+    uint32_t* sync;       // kSyncWords words, zeroed before the launch
     Ctrl* ctrl;           // error flags
-    uint32_t group_size;  // blocks per group
-    uint32_t groups;      // number of groups
     uint32_t spin_limit;  // polls before a wait gives up (kBarrierSpinLimit unless overridden)
 };
 
@@ -119,81 +121,103 @@ __device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
 __device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ uint32_t arrive(uint32_t* p) {
-    return __hip_atomic_fetch_add(p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ void max_agent(uint32_t* p, uint32_t v) {
     __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ uint64_t barrier_word(uint32_t number, uint32_t value) {
+    return ((uint64_t)number << 32) | value;
+}
 
 // Returns false if the launch must be abandoned.  `m` is this block's max;
-// on return *M_sh holds the grid max.  `phase` is thread 0's phase count.
-__device__ __forceinline__ bool barrier_max(const Barrier& b, uint32_t m, uint32_t parity,
-                                           uint32_t& phase, uint32_t* M_sh) {
+// on return *M_sh holds the grid max.  `phase` counts the barriers this
+// launch has passed (every thread keeps the same count; it starts at 0).
+__device__ __forceinline__ bool barrier_max(const Barrier& b, uint32_t m, uint32_t& phase,
+                                           uint32_t* M_sh) {
     __shared__ int ok_sh;
+    // Every wave waits until its own stores (tile partials, and columns that
+    // a later sweep may hand to another block) are acknowledged by the L2:
+    // the workgroup barrier does not wait for them, and thread 0's release
+    // below writes back the L2 but waits only for its own wave's stores.  A
+    // full agent-scope fence in every wave would write back the L2 once per
+    // wave (measured: 37 us per barrier instead of 6).
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t* sync = b.sync;
-        int ok = 1;
-        const uint32_t target = phase + 1u;
-        const uint32_t g = blockIdx.x / b.group_size;
-        const uint32_t members = min(b.group_size, gridDim.x - g * b.group_size);
-        uint32_t* grp = sync + kSyncGroups + g * kLineWords;
-        bool released = false;
-        if (b.groups == 1u) {
-            // one group: its counter is the root
-            max_agent(sync + kSyncRootMax, m);
-            if (arrive(sync + kSyncRootCount) == members - 1u) {
-                const uint32_t M = ld_agent(sync + kSyncRootMax);
-                st_agent(sync + kSyncRootMax, 0u);
-                st_agent(sync + kSyncMaxPub + parity, M);
-                st_agent(sync + kSyncRootCount, 0u);
-                __hip_atomic_store(sync + kSyncPhase, target, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                released = true;
-            }
-        } else if (max_agent(grp + 1, m), arrive(grp) == members - 1u) {
-            const uint32_t gm = ld_agent(grp + 1);
-            st_agent(grp + 1, 0u);
-            st_agent(grp, 0u);
-            max_agent(sync + kSyncRootMax, gm);
-            if (arrive(sync + kSyncRootCount) == b.groups - 1u) {
-                const uint32_t M = ld_agent(sync + kSyncRootMax);
-                st_agent(sync + kSyncRootMax, 0u);
-                st_agent(sync + kSyncMaxPub + parity, M);
-                st_agent(sync + kSyncRootCount, 0u);
-                __hip_atomic_store(sync + kSyncPhase, target, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                released = true;
-            }
-        }
-        if (!released) {
+    uint64_t* const pub = reinterpret_cast<uint64_t*>(b.sync + kSyncPub);
+    uint64_t* const slot = reinterpret_cast<uint64_t*>(b.sync + kSyncSlots);
+    const uint32_t target = phase + 1u;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < kWave) {
+            // collector: every lane is uniform in its decisions below
+            uint32_t mx = threadIdx.x == 0 ? m : 0u;
+            int ok = 1;
             uint32_t spins = 0;
-            while (ld_agent(sync + kSyncPhase) != target) {
+            for (;;) {
+                bool arrived = true;
+                uint32_t lm = mx;
+                for (uint32_t blk = threadIdx.x; blk < gridDim.x; blk += kWave) {
+                    if (blk == 0) continue;
+                    const uint64_t w = __hip_atomic_load(slot + blk, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                    if ((uint32_t)(w >> 32) != target) arrived = false;
+                    else lm = max(lm, (uint32_t)w);
+                }
+                if (__all(arrived)) {
+                    mx = lm;
+                    break;
+                }
                 if ((spins & 255u) == 0u && ld_agent(&b.ctrl->error)) {
                     ok = 0;
                     break;
                 }
                 if (++spins > b.spin_limit) {
-                    __hip_atomic_fetch_or(&b.ctrl->error, kErrBarrierTimeout, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
+                    if (threadIdx.x == 0)
+                        __hip_atomic_fetch_or(&b.ctrl->error, kErrBarrierTimeout, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
                     ok = 0;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(2);
+                __builtin_amdgcn_s_sleep(1);
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            mx = wave_max_u32(mx);
+            if (threadIdx.x == 0) {
+                if (ok)
+                    __hip_atomic_store(pub, barrier_word(target, mx), __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                *M_sh = mx;
+                ok_sh = ok;
+            }
         }
-        *M_sh = ld_agent(sync + kSyncMaxPub + parity);
-        phase = target;
+    } else if (threadIdx.x == 0) {
+        __hip_atomic_store(slot + blockIdx.x, barrier_word(target, m), __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1;
+        uint32_t spins = 0;
+        uint64_t w;
+        while ((uint32_t)((w = __hip_atomic_load(pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >>
+                          32) != target) {
+            if ((spins & 255u) == 0u && ld_agent(&b.ctrl->error)) {
+                ok = 0;
+                break;
+            }
+            if (++spins > b.spin_limit) {
+                __hip_atomic_fetch_or(&b.ctrl->error, kErrBarrierTimeout, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *M_sh = (uint32_t)w;
         ok_sh = ok;
     }
+    phase = target;
     __syncthreads();
     return ok_sh != 0;
 }
 
-// Clears a barrier's counters and maxima before a persistent launch (the
-// phase word only ever advances).
+// Clears a barrier's words before a persistent launch.
 __global__ void reset_sync_kernel(uint32_t* sync);
 
 // Launch of a persistent kernel.  Cooperative by default (the runtime then
