@@ -125,12 +125,26 @@ def persistent_bytes(variant: str, n: int, steps: int) -> int:
     return n * (20 + 32 * (steps - 1) + 24)  # prologue 20 B, sweeps 32 B, last sweep 24 B
 
 
+INFINITY_CACHE_MIB = 256
+
+
+def cache_residency(n: int) -> dict:
+    """How the school's columns compare with the 256 MiB last-level cache
+    (MI355X's Infinity Cache): the five columns, and the three (x, y, w) a
+    sweep of the persistent kernels keeps live."""
+    five, three = 5 * 4 * n / 2**20, 3 * 4 * n / 2**20
+    return {"cache_MiB": INFINITY_CACHE_MIB, "columns_MiB": five, "live_columns_MiB": three,
+            "columns_fit": five <= INFINITY_CACHE_MIB,
+            "live_columns_fit": three <= INFINITY_CACHE_MIB}
+
+
 def fused_vs_plain(n: int, steps: int, label: str):
     """The persistent form (both variants, and the one FSB_RUN_FUSED picks)
     against per-iteration launches on the same school."""
     import paper_2507_20173_amd as fsb
 
-    out = {"workload": label, "n_fish": n, "iterations": steps}
+    out = {"workload": label, "n_fish": n, "iterations": steps,
+           "infinity_cache": cache_residency(n)}
     probe = fsb.School(fsb.FsbConfig(n_fish=n, seed=0, history_len=1))
     us, _ = fsb.fsb_barrier_probe(probe.h, 0, 2000)
     probe.close()
@@ -151,6 +165,11 @@ def fused_vs_plain(n: int, steps: int, label: str):
                     "kernel_achieved_GBs": nbytes / kernel_s / 1e9,
                     "kernel_hbm_frac": nbytes / kernel_s / 1e9 / HBM_PEAK_GBS,
                     "barrier_share": us * 1e-3 / (wall / steps * 1e3)}
+        if key == "fused" and steps >= 4:
+            # per-iteration cost as the slope between a launch of steps/2 and one
+            # of steps iterations (the launch and its prologue drop out)
+            half, _, _ = run_form(n, steps // 2, mode)
+            out[key]["slope_ms_per_step"] = (wall - half) / (steps - steps // 2) * 1e3
     wp, cp, mp = run_form(n, steps, fsb.FSB_RUN_PLAIN)
     out["plain"] = {"value": n * steps / wp, "ms_per_step": wp / steps * 1e3,
                     "algorithmic_bytes_per_fish_step": sum(BYTES_PER_FISH.values()),
@@ -425,6 +444,21 @@ def batched_form(n_schools: int, steps: int, probe_steps: int, baseline_schools:
     }
 
 
+def host_cpu() -> dict:
+    """The host's CPU model and the processors this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "usable_cpus": len(os.sched_getaffinity(0)),
+            "online_cpus": os.cpu_count()}
+
+
 def cpu_baseline(n: int, budget_s: float = 12.0, max_steps: int = 400):
     """The oracle as it stands, on this host's cores, on a bounded prefix of
     the same workload."""
@@ -448,7 +482,7 @@ def cpu_baseline(n: int, budget_s: float = 12.0, max_steps: int = 400):
     el1 = time.perf_counter() - t1
     O.set_threads(cores)
     return {"value": n * done / el, "unit": "fish-updates/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "host": host_cpu(),
             "sample": f"first {done} iterations of the same school (N={n}, seed 0), binary32 "
                       f"oracle with binary64 reference sums, {el:.1f} s on {cores} threads",
             "single_thread": {"value": n * one / el1,
@@ -588,7 +622,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "plain FSB, one school: N=2^24 fish, 1000 iterations, "
                                "per-iteration fsb_step launches (swim pass + feed pass)",
-                   "n_fish": n, "iterations": args.steps, "seed": 0, "mode": "plain"},
+                   "n_fish": n, "iterations": args.steps, "seed": 0, "mode": "plain",
+                   "infinity_cache": cache_residency(n)},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk["achieved_GBs"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dk["achieved_GBs"] / HBM_PEAK_GBS, "traffic": traffic},

@@ -69,6 +69,22 @@ def test_persistent_bytes_accounting():
     assert sum(bench.BYTES_PER_FISH.values()) == 44
 
 
+def test_cache_residency_flags():
+    # CFG2's five columns (320 MiB) exceed the 256 MiB cache, its three live
+    # columns (192 MiB) fit; CFG4's do not
+    r = bench.cache_residency(1 << 24)
+    assert r["columns_MiB"] == 320 and r["live_columns_MiB"] == 192
+    assert not r["columns_fit"] and r["live_columns_fit"]
+    r = bench.cache_residency(1 << 26)
+    assert not r["columns_fit"] and not r["live_columns_fit"]
+    assert bench.cache_residency(10_000)["columns_fit"]
+
+
+def test_host_cpu_description():
+    h = bench.host_cpu()
+    assert h["model"] and 1 <= h["usable_cpus"] <= h["online_cpus"]
+
+
 @pytest.mark.gpu
 def test_json_line_contract():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--forms", "",
@@ -91,3 +107,5 @@ def test_json_line_contract():
     assert rl["frac"] == pytest.approx(rl["achieved"] / rl["peak"])
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0 and cb["sample"]
+    assert cb["single_thread"]["value"] > 0 and cb["host"]["usable_cpus"] >= 1
+    assert d["config"]["infinity_cache"]["columns_MiB"] == 320
