@@ -94,16 +94,17 @@ struct LaneSums {
 // ---------------------------------------------------------------------------
 // Grid barrier of the persistent kernels, which also reduces a max.
 //
-// No read-modify-write on the path: every wave waits for its stores, then
-// thread 0 of every block but block 0 release-stores {its max, barrier
-// number} into its own slot (agent scope).  Wave 0 of block 0 is the collector:
-// each lane polls every 64th slot until all carry the barrier number, then
-// the wave folds the maxima and lane 0 release-stores {M, barrier number} into the publish word, which the
-// waiting blocks poll (one load returns both).  Measured on MI355X with 256
-// blocks of 1024 threads: 6.8 us per barrier, against 9.9 us for a
-// two-level tree of same-address atomic counters, which serialise.  Waits are bounded: on
-// timeout, or when another block has flagged an error, every block leaves
-// the kernel and the host reports FSB_ERR_DEVICE.
+// No read-modify-write on the path: every wave waits for its own stores,
+// then thread 0 of every block but block 0 release-stores {its max, barrier
+// number} into its own slot (agent scope).  Wave 0 of block 0 is the
+// collector: each lane polls every 64th slot until all carry the barrier
+// number, then the wave folds the maxima and lane 0 release-stores {M,
+// barrier number} into the publish word, which the waiting blocks poll (one
+// load returns both).  Measured on MI355X with 256 blocks of 1024 threads:
+// 6.8 us per barrier, against 9.9 us for a two-level tree of same-address
+// atomic counters, which serialise.  Waits are bounded: on timeout, or when
+// another block has flagged an error, every block leaves the kernel and the
+// host reports FSB_ERR_DEVICE.
 // ---------------------------------------------------------------------------
 // s_waitcnt immediate for vmcnt(0) with expcnt and lgkmcnt left at their
 // maxima (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).

@@ -4,7 +4,7 @@ multiply-adds in any kernel are those inside the correctly rounded sqrtf
 v_div_fixup_f32) expansions, plus the swim displacements' explicit
 fma(S * 2^-23, r >> 8, -S), which rounds once exactly as S * v(r) does (its
 addend is the uniform -S, a negated SGPR); and no packed-FP32 instruction is
-emitted."""
+emitted, in the single-school and the batch kernels alike."""
 import re
 
 import pytest
@@ -14,18 +14,18 @@ from paper_2507_20173_amd import build as fsb_build
 
 @pytest.fixture(scope="module")
 def kernels():
-    path = fsb_build.assembly("fsb_kernels.hip")
-    text = open(path).read()
     bodies, name = {}, None
-    for line in text.splitlines():
-        m = re.match(r"^(_Z\w+):", line)
-        if m:
-            name = m.group(1)
-            bodies[name] = []
-        elif name:
-            bodies[name].append(line)
-            if line.strip().startswith(".Lfunc_end"):
-                name = None
+    for source in ("fsb_kernels.hip", "fsb_batch.hip"):
+        text = open(fsb_build.assembly(source)).read()
+        for line in text.splitlines():
+            m = re.match(r"^(_Z\w+):", line)
+            if m:
+                name = m.group(1)
+                bodies[name] = []
+            elif name:
+                bodies[name].append(line)
+                if line.strip().startswith(".Lfunc_end"):
+                    name = None
     return {k: "\n".join(v) for k, v in bodies.items()}
 
 
@@ -35,8 +35,9 @@ def count(body, pattern):
 
 def test_kernels_found(kernels):
     names = " ".join(kernels)
-    for k in ("init_kernel", "swim_eval_kernel", "feed_bary_kernel", "combine_kernel"):
-        assert k in names
+    for k in ("init_kernel", "swim_eval_kernel", "feed_bary_kernel", "combine_kernel",
+              "fused_kernel", "fused_lean_kernel", "batch_kernel", "batch_init_kernel"):
+        assert k in names, k
 
 
 DRAW_FMA = r"\bv_fma_f32\s+v\d+,\s*v\d+,\s*v\d+,\s*-s\d+"
@@ -78,3 +79,18 @@ def test_critical_mode_issues_one_atomic_per_fish(kernels):
     for name, body in feed.items():
         assert count(body, r"\bglobal_atomic_add_f32\b") == 15, name
         assert count(body, r"\bdpp|\bv_readlane") == 0, name
+
+
+def test_grid_barrier_waits_for_every_waves_stores(kernels):
+    """Each persistent kernel passes its grid barrier at two sites (after the
+    prologue and in the iteration loop); at both, every wave waits for its
+    own memory operations (vmcnt 0) right before the workgroup barrier that
+    precedes thread 0's release, so tile partials, max atomics and columns
+    written by any wave are covered by that release."""
+    persistent = {k: v for k, v in kernels.items()
+                  if re.search(r"fused_kernel|fused_lean_kernel|batch_kernel", k)}
+    assert len(persistent) >= 8
+    for name, body in persistent.items():
+        waits = len(re.findall(r"s_waitcnt vmcnt\(0\)[^\n]*\n(?:[^\n]*\n){0,2}?\s*s_barrier\b",
+                               body))
+        assert waits >= 2, f"{name}: {waits} barriers after a vmcnt(0) wait"
