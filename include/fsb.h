@@ -70,7 +70,8 @@ extern "C" {
 
 /* fsb_config.reduce_mode: how the school max and the barycentre sums are
  * reduced.  The max is exact in every mode (it does not depend on order). */
-#define FSB_REDUCE_COMPENSATED 0u /* per-lane compensated (TwoSum) float32, binary64 cross-block combine, fixed order */
+#define FSB_REDUCE_COMPENSATED 0u /* per-lane compensated (TwoSum) float32 over pairwise sums
+                                     of four fish, binary64 cross-block combine, fixed order */
 #define FSB_REDUCE_NAIVE_F32 1u   /* float32 block trees + float32 atomicAdd (accuracy baseline) */
 #define FSB_REDUCE_CRITICAL_F32 2u /* no tree: every fish updates one shared max word and three
                                       shared float32 sums with its own device-scope atomic, the GPU

@@ -378,8 +378,8 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
                     for (int f = 0; f < 4; ++f) {
                         const float diff = lane_of(P[q], f) - lane_of(C, f);
                         lane_of(W[q], f) = feed(lane_of(W[q], f), diff, M, wmin, wmax);
-                        ls.add(lane_of(W[q], f), lane_of(X[q], f), lane_of(Y[q], f));
                     }
+                    ls.add4(W[q], X[q], Y[q]);
                     stv<kNT>(a.w, c4, W[q]);
                     if constexpr (kLean) {
                         stv<kNT>(a.x, c4, X[q]);

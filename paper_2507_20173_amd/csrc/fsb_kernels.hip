@@ -405,8 +405,9 @@ __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArg
                 const float c = distance(lane_of(X[u], k), lane_of(Y[u], k));
                 const float diff = lane_of(P[u], k) - c;
                 lane_of(nw, k) = feed(lane_of(W[u], k), diff, M, wmin, wmax);
-                add(lane_of(nw, k), lane_of(X[u], k), lane_of(Y[u], k));
+                if constexpr (kRed == kRedCritical) add(lane_of(nw, k), lane_of(X[u], k), lane_of(Y[u], k));
             }
+            if constexpr (kRed != kRedCritical) ls.add4(nw, X[u], Y[u]);
             stv<NTW>(a.w, g, nw);
         }
     }
@@ -513,8 +514,8 @@ __global__ __launch_bounds__(kFusedBlock) void fused_kernel(SchoolArgs a, FusedA
                     lane_of(C, q) = distance(lane_of(X[u], q), lane_of(Y[u], q));
                     const float diff = lane_of(P[u], q) - lane_of(C, q);
                     lane_of(W[u], q) = feed(lane_of(W[u], q), diff, M, wmin, wmax);
-                    ls.add(lane_of(W[u], q), lane_of(X[u], q), lane_of(Y[u], q));
                 }
+                ls.add4(W[u], X[u], Y[u]);
                 stv<kNT>(a.w, g, W[u]);
                 if (last) {
                     stv<kNT>(a.cur, g, C);
@@ -650,8 +651,8 @@ __global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, F
                                           H, lane_of(C0, q), lane_of(W[u], q));
                     const float diff = lane_of(C0, q) - lane_of(C1, q);
                     lane_of(W[u], q) = feed(lane_of(W[u], q), diff, M, wmin, wmax);
-                    ls.add(lane_of(W[u], q), lane_of(X[u], q), lane_of(Y[u], q));
                 }
+                ls.add4(W[u], X[u], Y[u]);
                 stv<kNT>(a.x, g, X[u]);
                 stv<kNT>(a.y, g, Y[u]);
                 stv<kNT>(a.w, g, W[u]);

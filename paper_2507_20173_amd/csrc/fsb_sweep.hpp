@@ -76,6 +76,7 @@ template <bool kNaive>
 struct LaneSums {
     CSum c[3] = {{0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}};
     float f[3] = {0.0f, 0.0f, 0.0f};
+    // One fish.
     __device__ __forceinline__ void add(float w, float x, float y) {
         const float wx = w * x;
         const float wy = w * y;
@@ -87,6 +88,25 @@ struct LaneSums {
             csum_add(c[0], w);
             csum_add(c[1], wx);
             csum_add(c[2], wy);
+        }
+    }
+    // The four fish of a float4 group.  Compensated: each sum's four terms are
+    // added pairwise in binary32, (t0 + t1) + (t2 + t3), so every term passes
+    // two roundings (error at most gamma_2 times the sum of the group's |terms|,
+    // gamma_2 = 2u / (1 - 2u)), and the group total then enters the TwoSum
+    // accumulator: one TwoSum per group instead of four.  Naive: one by one.
+    __device__ __forceinline__ void add4(float4 w, float4 x, float4 y) {
+        if constexpr (kNaive) {
+            add(w.x, x.x, y.x);
+            add(w.y, x.y, y.y);
+            add(w.z, x.z, y.z);
+            add(w.w, x.w, y.w);
+        } else {
+            const float wx0 = w.x * x.x, wx1 = w.y * x.y, wx2 = w.z * x.z, wx3 = w.w * x.w;
+            const float wy0 = w.x * y.x, wy1 = w.y * y.y, wy2 = w.z * y.z, wy3 = w.w * y.w;
+            csum_add(c[0], (w.x + w.y) + (w.z + w.w));
+            csum_add(c[1], (wx0 + wx1) + (wx2 + wx3));
+            csum_add(c[2], (wy0 + wy1) + (wy2 + wy3));
         }
     }
 };
