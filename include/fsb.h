@@ -101,13 +101,16 @@ extern "C" {
 typedef struct fsb_config {
     uint64_t n_fish;      /* fish in the school, >= 1 */
     uint64_t seed;        /* Philox key */
-    float pond_half;      /* H > 0: the pond is [-H, H]^2 (Sec. 2.1.2: 200x200 -> 100) */
+    float pond_half;      /* H in (0, 2^63]: the pond is [-H, H]^2 (Sec. 2.1.2: 200x200 ->
+                             100); the bound keeps x*x + y*y finite */
     float swim_step;      /* S: per-axis displacement in [-S, S); 0 (zero swim) or
                              >= 2^-103 (so that S * 2^-23 is exact) */
     float w_init_lo;      /* initial weights in [lo, hi], lo <= hi */
     float w_init_hi;
     float w_min;          /* weight limits applied by feeding, w_min <= w_max */
-    float w_max;
+    float w_max;          /* all four weight bounds within [-2^24, 2^24], so that no
+                             float32 partial sum of w*x can overflow (2^40 fish x 2^24
+                             x 2^63 = 2^127) */
     uint32_t reduce_mode; /* FSB_REDUCE_* */
     uint32_t history_len; /* per-iteration records kept, >= 1 (a ring) */
     uint32_t swim_rule;   /* FSB_SWIM_* flags, 0 = plain random swim */

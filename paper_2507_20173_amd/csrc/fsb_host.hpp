@@ -44,8 +44,8 @@ inline int check_config(const fsb_config* c, bool need_fish) {
     if (!c) return fail(FSB_ERR_INVALID_ARG, "config is NULL");
     if (need_fish && c->n_fish == 0) return fail(FSB_ERR_INVALID_ARG, "n_fish must be >= 1");
     if (c->n_fish > kMaxFish) return fail(FSB_ERR_INVALID_ARG, "n_fish exceeds 2^40");
-    if (!(std::isfinite(c->pond_half) && c->pond_half > 0.0f))
-        return fail(FSB_ERR_INVALID_ARG, "pond_half must be finite and > 0");
+    if (!(std::isfinite(c->pond_half) && c->pond_half > 0.0f && c->pond_half <= 0x1p63f))
+        return fail(FSB_ERR_INVALID_ARG, "pond_half must be in (0, 2^63]");
     if (!(std::isfinite(c->swim_step) && c->swim_step >= 0.0f))
         return fail(FSB_ERR_INVALID_ARG, "swim_step must be finite and >= 0");
     if (c->swim_step != 0.0f && c->swim_step < 0x1p-103f)
@@ -54,6 +54,9 @@ inline int check_config(const fsb_config* c, bool need_fish) {
         return fail(FSB_ERR_INVALID_ARG, "need finite w_init_lo <= w_init_hi");
     if (!(std::isfinite(c->w_min) && std::isfinite(c->w_max) && c->w_min <= c->w_max))
         return fail(FSB_ERR_INVALID_ARG, "need finite w_min <= w_max");
+    for (float v : {c->w_init_lo, c->w_init_hi, c->w_min, c->w_max})
+        if (!(v >= -0x1p24f && v <= 0x1p24f))
+            return fail(FSB_ERR_INVALID_ARG, "weight bounds must lie in [-2^24, 2^24]");
     if (c->reduce_mode != FSB_REDUCE_COMPENSATED && c->reduce_mode != FSB_REDUCE_NAIVE_F32 &&
         c->reduce_mode != FSB_REDUCE_CRITICAL_F32)
         return fail(FSB_ERR_INVALID_ARG, "unknown reduce_mode");

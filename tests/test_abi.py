@@ -74,10 +74,21 @@ def test_workspace_bytes_pure_host():
     dict(w_max=float("nan")), dict(reduce_mode=3), dict(reduce_mode=7), dict(history_len=0),
     dict(swim_rule=4), dict(swim_rule=2, w_min=0.0), dict(swim_rule=3, w_init_lo=0.0, w_min=0.0),
     dict(swim_rule=2, w_init_lo=-1.0),
+    dict(pond_half=2.0 ** 63 * (1 + 2.0 ** -23)), dict(pond_half=3e38),
+    dict(w_max=2.0 ** 24 * (1 + 2.0 ** -23)), dict(w_min=-(2.0 ** 25)),
+    dict(w_init_lo=-(2.0 ** 24) * 2, w_init_hi=1.0),
     dict(n_fish=(1 << 40) + 1)])
 def test_bad_config_rejected(bad):
     rc, _ = ws_bytes(cfg(**bad))
     assert rc == _lib.FSB_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("edge", [
+    dict(pond_half=2.0 ** 63), dict(pond_half=2.0 ** -126), dict(swim_step=2.0 ** -103),
+    dict(w_min=-(2.0 ** 24), w_max=2.0 ** 24, w_init_lo=-(2.0 ** 24), w_init_hi=2.0 ** 24)])
+def test_edge_configs_accepted(edge):
+    rc, _ = ws_bytes(cfg(**edge))
+    assert rc == 0
     assert _lib.lib().fsb_last_error()
 
 
