@@ -444,6 +444,46 @@ def batched_form(n_schools: int, steps: int, probe_steps: int, baseline_schools:
     }
 
 
+def oracle_prefix(n: int, budget_s: float, max_steps: int = 200) -> dict:
+    """The oracle on a bounded prefix of one school's run (N = n, seed 0):
+    iterations until the budget is spent, the initialisation not timed."""
+    from oracle.oracle import Config, default
+
+    O = default()
+    cfg = Config(numFish=n, seed=0)
+    school = O.init(cfg)
+    done, t0 = 0, time.perf_counter()
+    while done < max_steps and (done == 0 or time.perf_counter() - t0 < budget_s):
+        O.step(cfg, school, done)
+        done += 1
+    el = time.perf_counter() - t0
+    return {"value": n * done / el, "unit": "fish-updates/s", "cores": O.max_threads(),
+            "kind": "oracle",
+            "sample": f"first {done} iterations of one school of N={n} (seed 0), {el:.1f} s; "
+                      "rate per fish-iteration, taken to hold for the whole run"}
+
+
+def oracle_schools(sizes, seeds, steps: int, budget_s: float) -> dict:
+    """The oracle on the first schools of a batch, one after another, each
+    for `steps` iterations, until the budget is spent."""
+    from oracle.oracle import Config, default
+
+    O = default()
+    fish_steps, k, el = 0, 0, 0.0
+    while k < len(sizes) and (k == 0 or el < budget_s):
+        cfg = Config(numFish=int(sizes[k]), seed=int(seeds[k]))
+        school = O.init(cfg)
+        t0 = time.perf_counter()
+        O.run(cfg, school, 0, steps)
+        el += time.perf_counter() - t0
+        fish_steps += int(sizes[k]) * steps
+        k += 1
+    return {"value": fish_steps / el, "unit": "fish-updates/s", "cores": O.max_threads(),
+            "kind": "oracle",
+            "sample": f"the first {k} schools ({fish_steps // steps} fish), {steps} iterations "
+                      f"each, {el:.1f} s; rate per fish-iteration, taken to hold for the batch"}
+
+
 def host_cpu() -> dict:
     """The host's CPU model and the processors this process may use."""
     model = "unknown"
@@ -579,6 +619,8 @@ def main() -> int:
                     help="run known-size device copies first (for counter scaling)")
     ap.add_argument("--traffic-out", default=TRAFFIC_FILE,
                     help="where --ingest-counters writes the per-launch traffic")
+    ap.add_argument("--form-oracle-seconds", type=float, default=4.0,
+                    help="CPU seconds of oracle timing beside each large form (0: none)")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=12.0,
                     help="budget of the oracle's timed sample")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -655,6 +697,18 @@ def main() -> int:
             [int(v) for v in args.ablation_sizes.split(",")], args.ablation_checked_steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_baseline_seconds)
+        if args.form_oracle_seconds > 0:
+            # the oracle beside each large form's GPU figure (bounded samples)
+            budget = args.form_oracle_seconds
+            f = line["forms"]
+            if "fused_cfg4" in f:
+                f["fused_cfg4"]["oracle"] = oracle_prefix(1 << 26, budget)
+            if "precision_cfg3" in f:
+                f["precision_cfg3"]["oracle"] = oracle_prefix(1 << 27, budget)
+            if "batched_cfg5" in f:
+                from paper_2507_20173_amd.workloads import log_uniform_school_sizes, school_seeds
+                f["batched_cfg5"]["oracle"] = oracle_schools(
+                    log_uniform_school_sizes(args.schools), school_seeds(args.schools), 2, budget)
     print(json.dumps(line), flush=True)
     return 0
 

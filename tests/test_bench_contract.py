@@ -85,6 +85,14 @@ def test_host_cpu_description():
     assert h["model"] and 1 <= h["usable_cpus"] <= h["online_cpus"]
 
 
+def test_oracle_samples_beside_the_forms():
+    r = bench.oracle_prefix(4099, 0.05, max_steps=3)
+    assert r["kind"] == "oracle" and r["value"] > 0 and r["cores"] >= 1
+    assert "iterations of one school of N=4099" in r["sample"]
+    r = bench.oracle_schools([10, 20, 30], [0, 1, 2], 2, 1e9)
+    assert r["value"] > 0 and "first 3 schools (60 fish), 2 iterations" in r["sample"]
+
+
 @pytest.mark.gpu
 def test_json_line_contract():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--forms", "",
