@@ -118,8 +118,24 @@ def run_form(n: int, steps: int, mode: int, warmup: int = 2, swim_rule: int = 0)
     return wall, counts, ms
 
 
+# Largest school the register-resident kernel holds on MI355X: 256 blocks of
+# 512 threads, four groups of four fish each, plus up to three tail fish.
+REGS_MAX_FISH = 4 * 4 * 512 * 256 + 3
+
+
+def fused_variant(n: int) -> str:
+    """The variant FSB_RUN_FUSED runs for a school of n fish."""
+    if n <= REGS_MAX_FISH:
+        return "regs"
+    # lean once the 16 B/fish of the 32-byte variant's live columns reach the
+    # 256 MiB last-level cache
+    return "lean" if n * 16 >= (256 << 20) else "prev"
+
+
 def persistent_bytes(variant: str, n: int, steps: int) -> int:
     """Algorithmic bytes of one persistent launch of `steps` iterations."""
+    if variant == "regs":  # x, y, w read once, all five columns written once
+        return n * (12 + 20)
     if variant == "lean":  # prologue reads x, y; sweeps 24 B; the last also writes prev, cur
         return n * (8 + 24 * steps + 8)
     return n * (20 + 32 * (steps - 1) + 24)  # prologue 20 B, sweeps 32 B, last sweep 24 B
@@ -139,7 +155,7 @@ def cache_residency(n: int) -> dict:
 
 
 def fused_vs_plain(n: int, steps: int, label: str):
-    """The persistent form (both variants, and the one FSB_RUN_FUSED picks)
+    """The persistent form (every variant, and the one FSB_RUN_FUSED picks)
     against per-iteration launches on the same school."""
     import paper_2507_20173_amd as fsb
 
@@ -150,18 +166,20 @@ def fused_vs_plain(n: int, steps: int, label: str):
     probe.close()
     del probe
     out["barrier_us"] = us
-    for key, mode in (("fused", fsb.FSB_RUN_FUSED), ("fused_prev", fsb.FSB_RUN_FUSED_PREV),
-                      ("fused_lean", fsb.FSB_RUN_FUSED_LEAN)):
+    forms = [("fused", fsb.FSB_RUN_FUSED), ("fused_prev", fsb.FSB_RUN_FUSED_PREV),
+             ("fused_lean", fsb.FSB_RUN_FUSED_LEAN)]
+    if n <= REGS_MAX_FISH:
+        forms.append(("fused_regs", fsb.FSB_RUN_FUSED_REGS))
+    for key, mode in forms:
         wall, counts, ms = run_form(n, steps, mode)
-        # FSB_RUN_FUSED picks lean once the 16 B/fish of the 32-byte variant's
-        # live columns reach the 256 MiB last-level cache
-        variant = {"fused_prev": "prev", "fused_lean": "lean"}.get(
-            key, "lean" if n * 16 >= (256 << 20) else "prev")
+        variant = {"fused_prev": "prev", "fused_lean": "lean", "fused_regs": "regs"}.get(
+            key, fused_variant(n))
         kernel_s = ms[fsb.FSB_KERNEL_FUSED] / 1e3
         nbytes = persistent_bytes(variant, n, steps)
+        per_step = {"lean": 24, "prev": 32, "regs": 32 / steps}[variant]
         out[key] = {"variant": variant, "value": n * steps / wall, "ms_per_step": wall / steps * 1e3,
                     "launches": int(counts[fsb.FSB_KERNEL_FUSED]),
-                    "algorithmic_bytes_per_fish_step": 24 if variant == "lean" else 32,
+                    "algorithmic_bytes_per_fish_step": per_step,
                     "kernel_achieved_GBs": nbytes / kernel_s / 1e9,
                     "kernel_hbm_frac": nbytes / kernel_s / 1e9 / HBM_PEAK_GBS,
                     "barrier_share": us * 1e-3 / (wall / steps * 1e3)}
@@ -600,7 +618,7 @@ def main() -> int:
     ap.add_argument("--n-fish", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-only", action="store_true", help="skip the other forms")
-    ap.add_argument("--forms", default="fused,precision,batched,ablation,rules",
+    ap.add_argument("--forms", default="fused,registers,precision,batched,ablation,rules",
                     help="comma list of the forms to measure beside the headline")
     ap.add_argument("--fused-steps", type=int, default=2000)
     ap.add_argument("--precision-steps", type=int, default=200)
@@ -683,6 +701,12 @@ def main() -> int:
         line["forms"]["fused_cfg2"] = fused_vs_plain(
             n, args.steps,
             f"persistent form on the headline school (N=2^24, {args.steps} iterations)")
+    if "registers" in forms:
+        line["forms"]["fused_registers"] = fused_vs_plain(
+            1 << 21, args.fused_steps,
+            f"register-resident persistent form: N=2^21 fish (the largest school it holds), "
+            f"{args.fused_steps} iterations in one cooperative launch, against the streaming "
+            "variants and per-iteration launches")
     if "precision" in forms:
         line["forms"]["precision_cfg3"] = precision_form(1 << 27, args.precision_steps,
                                                          args.precision_checked_steps)

@@ -93,10 +93,16 @@ extern "C" {
 /* fsb_run modes. */
 #define FSB_RUN_PLAIN 0u      /* one fsb_step (two kernels) per iteration */
 #define FSB_RUN_FUSED 1u      /* one persistent launch with a grid barrier per iteration;
-                                 the library picks one of the two variants below */
+                                 the library picks one of the three variants below:
+                                 registers for a school they hold, else by footprint */
 #define FSB_RUN_FUSED_PREV 2u /* persistent, x, y, w, prev live: 32 B/fish per iteration */
 #define FSB_RUN_FUSED_LEAN 3u /* persistent, x, y, w live and each swim computed twice:
                                  24 B/fish per iteration, more arithmetic */
+#define FSB_RUN_FUSED_REGS 4u /* persistent, all five values of every fish held in
+                                 registers for the whole launch: the columns are read
+                                 once and written once, no bytes per iteration.  Schools
+                                 of at most 4 x 512 x (co-resident blocks) groups of four
+                                 fish (2^21 + 3 fish on MI355X); FSB_ERR_UNSUPPORTED above */
 
 typedef struct fsb_config {
     uint64_t n_fish;      /* fish in the school, >= 1 */
@@ -209,10 +215,10 @@ int fsb_step(fsb_school *h);
 
 /* n_steps iterations.  FSB_RUN_PLAIN issues fsb_step n_steps times;
  * the FSB_RUN_FUSED* modes run them in one persistent launch with a grid
- * barrier per iteration.  Both give bit-identical columns and maxima (the sums agree to
+ * barrier per iteration.  All give bit-identical columns and maxima (the sums agree to
  * rounding; each mode is deterministic).  Asynchronous; FSB_ERR_UNSUPPORTED
- * if the fused grid cannot be co-resident, or for a fused mode under
- * FSB_REDUCE_CRITICAL_F32. */
+ * if the fused grid cannot be co-resident, for FSB_RUN_FUSED_REGS on a
+ * school too large for it, or for a fused mode under FSB_REDUCE_CRITICAL_F32. */
 int fsb_run(fsb_school *h, uint64_t n_steps, uint32_t mode);
 
 /* Test hook: one iteration with the displacements dx[n_fish], dy[n_fish]

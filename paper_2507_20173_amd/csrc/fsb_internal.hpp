@@ -104,6 +104,8 @@ struct FusedArgs {
     uint32_t spin_limit;  // barrier polls before giving up
     uint32_t lean;        // keep (x, y, w) live and redo each swim (24 B/fish) instead of
                           // keeping (x, y, w, prev) (32 B/fish)
+    uint32_t regs;        // > 0: the register-resident kernel holding `regs` groups of four
+                          // fish per thread (1, 2 or 4); streaming and lean are then unused
 };
 
 // Launchers (fsb_kernels.hip).  All enqueue on `stream` and return the HIP
@@ -121,6 +123,11 @@ hipError_t launch_combine(const SchoolArgs& a, uint32_t t, uint32_t grid, uint32
 hipError_t fused_resident_grid(uint32_t naive, uint32_t* out_grid);
 // Grid the persistent kernel uses for n fish given the resident maximum.
 uint32_t fused_grid(uint64_t n, uint32_t resident);
+// Largest co-resident grid of the register-resident kernels (0 if they cannot run).
+hipError_t regs_resident_grid(uint32_t naive, uint32_t* out_grid);
+// Launch plan of the register-resident kernel for n fish: its grid, and in
+// *groups the groups of four fish per thread (1, 2 or 4); 0 if n does not fit.
+uint32_t regs_plan(uint64_t n, uint32_t resident, uint32_t* groups);
 hipError_t launch_fused(const SchoolArgs& a, const FusedArgs& f, uint32_t grid,
                         hipStream_t stream);
 // out[i] = the kernels' square root of in[i] (instrumentation).

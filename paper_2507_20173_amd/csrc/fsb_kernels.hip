@@ -702,6 +702,141 @@ __global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, F
     }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident persistent kernel: for schools small enough, every fish's
+// (x, y, w, prev, cur) stays in registers for the whole launch, so an
+// iteration moves no column bytes at all: the columns are read once at the
+// start and written once at the end.  Thread i of the grid holds groups
+// i, i + T, ..., i + (KG - 1) T (T threads in the grid; groups past the end
+// are skipped).  Like the 32-byte variant, sweep s feeds with M_s from the
+// stored prev and cur, then swims s+1 for M_{s+1}; cur is the look-ahead
+// swim's own result, so each fish-iteration costs one draw and one square
+// root.  The tail fish (n mod 4) go through memory as in fused_kernel.
+// Blocks of 512 threads, one per CU: two waves per SIMD, so each thread may
+// use 256 registers.  Four groups (80 registers of state) compile to 209
+// registers with no spill; eight would spill.
+// ---------------------------------------------------------------------------
+constexpr int kRegsBlock = 512;
+constexpr uint32_t kRegsMaxGroups = 4;
+
+template <int KG, bool kNaive>
+__global__ __launch_bounds__(kRegsBlock) void fused_regs_kernel(SchoolArgs a, FusedArgs f) {
+    constexpr int B = kRegsBlock;
+    __shared__ uint32_t M_sh;
+    const float H = a.H, wmin = a.wmin, wmax = a.wmax;
+    const SwimRule rule{a.rule, a.wmin};
+    const uint32_t grid = gridDim.x;
+    const uint64_t n4 = a.n >> 2;
+    const uint64_t stride = (uint64_t)grid * B;
+    const uint64_t gbase = (uint64_t)blockIdx.x * B + threadIdx.x;
+    const uint64_t tail_i = 4 * n4 + threadIdx.x;
+    const bool has_tail = blockIdx.x == grid - 1 && tail_i < a.n;
+    const Barrier bar{a.sync, a.ctrl, f.spin_limit};
+    uint32_t phase = 0;
+
+    float4 X[KG], Y[KG], W[KG], P[KG], C[KG];
+    // Prologue: load, swim t0 (P = objective before it, C = after), M_t0.
+    {
+        uint32_t best = 0u;
+#pragma unroll
+        for (int j = 0; j < KG; ++j) {
+            const uint64_t g = gbase + j * stride;
+            if (g >= n4) break;
+            X[j] = ldv<false>(a.x, g);
+            Y[j] = ldv<false>(a.y, g);
+            W[j] = ldv<false>(a.w, g);
+            float dx[4], dy[4];
+            group_draws(a.S, a.k0, a.k1, g, f.t0, dx, dy);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                lane_of(P[j], q) = distance(lane_of(X[j], q), lane_of(Y[j], q));
+                lane_of(C[j], q) = swim(rule, lane_of(X[j], q), lane_of(Y[j], q), dx[q], dy[q], H,
+                                        lane_of(P[j], q), lane_of(W[j], q));
+                best = max(best, mag_bits(lane_of(P[j], q) - lane_of(C[j], q)));
+            }
+        }
+        if (has_tail) {
+            float dx, dy;
+            fish_draw(a.S, a.k0, a.k1, tail_i, f.t0, dx, dy);
+            float x = a.x[tail_i], y = a.y[tail_i];
+            const float c = distance(x, y);
+            const float wt = (rule.flags & kSwimWeighted) ? a.w[tail_i] : 1.0f;
+            const float nc = swim(rule, x, y, dx, dy, H, c, wt);
+            best = max(best, mag_bits(c - nc));
+            a.x[tail_i] = x;
+            a.y[tail_i] = y;
+            a.prev[tail_i] = c;
+        }
+        const uint32_t m = block_max<B>(best);
+        if (!barrier_max(bar, m, phase, &M_sh)) return;
+    }
+
+    uint32_t M_prev = 0u;  // M of the previous sweep, for its record
+    for (uint32_t k = 0; k < f.steps; ++k) {
+        const uint32_t s = f.t0 + k;
+        const bool last = k + 1 == f.steps;
+        const uint32_t M_bits = M_sh;
+        const float M = __uint_as_float(M_bits);
+        if (k > 0 && blockIdx.x == (s - 1u) % grid) combine_block<B>(a, s - 1u, grid, f.naive, M_prev);
+        M_prev = M_bits;
+
+        LaneSums<kNaive> ls;
+        uint32_t best = 0u;
+#pragma unroll
+        for (int j = 0; j < KG; ++j) {
+            const uint64_t g = gbase + j * stride;
+            if (g >= n4) break;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                lane_of(W[j], q) = feed(lane_of(W[j], q), lane_of(P[j], q) - lane_of(C[j], q), M,
+                                        wmin, wmax);
+            ls.add4(W[j], X[j], Y[j]);
+            if (last) {
+                stv<false>(a.x, g, X[j]);
+                stv<false>(a.y, g, Y[j]);
+                stv<false>(a.w, g, W[j]);
+                stv<false>(a.prev, g, P[j]);
+                stv<false>(a.cur, g, C[j]);
+            } else {
+                float dx[4], dy[4];
+                group_draws(a.S, a.k0, a.k1, g, s + 1u, dx, dy);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    lane_of(P[j], q) = lane_of(C[j], q);
+                    lane_of(C[j], q) = swim(rule, lane_of(X[j], q), lane_of(Y[j], q), dx[q], dy[q],
+                                            H, lane_of(P[j], q), lane_of(W[j], q));
+                    best = max(best, mag_bits(lane_of(P[j], q) - lane_of(C[j], q)));
+                }
+            }
+        }
+        if (has_tail) {
+            float x = a.x[tail_i], y = a.y[tail_i];
+            const float c = distance(x, y);
+            const float nw = feed(a.w[tail_i], a.prev[tail_i] - c, M, wmin, wmax);
+            a.w[tail_i] = nw;
+            ls.add(nw, x, y);
+            if (last) {
+                a.cur[tail_i] = c;
+            } else {
+                float dx, dy;
+                fish_draw(a.S, a.k0, a.k1, tail_i, s + 1u, dx, dy);
+                const float nc = swim(rule, x, y, dx, dy, H, c, nw);
+                best = max(best, mag_bits(c - nc));
+                a.x[tail_i] = x;
+                a.y[tail_i] = y;
+                a.prev[tail_i] = c;
+            }
+        }
+        block_sums<kNaive, B>(a, ls, s);
+        if (last) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->last_max = M_sh;
+        } else {
+            const uint32_t m = block_max<B>(best);
+            if (!barrier_max(bar, m, phase, &M_sh)) return;
+        }
+    }
+}
+
 // Instrumentation: f.steps barriers of the persistent kernels' kind with no
 // other work, each folding max(block index + k) over the grid, so the
 // synchronisation a persistent iteration adds can be timed on its own (and
@@ -825,6 +960,56 @@ const void* pick_fused(uint32_t naive, uint32_t streaming, uint32_t lean) {
     return streaming ? fused_fn<false, true>(lean) : fused_fn<false, false>(lean);
 }
 
+template <bool kNaive>
+const void* regs_fn(uint32_t groups) {
+    switch (groups) {
+        case 1: return reinterpret_cast<const void*>(fused_regs_kernel<1, kNaive>);
+        case 2: return reinterpret_cast<const void*>(fused_regs_kernel<2, kNaive>);
+        default: return reinterpret_cast<const void*>(fused_regs_kernel<4, kNaive>);
+    }
+}
+
+const void* pick_regs(uint32_t naive, uint32_t groups) {
+    return naive ? regs_fn<true>(groups) : regs_fn<false>(groups);
+}
+
+hipError_t regs_resident_grid(uint32_t naive, uint32_t* out_grid) {
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    int per_cu = 1 << 30;
+    for (uint32_t groups : {1u, 2u, 4u}) {  // every instance must fit
+        int b = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, pick_regs(naive, groups), kRegsBlock,
+                                                         0);
+        if (e != hipSuccess) return e;
+        per_cu = b < per_cu ? b : per_cu;
+    }
+    uint64_t g = (uint64_t)cus * (uint64_t)(per_cu > 0 ? per_cu : 0);
+    if (g > kMaxBarrierBlocks) g = kMaxBarrierBlocks;
+    if (g > kMaxGrid) g = kMaxGrid;
+    *out_grid = (uint32_t)g;
+    return hipSuccess;
+}
+
+uint32_t regs_plan(uint64_t n, uint32_t resident, uint32_t* groups) {
+    const uint64_t n4 = n >> 2;
+    *groups = 0;
+    if (resident == 0) return 0;
+    const uint64_t threads = (uint64_t)resident * kRegsBlock;
+    const uint64_t per = (n4 + threads - 1) / threads;  // groups per thread needed
+    if (per > kRegsMaxGroups) return 0;
+    uint32_t kg = 1;
+    while (kg < per) kg *= 2;
+    uint64_t g = (n4 + (uint64_t)kg * kRegsBlock - 1) / ((uint64_t)kg * kRegsBlock);
+    if (g < 1) g = 1;
+    if (g > resident) g = resident;
+    *groups = kg;
+    return (uint32_t)g;
+}
+
 hipError_t fused_resident_grid(uint32_t naive, uint32_t* out_grid) {
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -902,8 +1087,9 @@ hipError_t launch_fused(const SchoolArgs& a, const FusedArgs& f, uint32_t grid,
     SchoolArgs sa = a;
     FusedArgs fa = f;
     void* args[] = {&sa, &fa};
-    return launch_persistent(pick_fused(f.naive, f.streaming, f.lean), dim3(grid),
-                             dim3(kFusedBlock), args, stream);
+    const void* fn = f.regs ? pick_regs(f.naive, f.regs) : pick_fused(f.naive, f.streaming, f.lean);
+    return launch_persistent(fn, dim3(grid), dim3(f.regs ? kRegsBlock : kFusedBlock), args,
+                             stream);
 }
 
 }  // namespace fsb

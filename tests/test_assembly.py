@@ -3,7 +3,8 @@ multiply-adds in any kernel are those inside the correctly rounded sqrtf
 (two residual checks per v_sqrt_f32) and division (five per
 v_div_fixup_f32) expansions, plus the swim displacements' explicit
 fma(S * 2^-23, r >> 8, -S), which rounds once exactly as S * v(r) does (its
-addend is the uniform -S, a negated SGPR); and no packed-FP32 instruction is
+addend is the uniform -S, read from a scalar register, negated there or by the
+operand modifier); and no packed-FP32 instruction is
 emitted, in the single-school and the batch kernels alike."""
 import re
 
@@ -40,7 +41,7 @@ def test_kernels_found(kernels):
         assert k in names, k
 
 
-DRAW_FMA = r"\bv_fma_f32\s+v\d+,\s*v\d+,\s*v\d+,\s*-s\d+"
+DRAW_FMA = r"\bv_fma_f32\s+v\d+,\s*v\d+,\s*v\d+,\s*-?s\d+"
 
 
 def test_no_contraction_outside_sqrt_and_div(kernels):

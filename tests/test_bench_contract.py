@@ -66,6 +66,9 @@ def test_persistent_bytes_accounting():
     n = 1000
     assert bench.persistent_bytes("lean", n, 10) == n * (8 + 24 * 10 + 8)
     assert bench.persistent_bytes("prev", n, 10) == n * (20 + 32 * 9 + 24)
+    assert bench.persistent_bytes("regs", n, 10) == n * 32
+    assert bench.fused_variant(1 << 21) == "regs" and bench.fused_variant((1 << 21) + 4) == "prev"
+    assert bench.fused_variant(1 << 24) == "lean" and bench.fused_variant(1 << 26) == "lean"
     assert sum(bench.BYTES_PER_FISH.values()) == 44
 
 
