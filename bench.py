@@ -39,8 +39,9 @@ def log(*a):
 
 
 def source_digest() -> str:
+    """Digest of the sources the plain kernels are built from."""
     h = hashlib.sha256()
-    for name in ("fsb_kernels.hip", "fsb_device.hpp", "fsb_internal.hpp"):
+    for name in ("fsb_kernels.hip", "fsb_device.hpp", "fsb_sweep.hpp", "fsb_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2507_20173_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
