@@ -342,8 +342,8 @@ int fsb_batch_profile_enable(fsb_batch *b, int every);
 int fsb_batch_kernel_times(fsb_batch *b, uint64_t *count, double *ms);
 
 /* Synchronisation cost of the persistent form: one persistent launch of
- * `grid` blocks of 1024 threads (0 = the grid fsb_run(FSB_RUN_FUSED) uses for
- * this school) that does n_barriers >= 1 of its grid barriers and nothing
+ * `grid` blocks of 1024 threads (0 = the grid of the streaming persistent
+ * variants for this school) that does n_barriers >= 1 of its grid barriers and nothing
  * else.  Each barrier carries the school-wide max, the dependency of eat()
  * (Sec. 2.3.2): barrier k folds max(block index + k) over the grid.  Writes
  * the average microseconds per barrier (HIP events around the launch, so a
