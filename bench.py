@@ -124,8 +124,14 @@ def run_form(n: int, steps: int, mode: int, warmup: int = 2, swim_rule: int = 0)
 REGS_MAX_FISH = 4 * 4 * 512 * 256 + 3
 
 
-def fused_variant(n: int) -> str:
-    """The variant FSB_RUN_FUSED runs for a school of n fish."""
+DEEP_DEPTH = 8  # iterations per grid barrier of the deep kernel
+
+
+def fused_variant(n: int, deep_ok: bool = True) -> str:
+    """The variant FSB_RUN_FUSED runs for a school of n fish (deep_ok: the
+    compensated sums and no weighted rule, the default configuration)."""
+    if deep_ok:
+        return "deep"
     if n <= REGS_MAX_FISH:
         return "regs"
     # lean once the 16 B/fish of the 32-byte variant's live columns reach the
@@ -137,6 +143,8 @@ def persistent_bytes(variant: str, n: int, steps: int) -> int:
     """Algorithmic bytes of one persistent launch of `steps` iterations."""
     if variant == "regs":  # x, y, w read once, all five columns written once
         return n * (12 + 20)
+    if variant == "deep":  # prologue reads x, y; 24 B per superstep; the last adds prev, cur
+        return n * (8 + 24 * -(-steps // DEEP_DEPTH) + 8)
     if variant == "lean":  # prologue reads x, y; sweeps 24 B; the last also writes prev, cur
         return n * (8 + 24 * steps + 8)
     return n * (20 + 32 * (steps - 1) + 24)  # prologue 20 B, sweeps 32 B, last sweep 24 B
@@ -177,7 +185,7 @@ def fused_vs_plain(n: int, steps: int, label: str):
             key, fused_variant(n))
         kernel_s = ms[fsb.FSB_KERNEL_FUSED] / 1e3
         nbytes = persistent_bytes(variant, n, steps)
-        per_step = {"lean": 24, "prev": 32, "regs": 32 / steps}[variant]
+        per_step = {"lean": 24, "prev": 32, "regs": 32 / steps, "deep": 24 / DEEP_DEPTH}[variant]
         out[key] = {"variant": variant, "value": n * steps / wall, "ms_per_step": wall / steps * 1e3,
                     "launches": int(counts[fsb.FSB_KERNEL_FUSED]),
                     "algorithmic_bytes_per_fish_step": per_step,
@@ -705,9 +713,9 @@ def main() -> int:
     if "registers" in forms:
         line["forms"]["fused_registers"] = fused_vs_plain(
             1 << 21, args.fused_steps,
-            f"register-resident persistent form: N=2^21 fish (the largest school it holds), "
-            f"{args.fused_steps} iterations in one cooperative launch, against the streaming "
-            "variants and per-iteration launches")
+            f"persistent forms at N=2^21 fish (the largest school the register-resident kernel "
+            f"holds), {args.fused_steps} iterations in one cooperative launch, every variant "
+            "against per-iteration launches")
     if "precision" in forms:
         line["forms"]["precision_cfg3"] = precision_form(1 << 27, args.precision_steps,
                                                          args.precision_checked_steps)

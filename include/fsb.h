@@ -92,9 +92,9 @@ extern "C" {
 
 /* fsb_run modes. */
 #define FSB_RUN_PLAIN 0u      /* one fsb_step (two kernels) per iteration */
-#define FSB_RUN_FUSED 1u      /* one persistent launch with a grid barrier per iteration;
-                                 the library picks one of the three variants below:
-                                 registers for a school they hold, else by footprint */
+#define FSB_RUN_FUSED 1u      /* one persistent launch; the library picks a variant below:
+                                 deep whenever it can run, else registers for a school
+                                 they hold, else store-prev or lean by footprint */
 #define FSB_RUN_FUSED_PREV 2u /* persistent, x, y, w, prev live: 32 B/fish per iteration */
 #define FSB_RUN_FUSED_LEAN 3u /* persistent, x, y, w live and each swim computed twice:
                                  24 B/fish per iteration, more arithmetic */
@@ -103,6 +103,15 @@ extern "C" {
                                  once and written once, no bytes per iteration.  Schools
                                  of at most 4 x 512 x (co-resident blocks) groups of four
                                  fish (2^21 + 3 fish on MI355X); FSB_ERR_UNSUPPORTED above */
+#define FSB_RUN_FUSED_DEEP 5u /* persistent, x, y, w live, several iterations per grid
+                                 barrier: positions do not depend on weights, so the
+                                 differences of the next iterations are formed before
+                                 their maxima are known; each swim is computed twice,
+                                 24 B per fish per barrier.  8 iterations per barrier
+                                 (the environment variable FSB_DEEP_DEPTH, read once,
+                                 may say 2 or 4): 3 B per fish-iteration.
+                                 FSB_ERR_UNSUPPORTED under the weighted swim rule or a
+                                 reduce_mode other than FSB_REDUCE_COMPENSATED */
 
 typedef struct fsb_config {
     uint64_t n_fish;      /* fish in the school, >= 1 */
@@ -215,7 +224,7 @@ int fsb_step(fsb_school *h);
 
 /* n_steps iterations.  FSB_RUN_PLAIN issues fsb_step n_steps times;
  * the FSB_RUN_FUSED* modes run them in one persistent launch with a grid
- * barrier per iteration.  All give bit-identical columns and maxima (the sums agree to
+ * barrier per iteration (per 8 iterations for FSB_RUN_FUSED_DEEP).  All give bit-identical columns and maxima (the sums agree to
  * rounding; each mode is deterministic).  Asynchronous; FSB_ERR_UNSUPPORTED
  * if the fused grid cannot be co-resident, for FSB_RUN_FUSED_REGS on a
  * school too large for it, or for a fused mode under FSB_REDUCE_CRITICAL_F32. */

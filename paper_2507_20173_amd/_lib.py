@@ -31,6 +31,7 @@ FSB_RUN_FUSED = 1
 FSB_RUN_FUSED_PREV = 2
 FSB_RUN_FUSED_LEAN = 3
 FSB_RUN_FUSED_REGS = 4
+FSB_RUN_FUSED_DEEP = 5
 
 FSB_KERNEL_SWIM_EVAL = 0
 FSB_KERNEL_FEED_BARY = 1

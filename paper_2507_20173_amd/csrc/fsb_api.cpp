@@ -34,6 +34,7 @@ struct fsb_school {
     uint64_t launches[FSB_KERNEL_KINDS];
     uint32_t resident[2];  // co-resident grid of the persistent kernel (per reduce mode; 0 = unknown)
     uint32_t resident_regs[2];  // the same for the register-resident kernel
+    uint32_t resident_deep;     // the same for the deep kernel (compensated sums only)
     Timer timers[FSB_KERNEL_KINDS];
 };
 
@@ -73,6 +74,7 @@ SchoolArgs make_args(const fsb_config& c, const fsb_state& st, void* ws, const L
     a.hist_len = c.history_len;
     a.blockmax = reinterpret_cast<uint32_t*>(base + L.blockmax);
     a.partials = reinterpret_cast<double*>(base + L.partials);
+    a.deep = reinterpret_cast<double*>(base + L.deep);
     a.sync = reinterpret_cast<uint32_t*>(base + L.sync);
     return a;
 }
@@ -161,7 +163,8 @@ int do_step(fsb_school* h, const float* dx, const float* dy) {
     return FSB_OK;
 }
 
-// FSB_RUN_FUSED: the lean variant trades a second swim per fish for a
+// FSB_RUN_FUSED without the deep kernel (naive sums or the weighted rule) on
+// a school too large for registers: the lean variant trades a second swim per fish for a
 // quarter less traffic.  Measured on MI355X it wins once the 32-byte
 // variant's live columns (16 B/fish) no longer fit the 256 MiB last-level
 // cache with room to spare (N >= 2^24); below that the cache feeds both and
@@ -179,9 +182,14 @@ int run_fused(fsb_school* h, uint64_t n_steps, uint32_t mode) {
         FSB_HIP_TRY(fused_resident_grid(naive, &h->resident[naive]), "occupancy query");
     if (h->resident[naive] == 0)
         return fail(FSB_ERR_UNSUPPORTED, "the persistent kernel cannot be resident on this device");
-    // The register-resident kernel, if asked for, or picked for a school it holds
-    // (measured 1.4-1.6x faster per iteration than the streaming variants from
-    // 2^12 to 2^21 fish: no column traffic, and no load latency in the chain).
+    // FSB_RUN_FUSED takes the deep kernel whenever it can run (compensated sums,
+    // no weighted rule): measured on MI355X it is the fastest persistent form at
+    // every size from 2^10 to 2^26 fish (3.9 us per iteration at 2^16 against
+    // 5.6 for registers; 261 us at 2^26 against 334 for lean).  Otherwise the
+    // register-resident kernel for a school it holds (1.4-1.6x faster than the
+    // streaming variants from 2^12 to 2^21 fish), else lean or store-prev.
+    const bool deep_ok = !naive && !(h->cfg.swim_rule & FSB_SWIM_WEIGHTED);
+    if (mode == FSB_RUN_FUSED && deep_ok) mode = FSB_RUN_FUSED_DEEP;
     uint32_t groups = 0, grid = 0;
     if (mode == FSB_RUN_FUSED_REGS || mode == FSB_RUN_FUSED) {
         if (h->resident_regs[naive] == 0)
@@ -191,11 +199,26 @@ int run_fused(fsb_school* h, uint64_t n_steps, uint32_t mode) {
             return fail(FSB_ERR_UNSUPPORTED, "school too large to be held in registers (" +
                                                  std::to_string(h->cfg.n_fish) + " fish)");
     }
+    // The deep kernel, if asked for.
+    uint32_t depth = 0;
+    if (mode == FSB_RUN_FUSED_DEEP) {
+        if (!deep_ok)
+            return fail(FSB_ERR_UNSUPPORTED,
+                        "the deep kernel needs compensated sums and positions that do not depend "
+                        "on weights (no weighted swim rule)");
+        depth = deep_depth();
+        if (h->resident_deep == 0)
+            FSB_HIP_TRY(deep_resident_grid(&h->resident_deep), "occupancy query");
+        if (h->resident_deep == 0)
+            return fail(FSB_ERR_UNSUPPORTED, "the deep kernel cannot be resident on this device");
+        grid = deep_grid(h->cfg.n_fish, h->resident_deep);
+    }
     int rc = finish_pending(h);
     if (rc) return rc;
-    if (groups == 0) grid = fused_grid(h->cfg.n_fish, h->resident[naive]);
+    if (groups == 0 && depth == 0) grid = fused_grid(h->cfg.n_fish, h->resident[naive]);
     FusedArgs f{};
     f.regs = groups;
+    f.deep = depth;
     f.t0 = (uint32_t)h->t;
     f.steps = (uint32_t)n_steps;
     f.naive = naive;
@@ -214,7 +237,9 @@ int run_fused(fsb_school* h, uint64_t n_steps, uint32_t mode) {
         return fail(FSB_ERR_UNSUPPORTED, "persistent grid cannot be co-resident");
     if (e != hipSuccess) return hip_fail(e, "persistent kernel launch");
     if (ev) FSB_HIP_TRY(hipEventRecord(ev->second, h->stream), "hipEventRecord");
-    h->pending = true;
+    // The deep kernel writes every record itself; the others leave the last
+    // iteration's partials for a combine launch.
+    h->pending = depth == 0;
     h->pending_t = (uint32_t)(h->t + n_steps - 1);
     h->pending_grid = grid;
     h->t += n_steps;
@@ -294,7 +319,7 @@ int fsb_step_displaced(fsb_school* h, const float* dx, const float* dy) {
 
 int fsb_run(fsb_school* h, uint64_t n_steps, uint32_t mode) {
     if (!h) return fail(FSB_ERR_INVALID_ARG, "handle is NULL");
-    if (mode > FSB_RUN_FUSED_REGS) return fail(FSB_ERR_INVALID_ARG, "unknown run mode");
+    if (mode > FSB_RUN_FUSED_DEEP) return fail(FSB_ERR_INVALID_ARG, "unknown run mode");
     if (n_steps > kStepLimit - h->t) return fail(FSB_ERR_INVALID_ARG, "iteration index would pass 2^32");
     if (mode != FSB_RUN_PLAIN) return run_fused(h, n_steps, mode);
     for (uint64_t k = 0; k < n_steps; ++k) {

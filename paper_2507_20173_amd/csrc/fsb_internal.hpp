@@ -36,23 +36,29 @@ constexpr uint32_t kBarrierSpinLimit = 1u << 22;
 uint32_t barrier_spin_limit();
 
 // Synchronisation words of the persistent kernels' grid barrier (cleared
-// before every persistent launch):
-//   kSyncPub    one 64-bit word {max (low half), barrier number (high half)}
+// before every persistent launch).  A barrier reduces KD maxima at once
+// (KD = 1, or the look-ahead depth of the deep kernel, at most kMaxDepth):
+//   kSyncPub    KD 64-bit words {max (low half), barrier number (high half)}
 //               that block 0 publishes when every block has arrived;
-//   kSyncSlots  one 64-bit word per block, {its max, the barrier number it
+//   kSyncSlots  KD 64-bit words per block, {its max, the barrier number it
 //               has reached}.
 constexpr uint32_t kLineWords = 64;
+constexpr uint32_t kMaxDepth = 8;
 constexpr uint32_t kSyncPub = 0;
 constexpr uint32_t kSyncSlots = kLineWords;
 constexpr uint32_t kMaxBarrierBlocks = 1024;  // largest persistent grid
-constexpr uint32_t kSyncWords = kSyncSlots + 2 * kMaxBarrierBlocks;
+constexpr uint32_t kSyncWords = kSyncSlots + 2 * kMaxDepth * kMaxBarrierBlocks;
+static_assert(2 * kMaxDepth <= kLineWords, "the publish words fit one line");
 
 // Workspace of one school:
 //   [Ctrl][history ring][block maxima u32 x kMaxGrid]
 //   [block partials f64 x 3 x kMaxGrid x 2 (slot t & 1)][barrier sync area]
+//   [deep kernel's block partials f64 x 3 x kMaxBarrierBlocks x 2 kMaxDepth
+//    (slot t mod 2 kMaxDepth)]
 struct Layout {
-    size_t ctrl, hist, blockmax, partials, sync, total;
+    size_t ctrl, hist, blockmax, partials, sync, deep, total;
 };
+constexpr uint32_t kDeepSlots = 2 * kMaxDepth;
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -63,7 +69,9 @@ inline Layout school_layout(uint32_t history_len) {
     L.blockmax = align_up(L.hist + (size_t)history_len * sizeof(fsb_record), kAlign);
     L.partials = align_up(L.blockmax + kMaxGrid * sizeof(uint32_t), kAlign);
     L.sync = align_up(L.partials + 2 * 3 * (size_t)kMaxGrid * sizeof(double), kAlign);
-    L.total = align_up(L.sync + kSyncWords * sizeof(uint32_t), kAlign);
+    L.deep = align_up(L.sync + kSyncWords * sizeof(uint32_t), kAlign);
+    L.total = align_up(L.deep + (size_t)kDeepSlots * 3 * kMaxBarrierBlocks * sizeof(double),
+                       kAlign);
     return L;
 }
 
@@ -80,6 +88,7 @@ struct SchoolArgs {
     uint32_t *blockmax;   // [kMaxGrid] per-block max |diff| bits of the swim pass
     double *partials;     // [2][3][kMaxGrid] per-block binary64 sums
     uint32_t *sync;       // [kSyncWords] persistent-kernel barrier words
+    double *deep;         // [kDeepSlots][3][kMaxBarrierBlocks] the deep kernel's partials
 };
 
 // Step-specific arguments of the plain passes.
@@ -106,6 +115,8 @@ struct FusedArgs {
                           // keeping (x, y, w, prev) (32 B/fish)
     uint32_t regs;        // > 0: the register-resident kernel holding `regs` groups of four
                           // fish per thread (1, 2 or 4); streaming and lean are then unused
+    uint32_t deep;        // > 0: the deep kernel, `deep` iterations per grid barrier (lean is
+                          // then unused)
 };
 
 // Launchers (fsb_kernels.hip).  All enqueue on `stream` and return the HIP
@@ -123,6 +134,13 @@ hipError_t launch_combine(const SchoolArgs& a, uint32_t t, uint32_t grid, uint32
 hipError_t fused_resident_grid(uint32_t naive, uint32_t* out_grid);
 // Grid the persistent kernel uses for n fish given the resident maximum.
 uint32_t fused_grid(uint64_t n, uint32_t resident);
+// Iterations per grid barrier of the deep kernel: kDeepDepth unless the
+// environment variable FSB_DEEP_DEPTH (read once) says 2, 4 or 8.
+constexpr uint32_t kDeepDepth = 8;
+uint32_t deep_depth();
+// Largest co-resident grid of the deep kernels, and the grid for n fish.
+hipError_t deep_resident_grid(uint32_t* out_grid);
+uint32_t deep_grid(uint64_t n, uint32_t resident);
 // Largest co-resident grid of the register-resident kernels (0 if they cannot run).
 hipError_t regs_resident_grid(uint32_t naive, uint32_t* out_grid);
 // Launch plan of the register-resident kernel for n fish: its grid, and in

@@ -54,6 +54,11 @@ __device__ __forceinline__ double* partial_slot(const SchoolArgs& a, uint32_t t,
     return a.partials + ((size_t)(t & 1u) * 3 + k) * kMaxGrid;
 }
 
+// The deep kernel's partials of iteration t: slot t mod kDeepSlots.
+__device__ __forceinline__ double* deep_slot(const SchoolArgs& a, uint32_t t, int k) {
+    return a.deep + ((size_t)(t % kDeepSlots) * 3 + k) * kMaxBarrierBlocks;
+}
+
 // Block-wide reduction of the lane sums: binary64 partial of this block for
 // iteration t (compensated mode) or float32 atomics into slot t & 1 (naive).
 template <bool kNaive, int BLOCK = kBlock>
@@ -93,6 +98,32 @@ __device__ __forceinline__ void block_sums(const SchoolArgs& a, LaneSums<kNaive>
     }
 }
 
+// The same for KD iterations of the deep kernel at once (compensated sums
+// only): ls[j] holds iteration t0 + j, for j < kd.
+template <int KD, int BLOCK>
+__device__ __forceinline__ void block_sums_deep(const SchoolArgs& a, LaneSums<false> (&ls)[KD],
+                                                uint32_t t0, uint32_t kd) {
+    constexpr int W = BLOCK / kWave;
+    __shared__ CSum wave_cs[KD][3][W];
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int j = 0; j < KD; ++j) {
+        if ((uint32_t)j >= kd) break;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const CSum v = wave_csum(ls[j].c[k]);
+            if (lane == 0) wave_cs[j][k][wid] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kd * 3) {  // one thread per (iteration, sum)
+        const uint32_t j = threadIdx.x / 3, k = threadIdx.x % 3;
+        double v = 0.0;
+        for (int w = 0; w < W; ++w) v += csum_value(wave_cs[j][k][w]);
+        deep_slot(a, t0 + j, (int)k)[blockIdx.x] = v;
+    }
+}
+
 // Block max of per-thread maxima (every thread gets it).
 template <int BLOCK = kBlock>
 __device__ __forceinline__ uint32_t block_max(uint32_t v) {
@@ -104,6 +135,26 @@ __device__ __forceinline__ uint32_t block_max(uint32_t v) {
     uint32_t m = wave_best[0];
     for (int w = 1; w < W; ++w) m = max(m, wave_best[w]);
     return m;
+}
+
+// Block maxima of KD per-thread values at once (thread 0 gets them; the
+// caller passes a barrier, which synchronises, before the next call).
+template <int KD, int BLOCK>
+__device__ __forceinline__ void block_max_k(const uint32_t (&v)[KD], uint32_t (&out)[KD]) {
+    constexpr int W = BLOCK / kWave;
+    __shared__ uint32_t wave_best[KD][W];
+#pragma unroll
+    for (int j = 0; j < KD; ++j) {
+        const uint32_t m = wave_max_u32(v[j]);
+        if (threadIdx.x % kWave == 0) wave_best[j][threadIdx.x / kWave] = m;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < KD; ++j) {
+        uint32_t m = wave_best[j][0];
+        for (int w = 1; w < W; ++w) m = max(m, wave_best[j][w]);
+        out[j] = m;
+    }
 }
 
 // Critical-mode updates of a shared word by every lane.  The address is
@@ -192,13 +243,14 @@ __global__ __launch_bounds__(kBlock) void init_kernel(InitArgs ia) {
 // ---------------------------------------------------------------------------
 template <int BLOCK = kBlock>
 __device__ void combine_block(const SchoolArgs& a, uint32_t t, uint32_t grid, uint32_t naive,
-                              uint32_t max_bits) {
+                              uint32_t max_bits, bool deep = false) {
     constexpr int W = BLOCK / kWave;
     __shared__ double part[3][W];
     if (!naive) {
         double acc[3] = {0.0, 0.0, 0.0};
         for (uint32_t b = threadIdx.x; b < grid; b += BLOCK)
-            for (int k = 0; k < 3; ++k) acc[k] += partial_slot(a, t, k)[b];
+            for (int k = 0; k < 3; ++k)
+                acc[k] += (deep ? deep_slot(a, t, k) : partial_slot(a, t, k))[b];
         for (int k = 0; k < 3; ++k) {
             acc[k] = wave_sum_f64(acc[k]);
             if (threadIdx.x % kWave == 0) part[k][threadIdx.x / kWave] = acc[k];
@@ -703,6 +755,198 @@ __global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, F
 }
 
 // ---------------------------------------------------------------------------
+// Deep persistent kernel: KD iterations per grid barrier.  Without the
+// weighted rule a fish's positions do not depend on its weight (the draws
+// depend on (seed, fish, t) only, and the greedy test on objectives only), so
+// the differences of KD iterations ahead can be formed before any of their
+// maxima is known.  A superstep of kd <= KD iterations s0 .. s0 + kd - 1
+// reads (x, y, w) once: it replays swims s0 .. s0 + kd - 1 from the stored
+// positions, feeding with the maxima M_s0 .. published by the previous
+// barrier and adding each iteration's partial sums; then, from a copy of the
+// final positions, it swims the next superstep's iterations only for their
+// maxima; it writes (x, y, w) once.  One barrier reduces all those maxima.
+// Columns: 24 B per fish per superstep, 24 / KD per fish-iteration; each swim
+// is computed twice, as in the lean kernel.  Every operation of a fish is the
+// plain path's, in the same order, so the bits are the same.  Compensated
+// sums only; the host never picks it under the weighted rule.  Blocks of 512
+// threads (two waves per SIMD, 256 registers each): the KD unrolled swims and
+// KD sets of lane sums spill at 128.
+// ---------------------------------------------------------------------------
+constexpr int kDeepBlock = 512;
+
+template <int KD, bool kNT>
+__global__ __launch_bounds__(kDeepBlock) void fused_deep_kernel(SchoolArgs a, FusedArgs f) {
+    constexpr int B = kDeepBlock;
+    __shared__ uint32_t M_sh[KD];
+    const float H = a.H, wmin = a.wmin, wmax = a.wmax;
+    const SwimRule rule{a.rule, a.wmin};
+    const uint32_t grid = gridDim.x;
+    const uint64_t n4 = a.n >> 2;
+    const uint64_t stride = (uint64_t)grid * B;
+    const uint64_t gbase = (uint64_t)blockIdx.x * B + threadIdx.x;
+    const uint64_t tail_i = 4 * n4 + threadIdx.x;
+    const bool has_tail = blockIdx.x == grid - 1 && tail_i < a.n;
+    const Barrier bar{a.sync, a.ctrl, f.spin_limit};
+    uint32_t phase = 0;
+
+    // Look-ahead maxima of iterations t .. t + kd - 1 from positions (x, y)
+    // with objective c, into best[] (nothing is stored).
+    auto look_ahead = [&](float x, float y, float c, uint64_t fish, uint32_t t, uint32_t kd,
+                          uint32_t (&best)[KD]) {
+#pragma unroll
+        for (int j = 0; j < KD; ++j) {
+            if ((uint32_t)j >= kd) break;
+            float dx, dy;
+            fish_draw(a.S, a.k0, a.k1, fish, t + j, dx, dy);
+            const float nc = swim(rule, x, y, dx, dy, H, c, 1.0f);
+            best[j] = max(best[j], mag_bits(c - nc));
+            c = nc;
+        }
+    };
+
+    // Prologue: maxima of the first superstep's iterations.
+    {
+        const uint32_t kd0 = min((uint32_t)KD, f.steps);
+        uint32_t best[KD];
+#pragma unroll
+        for (int j = 0; j < KD; ++j) best[j] = 0u;
+        for (uint64_t g = gbase; g < n4; g += stride) {
+            float4 X = ldv<kNT>(a.x, g), Y = ldv<kNT>(a.y, g);
+            float4 C;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) lane_of(C, q) = distance(lane_of(X, q), lane_of(Y, q));
+#pragma unroll
+            for (int j = 0; j < KD; ++j) {
+                if ((uint32_t)j >= kd0) break;
+                float dx[4], dy[4];
+                group_draws(a.S, a.k0, a.k1, g, f.t0 + j, dx, dy);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float nc = swim(rule, lane_of(X, q), lane_of(Y, q), dx[q], dy[q], H,
+                                          lane_of(C, q), 1.0f);
+                    best[j] = max(best[j], mag_bits(lane_of(C, q) - nc));
+                    lane_of(C, q) = nc;
+                }
+            }
+        }
+        if (has_tail) {
+            const float x = a.x[tail_i], y = a.y[tail_i];
+            look_ahead(x, y, distance(x, y), tail_i, f.t0, kd0, best);
+        }
+        uint32_t m[KD];
+        block_max_k<KD, B>(best, m);
+        if (!barrier_maxima<KD>(bar, m, phase, M_sh)) return;
+    }
+
+    uint32_t M_prev[KD];
+    uint32_t kd_prev = 0;
+    for (uint32_t k0 = 0; k0 < f.steps; k0 += KD) {
+        const uint32_t s0 = f.t0 + k0;
+        const uint32_t kd = min((uint32_t)KD, f.steps - k0);
+        const uint32_t kd_next = min((uint32_t)KD, f.steps - k0 - kd);
+        const bool last = kd_next == 0;
+        float M[KD];
+        uint32_t M_bits[KD];
+#pragma unroll
+        for (int j = 0; j < KD; ++j) {
+            M_bits[j] = M_sh[j];
+            M[j] = __uint_as_float(M_bits[j]);
+        }
+        // Records of the previous superstep, each by a rotating block.
+        for (uint32_t j = 0; j < kd_prev; ++j) {
+            const uint32_t t = s0 - kd_prev + j;
+            if (blockIdx.x == t % grid) combine_block<B>(a, t, grid, 0u, M_prev[j], true);
+        }
+#pragma unroll
+        for (int j = 0; j < KD; ++j) M_prev[j] = M_bits[j];
+        kd_prev = kd;
+
+        LaneSums<false> ls[KD];
+        uint32_t best[KD];
+#pragma unroll
+        for (int j = 0; j < KD; ++j) best[j] = 0u;
+        for (uint64_t g = gbase; g < n4; g += stride) {
+            float4 X = ldv<kNT>(a.x, g), Y = ldv<kNT>(a.y, g), W = ldv<kNT>(a.w, g);
+            float4 C, P;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) lane_of(C, q) = distance(lane_of(X, q), lane_of(Y, q));
+#pragma unroll
+            for (int j = 0; j < KD; ++j) {
+                if ((uint32_t)j >= kd) break;
+                float dx[4], dy[4];
+                group_draws(a.S, a.k0, a.k1, g, s0 + j, dx, dy);
+                P = C;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    lane_of(C, q) = swim(rule, lane_of(X, q), lane_of(Y, q), dx[q], dy[q], H,
+                                         lane_of(P, q), 1.0f);
+                    lane_of(W, q) = feed(lane_of(W, q), lane_of(P, q) - lane_of(C, q), M[j], wmin,
+                                         wmax);
+                }
+                ls[j].add4(W, X, Y);
+            }
+            stv<kNT>(a.x, g, X);
+            stv<kNT>(a.y, g, Y);
+            stv<kNT>(a.w, g, W);
+            if (last) {
+                stv<kNT>(a.prev, g, P);
+                stv<kNT>(a.cur, g, C);
+            } else {
+#pragma unroll
+                for (int j = 0; j < KD; ++j) {
+                    if ((uint32_t)j >= kd_next) break;
+                    float dx[4], dy[4];
+                    group_draws(a.S, a.k0, a.k1, g, s0 + kd + j, dx, dy);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const float nc = swim(rule, lane_of(X, q), lane_of(Y, q), dx[q], dy[q], H,
+                                              lane_of(C, q), 1.0f);
+                        best[j] = max(best[j], mag_bits(lane_of(C, q) - nc));
+                        lane_of(C, q) = nc;
+                    }
+                }
+            }
+        }
+        if (has_tail) {
+            float x = a.x[tail_i], y = a.y[tail_i], w = a.w[tail_i];
+            float c = distance(x, y), p = c;
+#pragma unroll
+            for (int j = 0; j < KD; ++j) {
+                if ((uint32_t)j >= kd) break;
+                float dx, dy;
+                fish_draw(a.S, a.k0, a.k1, tail_i, s0 + j, dx, dy);
+                p = c;
+                c = swim(rule, x, y, dx, dy, H, p, 1.0f);
+                w = feed(w, p - c, M[j], wmin, wmax);
+                ls[j].add(w, x, y);
+            }
+            a.x[tail_i] = x;
+            a.y[tail_i] = y;
+            a.w[tail_i] = w;
+            if (last) {
+                a.prev[tail_i] = p;
+                a.cur[tail_i] = c;
+            } else {
+                look_ahead(x, y, c, tail_i, s0 + kd, kd_next, best);
+            }
+        }
+        block_sums_deep<KD, B>(a, ls, s0, kd);
+        // The barrier that ends the superstep: the next maxima (none after the
+        // last superstep, whose barrier only makes its partials visible).
+        uint32_t m[KD];
+        block_max_k<KD, B>(best, m);
+        if (!barrier_maxima<KD>(bar, m, phase, M_sh)) return;
+        if (last) {
+            for (uint32_t j = 0; j < kd; ++j) {
+                const uint32_t t = s0 + j;
+                if (blockIdx.x == t % grid) combine_block<B>(a, t, grid, 0u, M_prev[j], true);
+            }
+            if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->last_max = M_prev[kd - 1];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Register-resident persistent kernel: for schools small enough, every fish's
 // (x, y, w, prev, cur) stays in registers for the whole launch, so an
 // iteration moves no column bytes at all: the columns are read once at the
@@ -960,6 +1204,55 @@ const void* pick_fused(uint32_t naive, uint32_t streaming, uint32_t lean) {
     return streaming ? fused_fn<false, true>(lean) : fused_fn<false, false>(lean);
 }
 
+template <bool kNT>
+const void* deep_fn(uint32_t depth) {
+    switch (depth) {
+        case 2: return reinterpret_cast<const void*>(fused_deep_kernel<2, kNT>);
+        case 4: return reinterpret_cast<const void*>(fused_deep_kernel<4, kNT>);
+        default: return reinterpret_cast<const void*>(fused_deep_kernel<8, kNT>);
+    }
+}
+
+const void* pick_deep(uint32_t streaming, uint32_t depth) {
+    return streaming ? deep_fn<true>(depth) : deep_fn<false>(depth);
+}
+
+hipError_t deep_resident_grid(uint32_t* out_grid) {
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    int per_cu = 1 << 30;
+    for (uint32_t depth : {2u, 4u, 8u})  // every instance must fit
+        for (uint32_t nt = 0; nt < 2; ++nt) {
+            int b = 0;
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, pick_deep(nt, depth), kDeepBlock, 0);
+            if (e != hipSuccess) return e;
+            per_cu = b < per_cu ? b : per_cu;
+        }
+    uint64_t g = (uint64_t)cus * (uint64_t)(per_cu > 0 ? per_cu : 0);
+    if (g > kMaxBarrierBlocks) g = kMaxBarrierBlocks;
+    *out_grid = (uint32_t)g;
+    return hipSuccess;
+}
+
+uint32_t deep_grid(uint64_t n, uint32_t resident) {
+    uint64_t g = ((n >> 2) + kDeepBlock - 1) / kDeepBlock;
+    if (g < 1) g = 1;
+    if (g > resident) g = resident;
+    return (uint32_t)g;
+}
+
+uint32_t deep_depth() {
+    static const uint32_t depth = [] {
+        const char* v = std::getenv("FSB_DEEP_DEPTH");
+        const unsigned long d = v && *v ? std::strtoul(v, nullptr, 10) : kDeepDepth;
+        return d == 2 || d == 4 || d == 8 ? (uint32_t)d : kDeepDepth;
+    }();
+    return depth;
+}
+
 template <bool kNaive>
 const void* regs_fn(uint32_t groups) {
     switch (groups) {
@@ -1024,6 +1317,7 @@ hipError_t fused_resident_grid(uint32_t naive, uint32_t* out_grid) {
         if (e != hipSuccess) return e;
         per_cu = b < per_cu ? b : per_cu;
     }
+
     uint64_t g = (uint64_t)cus * (uint64_t)(per_cu > 0 ? per_cu : 0);
     if (g > kMaxBarrierBlocks) g = kMaxBarrierBlocks;
     if (g > kMaxGrid) g = kMaxGrid;
@@ -1087,9 +1381,11 @@ hipError_t launch_fused(const SchoolArgs& a, const FusedArgs& f, uint32_t grid,
     SchoolArgs sa = a;
     FusedArgs fa = f;
     void* args[] = {&sa, &fa};
-    const void* fn = f.regs ? pick_regs(f.naive, f.regs) : pick_fused(f.naive, f.streaming, f.lean);
-    return launch_persistent(fn, dim3(grid), dim3(f.regs ? kRegsBlock : kFusedBlock), args,
-                             stream);
+    const void* fn = f.regs   ? pick_regs(f.naive, f.regs)
+                     : f.deep ? pick_deep(f.streaming, f.deep)
+                              : pick_fused(f.naive, f.streaming, f.lean);
+    const uint32_t block = f.regs ? kRegsBlock : f.deep ? kDeepBlock : kFusedBlock;
+    return launch_persistent(fn, dim3(grid), dim3(block), args, stream);
 }
 
 }  // namespace fsb

@@ -149,11 +149,16 @@ __device__ __forceinline__ uint64_t barrier_word(uint32_t number, uint32_t value
     return ((uint64_t)number << 32) | value;
 }
 
-// Returns false if the launch must be abandoned.  `m` is this block's max;
-// on return *M_sh holds the grid max.  `phase` counts the barriers this
-// launch has passed (every thread keeps the same count; it starts at 0).
-__device__ __forceinline__ bool barrier_max(const Barrier& b, uint32_t m, uint32_t& phase,
-                                           uint32_t* M_sh) {
+// Returns false if the launch must be abandoned.  `m` holds this block's KD
+// maxima (read by thread 0); on return M_sh[0..KD) hold the grid maxima.
+// `phase` counts the barriers this launch has passed (every thread keeps the
+// same count; it starts at 0).  Block b's slot for value j is the 64-bit word
+// KD * b + j; the publish words are 0..KD.  A release fence followed by
+// relaxed stores of the KD words, read by relaxed polls followed by an
+// acquire fence, orders everything before the fence for the reader.
+template <int KD>
+__device__ __forceinline__ bool barrier_maxima(const Barrier& b, const uint32_t (&m)[KD],
+                                               uint32_t& phase, uint32_t* M_sh) {
     __shared__ int ok_sh;
     // Every wave waits until its own stores (tile partials, and columns that
     // a later sweep may hand to another block) are acknowledged by the L2:
@@ -169,21 +174,29 @@ __device__ __forceinline__ bool barrier_max(const Barrier& b, uint32_t m, uint32
     if (blockIdx.x == 0) {
         if (threadIdx.x < kWave) {
             // collector: every lane is uniform in its decisions below
-            uint32_t mx = threadIdx.x == 0 ? m : 0u;
+            uint32_t mx[KD];
+#pragma unroll
+            for (int j = 0; j < KD; ++j) mx[j] = threadIdx.x == 0 ? m[j] : 0u;
             int ok = 1;
             uint32_t spins = 0;
             for (;;) {
                 bool arrived = true;
-                uint32_t lm = mx;
+                uint32_t lm[KD];
+#pragma unroll
+                for (int j = 0; j < KD; ++j) lm[j] = mx[j];
                 for (uint32_t blk = threadIdx.x; blk < gridDim.x; blk += kWave) {
                     if (blk == 0) continue;
-                    const uint64_t w = __hip_atomic_load(slot + blk, __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-                    if ((uint32_t)(w >> 32) != target) arrived = false;
-                    else lm = max(lm, (uint32_t)w);
+#pragma unroll
+                    for (int j = 0; j < KD; ++j) {
+                        const uint64_t w = __hip_atomic_load(slot + (size_t)blk * KD + j,
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if ((uint32_t)(w >> 32) != target) arrived = false;
+                        else lm[j] = max(lm[j], (uint32_t)w);
+                    }
                 }
                 if (__all(arrived)) {
-                    mx = lm;
+#pragma unroll
+                    for (int j = 0; j < KD; ++j) mx[j] = lm[j];
                     break;
                 }
                 if ((spins & 255u) == 0u && ld_agent(&b.ctrl->error)) {
@@ -200,23 +213,38 @@ __device__ __forceinline__ bool barrier_max(const Barrier& b, uint32_t m, uint32
                 __builtin_amdgcn_s_sleep(1);
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            mx = wave_max_u32(mx);
+#pragma unroll
+            for (int j = 0; j < KD; ++j) mx[j] = wave_max_u32(mx[j]);
             if (threadIdx.x == 0) {
-                if (ok)
-                    __hip_atomic_store(pub, barrier_word(target, mx), __ATOMIC_RELEASE,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                *M_sh = mx;
+                if (ok) {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+#pragma unroll
+                    for (int j = 0; j < KD; ++j)
+                        __hip_atomic_store(pub + j, barrier_word(target, mx[j]), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
+#pragma unroll
+                for (int j = 0; j < KD; ++j) M_sh[j] = mx[j];
                 ok_sh = ok;
             }
         }
     } else if (threadIdx.x == 0) {
-        __hip_atomic_store(slot + blockIdx.x, barrier_word(target, m), __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+#pragma unroll
+        for (int j = 0; j < KD; ++j)
+            __hip_atomic_store(slot + (size_t)blockIdx.x * KD + j, barrier_word(target, m[j]),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int ok = 1;
         uint32_t spins = 0;
-        uint64_t w;
-        while ((uint32_t)((w = __hip_atomic_load(pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >>
-                          32) != target) {
+        uint64_t w[KD];
+        for (;;) {
+            bool arrived = true;
+#pragma unroll
+            for (int j = 0; j < KD; ++j) {
+                w[j] = __hip_atomic_load(pub + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((uint32_t)(w[j] >> 32) != target) arrived = false;
+            }
+            if (arrived) break;
             if ((spins & 255u) == 0u && ld_agent(&b.ctrl->error)) {
                 ok = 0;
                 break;
@@ -230,12 +258,20 @@ __device__ __forceinline__ bool barrier_max(const Barrier& b, uint32_t m, uint32
             __builtin_amdgcn_s_sleep(1);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        *M_sh = (uint32_t)w;
+#pragma unroll
+        for (int j = 0; j < KD; ++j) M_sh[j] = (uint32_t)w[j];
         ok_sh = ok;
     }
     phase = target;
     __syncthreads();
     return ok_sh != 0;
+}
+
+// The one-value barrier of the kernels that reduce one max per iteration.
+__device__ __forceinline__ bool barrier_max(const Barrier& b, uint32_t m, uint32_t& phase,
+                                           uint32_t* M_sh) {
+    const uint32_t mm[1] = {m};
+    return barrier_maxima<1>(b, mm, phase, M_sh);
 }
 
 // Clears a barrier's words before a persistent launch.

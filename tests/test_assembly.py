@@ -83,15 +83,18 @@ def test_critical_mode_issues_one_atomic_per_fish(kernels):
 
 
 def test_grid_barrier_waits_for_every_waves_stores(kernels):
-    """Each persistent kernel passes its grid barrier at two sites (after the
-    prologue and in the iteration loop); at both, every wave waits for its
-    own memory operations (vmcnt 0) right before the workgroup barrier that
+    """Each persistent kernel passes its grid barrier after the prologue and
+    in the iteration loop; where memory operations may be outstanding, every
+    wave waits for its own (vmcnt 0) right before the workgroup barrier that
     precedes thread 0's release, so tile partials, max atomics and columns
-    written by any wave are covered by that release."""
+    written by any wave are covered by that release.  (The compiler drops the
+    wait where it can prove nothing is outstanding, as after the register-
+    resident kernel's prologue, whose loads have all been consumed.)"""
     persistent = {k: v for k, v in kernels.items()
-                  if re.search(r"fused_kernel|fused_lean_kernel|batch_kernel", k)}
-    assert len(persistent) >= 8
+                  if re.search(r"fused_kernel|fused_lean_kernel|fused_regs_kernel|"
+                               r"fused_deep_kernel|batch_kernel", k)}
+    assert len(persistent) >= 20
     for name, body in persistent.items():
         waits = len(re.findall(r"s_waitcnt vmcnt\(0\)[^\n]*\n(?:[^\n]*\n){0,2}?\s*s_barrier\b",
                                body))
-        assert waits >= 2, f"{name}: {waits} barriers after a vmcnt(0) wait"
+        assert waits >= (1 if "regs" in name else 2), f"{name}: {waits} barriers after a wait"

@@ -67,8 +67,12 @@ def test_persistent_bytes_accounting():
     assert bench.persistent_bytes("lean", n, 10) == n * (8 + 24 * 10 + 8)
     assert bench.persistent_bytes("prev", n, 10) == n * (20 + 32 * 9 + 24)
     assert bench.persistent_bytes("regs", n, 10) == n * 32
-    assert bench.fused_variant(1 << 21) == "regs" and bench.fused_variant((1 << 21) + 4) == "prev"
-    assert bench.fused_variant(1 << 24) == "lean" and bench.fused_variant(1 << 26) == "lean"
+    assert bench.persistent_bytes("deep", n, 16) == n * (8 + 24 * 2 + 8)
+    assert bench.persistent_bytes("deep", n, 17) == n * (8 + 24 * 3 + 8)
+    assert bench.fused_variant(1 << 26) == "deep"
+    f = bench.fused_variant
+    assert f(1 << 21, False) == "regs" and f((1 << 21) + 4, False) == "prev"
+    assert f(1 << 24, False) == "lean" and f(1 << 26, False) == "lean"
     assert sum(bench.BYTES_PER_FISH.values()) == 44
 
 

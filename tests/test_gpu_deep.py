@@ -1,0 +1,129 @@
+"""Deep persistent mode (FSB_RUN_FUSED_DEEP): several iterations per grid
+barrier, their differences formed ahead of their maxima.  Columns, every
+iteration's M and record must equal the oracle's (bit for bit; sums within
+the 1e-6 gate), for iteration counts that fill the last superstep and for
+counts that leave it short, and across launches interleaved with the other
+modes."""
+import numpy as np
+import pytest
+
+import paper_2507_20173_amd as fsb
+from oracle.oracle import default
+from parity_util import assert_columns_equal, assert_sums_close, oracle_config
+
+pytestmark = pytest.mark.gpu
+DEEP = fsb.FSB_RUN_FUSED_DEEP
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def O():
+    return default()
+
+
+def announce(msg):
+    print(f"[deep] {msg}", flush=True)
+
+
+def history_sums(h):
+    return np.stack([h["sum_w"], h["sum_wx"], h["sum_wy"]], 1)
+
+
+def check_run(O, cfg, runs, what):
+    steps = sum(k for k, _ in runs)
+    ocfg = oracle_config(cfg)
+    school = O.init(ocfg)
+    m, s, a = O.run(ocfg, school, 0, steps)
+    sch = fsb.School(cfg)
+    for k, mode in runs:
+        sch.run(k, mode)
+    h = sch.history(0, steps)
+    assert np.array_equal(h["step_lo"], np.arange(steps))
+    assert np.array_equal(h["max_delta"].view(np.uint32), m.view(np.uint32)), (h["max_delta"], m)
+    assert_sums_close(history_sums(h), s, a, what=what)
+    assert sch.max_delta() == m[-1]
+    assert_columns_equal(sch.state(), school, what)
+    sch.close()
+
+
+@pytest.mark.parametrize("n,steps", [(1, 5), (3, 3), (5, 9), (64, 4), (1001, 6), (4097, 8),
+                                     (65539, 7), ((1 << 20) + 3, 5), ((1 << 22) + 1, 4),
+                                     ((1 << 24) + 7, 3)])
+def test_deep_matches_oracle(torch_cuda, O, n, steps):
+    announce(f"n={n} steps={steps}")
+    check_run(O, fsb.FsbConfig(n_fish=n, seed=606 + n, history_len=steps), [(steps, DEEP)],
+              f"deep n={n}")
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3, 4, 5, 8, 9, 17])
+def test_deep_every_superstep_length(torch_cuda, O, steps):
+    """Full and short last supersteps, and a launch shorter than one."""
+    announce(f"steps={steps}")
+    check_run(O, fsb.FsbConfig(n_fish=20_011, seed=5, history_len=steps), [(steps, DEEP)],
+              f"deep steps={steps}")
+
+
+def test_deep_interleaved_with_every_mode(torch_cuda, O):
+    """plain 2 + deep 5 + prev 2 + deep 1 + lean 3 + regs 2 + deep 6 == oracle 21."""
+    announce("interleaved")
+    cfg = fsb.FsbConfig(n_fish=300_007, seed=12, history_len=21)
+    check_run(O, cfg, [(2, fsb.FSB_RUN_PLAIN), (5, DEEP), (2, fsb.FSB_RUN_FUSED_PREV), (1, DEEP),
+                       (3, fsb.FSB_RUN_FUSED_LEAN), (2, fsb.FSB_RUN_FUSED_REGS), (6, DEEP)],
+              "interleaved")
+
+
+def test_deep_greedy_rule(torch_cuda, O):
+    announce("greedy")
+    cfg = fsb.FsbConfig(n_fish=(1 << 20) + 7, seed=13, swim_step=0.5,
+                        swim_rule=fsb.FSB_SWIM_GREEDY, history_len=7)
+    check_run(O, cfg, [(7, DEEP)], "deep greedy")
+
+
+def test_deep_zero_swim(torch_cuda):
+    announce("zero swim")
+    sch = fsb.School(fsb.FsbConfig(n_fish=7777, seed=3, swim_step=0.0, history_len=6))
+    before = sch.state()
+    sch.run(6, DEEP)
+    assert (sch.history(0, 6)["max_delta"] == 0).all()
+    after = sch.state()
+    for k in before:
+        assert np.array_equal(before[k], after[k]), k
+    sch.close()
+
+
+def test_deep_is_deterministic(torch_cuda):
+    announce("determinism")
+    cfg = fsb.FsbConfig(n_fish=(1 << 20) + 1, seed=9, history_len=9)
+    runs = []
+    for _ in range(2):
+        sch = fsb.School(cfg)
+        sch.run(9, DEEP)
+        runs.append(sch.history(0, 9).tobytes())
+        sch.close()
+    assert runs[0] == runs[1]
+
+
+def test_deep_cfg4_full_size_prefix(torch_cuda, O):
+    """N = 2^26, 5 iterations (one full superstep and a short one)."""
+    n, steps = 1 << 26, 5
+    announce(f"cfg4 N={n} prefix {steps}")
+    check_run(O, fsb.FsbConfig(n_fish=n, seed=0, history_len=steps), [(steps, DEEP)],
+              "deep cfg4 prefix")
+
+
+@pytest.mark.parametrize("cfg", [dict(swim_rule=fsb.FSB_SWIM_WEIGHTED),
+                                 dict(reduce_mode=fsb.FSB_REDUCE_NAIVE_F32),
+                                 dict(reduce_mode=fsb.FSB_REDUCE_CRITICAL_F32)],
+                         ids=["weighted", "naive", "critical"])
+def test_deep_refuses_what_it_cannot_run(torch_cuda, cfg):
+    sch = fsb.School(fsb.FsbConfig(n_fish=1000, seed=1, **cfg))
+    with pytest.raises(fsb.FsbError) as e:
+        sch.run(2, DEEP)
+    assert e.value.code == fsb._lib.FSB_ERR_UNSUPPORTED
+    sch.close()

@@ -177,13 +177,15 @@ import sys
 sys.path.insert(0, sys.argv[1])
 import paper_2507_20173_amd as fsb
 out = []
-s = fsb.School(fsb.FsbConfig(n_fish=1 << 20, seed=1))
-s.run(20, fsb.FSB_RUN_FUSED)
-try:
-    s.sync()
-    out.append("fused ok")
-except fsb.FsbError as e:
-    out.append(f"fused {e.code} {e}")
+for mode in (fsb.FSB_RUN_FUSED_REGS, fsb.FSB_RUN_FUSED_LEAN, fsb.FSB_RUN_FUSED_DEEP):
+    s = fsb.School(fsb.FsbConfig(n_fish=1 << 20, seed=1))
+    s.run(20, mode)
+    try:
+        s.sync()
+        out.append("fused ok")
+    except fsb.FsbError as e:
+        out.append(f"fused {e.code} {e}")
+    s.close()
 b = fsb.Batch(fsb.FsbConfig(n_fish=0), [1000] * 64, list(range(64)))
 b.run(20, fsb.tuning(1024, 8, 20))
 try:
@@ -212,9 +214,11 @@ def test_barrier_timeout_is_reported(torch_cuda):
     r = subprocess.run([sys.executable, "-c", CHILD_TIMEOUT, root], env=env, capture_output=True,
                        text=True, timeout=240)
     assert r.returncode == 0, r.stderr[-2000:]
-    fused, batch = r.stdout.strip().splitlines()[-1].split("|")
+    *fused, batch = r.stdout.strip().splitlines()[-1].split("|")
     code = str(fsb._lib.FSB_ERR_DEVICE)
-    assert fused.startswith(f"fused {code}") and "timed out" in fused, fused
+    assert len(fused) == 3  # register-resident, lean, deep
+    for f in fused:
+        assert f.startswith(f"fused {code}") and "timed out" in f, f
     assert batch.startswith(f"batch {code}") and "timed out" in batch, batch
 
 
