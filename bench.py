@@ -163,6 +163,18 @@ def cache_residency(n: int) -> dict:
             "live_columns_fit": three <= INFINITY_CACHE_MIB}
 
 
+def batch_bytes(variant: str, fish: int, steps: int, per_launch: int, launches: int) -> int:
+    """Algorithmic bytes of a batched run of `steps` iterations in launches of
+    `per_launch` (the last one shorter if it does not divide)."""
+    if variant == "lean":  # prologue reads x, y; 24 B per iteration; the last sweep writes prev, cur
+        return fish * (16 * launches + 24 * steps)
+    if variant == "deep":  # the same per launch; 24 B per superstep of DEEP_DEPTH iterations
+        full, rest = divmod(steps, per_launch)
+        supersteps = full * -(-per_launch // DEEP_DEPTH) + -(-rest // DEEP_DEPTH)
+        return fish * (16 * launches + 24 * supersteps)
+    return fish * (44 * launches + 32 * (steps - launches))  # prologue 20 B, last sweep 24 B
+
+
 def fused_vs_plain(n: int, steps: int, label: str):
     """The persistent form (every variant, and the one FSB_RUN_FUSED picks)
     against per-iteration launches on the same school."""
@@ -434,9 +446,9 @@ def batched_form(n_schools: int, steps: int, probe_steps: int, baseline_schools:
     del b
     torch.cuda.empty_cache()
     K = min(tune.steps_per_launch, steps)
-    lean = tune.variant == fsb.FSB_RUN_FUSED_LEAN
-    bytes_total = (total * (8 * launches + 24 * steps + 8 * launches) if lean
-                   else total * (20 * launches + 32 * (steps - launches) + 24 * launches))
+    variant = {fsb.FSB_RUN_FUSED_LEAN: "lean", fsb.FSB_RUN_FUSED_DEEP: "deep"}.get(tune.variant,
+                                                                                "prev")
+    bytes_total = batch_bytes(variant, total, steps, K, launches)
 
     # baseline: the first schools one by one, fsb_step per iteration
     base_fish, base_wall = 0, 0.0
@@ -460,8 +472,8 @@ def batched_form(n_schools: int, steps: int, probe_steps: int, baseline_schools:
         "n_schools": n_schools, "total_fish": total, "iterations": steps,
         "tuning": fsb.tuning_dict(tune), "autotune_probe_steps": probe_steps,
         "value": value, "ms_per_step": wall / steps * 1e3, "launches": int(launches),
-        "variant": "lean" if lean else "prev",
-        "algorithmic_bytes_per_fish_step": 24 if lean else 32,
+        "variant": variant,
+        "algorithmic_bytes_per_fish_step": {"lean": 24, "prev": 32, "deep": 24 / DEEP_DEPTH}[variant],
         "kernel_achieved_GBs": bytes_total / (ms / 1e3) / 1e9,
         "kernel_hbm_frac": bytes_total / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
         "baseline_per_school_plain": {"schools": baseline_schools, "fish": base_fish,
@@ -497,7 +509,8 @@ def oracle_schools(sizes, seeds, steps: int, budget_s: float) -> dict:
 
     O = default()
     fish_steps, k, el = 0, 0, 0.0
-    while k < len(sizes) and (k == 0 or el < budget_s):
+    start = time.perf_counter()  # the initialisations count against the budget too
+    while k < len(sizes) and (k == 0 or time.perf_counter() - start < budget_s):
         cfg = Config(numFish=int(sizes[k]), seed=int(seeds[k]))
         school = O.init(cfg)
         t0 = time.perf_counter()

@@ -173,9 +173,12 @@ typedef struct fsb_tuning {
                                   wavefront's share of one school: 64 x this many fish) */
     uint32_t steps_per_launch; /* iterations per persistent launch, >= 1 */
     uint32_t blocks_per_cu;    /* resident blocks per compute unit to use (0 = all that fit) */
-    uint32_t variant;          /* 0 = chosen by the library, FSB_RUN_FUSED_PREV (x, y, w, prev
-                                  live: 32 B/fish per iteration) or FSB_RUN_FUSED_LEAN (x, y, w
-                                  live, each swim done twice: 24 B/fish) */
+    uint32_t variant;          /* 0 = chosen by the library (deep with 256-thread blocks where
+                                  it can run, else by footprint), FSB_RUN_FUSED_PREV (x, y, w,
+                                  prev live: 32 B/fish per iteration), FSB_RUN_FUSED_LEAN (x, y,
+                                  w live, each swim done twice: 24 B/fish) or FSB_RUN_FUSED_DEEP
+                                  (8 iterations per grid barrier, 3 B/fish-iteration; needs
+                                  block_size 256, compensated sums, no weighted rule) */
     uint32_t schedule;         /* FSB_SCHED_* */
     uint32_t chunk_tiles;      /* static: tiles per chunk (0 = n_tiles / W); dynamic: tiles
                                   per chunk, >= 1; guided: smallest chunk, >= 1 */
@@ -285,8 +288,10 @@ int fsb_batch_workspace_bytes(const fsb_config *common, uint32_t n_schools,
                               size_t *out_bytes);
 
 /* Initialise every school (Sec. 2.1.1 draws, per-school key) and return a
- * handle at iteration 0 with the default tuning (1024 threads, 8 fish per
- * lane, 100 iterations per launch, variant chosen by the library).  Uploads
+ * handle at iteration 0 with the default tuning (8 fish per lane, 100
+ * iterations per launch, variant chosen by the library; 256 threads, which
+ * lets it choose the deep variant, with compensated sums and no weighted
+ * rule, else 1024 threads).  Uploads
  * the school tables (synchronous copies), then enqueues the init kernel on
  * `stream`.  FSB_ERR_UNSUPPORTED for reduce_mode FSB_REDUCE_CRITICAL_F32. */
 int fsb_batch_init(const fsb_config *common, uint32_t n_schools,

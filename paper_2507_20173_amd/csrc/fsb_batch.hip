@@ -134,7 +134,7 @@ __global__ void batch_reset_kernel(BatchArgs a) {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nth = gridDim.x * blockDim.x;
     for (uint32_t i = tid; i < kSyncWords; i += nth) a.sync[i] = 0u;
-    for (uint32_t i = tid; i < 3 * a.n_schools; i += nth) a.school_max[i] = 0u;
+    for (uint32_t i = tid; i < a.max_slots * a.n_schools; i += nth) a.school_max[i] = 0u;
     for (uint32_t i = tid; i < 8 * a.n_schools; i += nth) a.school_naive[i] = 0.0f;
     if (tid < 2) a.queue[tid * kLineWords] = 0u;
 }
@@ -456,6 +456,259 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Deep batched kernel: KD iterations per grid barrier, as the single-school
+// deep kernel (positions do not depend on weights, so a superstep replays its
+// swims with the published maxima and swims the next superstep ahead for its
+// maxima; x, y, w are read and written once per superstep).  Per school the
+// maxima of iteration t live in slot t mod 3 KD of the max ring (written by
+// the previous superstep's look-ahead, read by this one, cleared by the next
+// one's combine), the tile partials of iteration t in slot t mod 2 KD.
+// Compensated sums only; 256-thread blocks (a lane needs ~230 registers).
+// ---------------------------------------------------------------------------
+template <int KD>
+__device__ void combine_schools_deep(const BatchArgs& a, uint32_t t0, uint32_t count,
+                                     uint32_t wave, uint32_t n_waves, uint32_t lane) {
+    const uint32_t S = a.n_schools;
+    for (uint32_t c = wave; c < S; c += n_waves) {
+        const uint32_t tb = a.tile_begin[c], te = a.tile_begin[c + 1];
+        for (uint32_t j = 0; j < count; ++j) {
+            const uint32_t t = t0 + j;
+            const double* part = a.tile_part + (size_t)(t % (2 * KD)) * 3 * a.tile_cap;
+            double acc[3] = {0.0, 0.0, 0.0};
+            for (uint32_t i = tb + lane; i < te; i += kWave)
+                for (int k = 0; k < 3; ++k) acc[k] += part[(size_t)k * a.tile_cap + i];
+            for (int k = 0; k < 3; ++k) acc[k] = wave_sum_f64(acc[k]);
+            if (lane == 0) {
+                uint32_t* slot = a.school_max + (size_t)(t % (3 * KD)) * S + c;
+                fsb_record r;
+                r.sum_w = acc[0];
+                r.sum_wx = acc[1];
+                r.sum_wy = acc[2];
+                r.max_delta = __uint_as_float(ld_agent(slot));
+                r.step_lo = t;
+                a.rec[(size_t)(t % a.hist_len) * S + c] = r;
+                st_agent(slot, 0u);
+            }
+        }
+    }
+}
+
+// The wave's maxima of kd iterations t .. t + kd - 1 for one school, into
+// the ring (one device-scope atomic max per iteration, lane 0).
+template <int KD>
+__device__ __forceinline__ void flush_maxima(const BatchArgs& a, uint32_t (&best)[KD],
+                                             uint32_t t, uint32_t kd, uint32_t school,
+                                             uint32_t lane) {
+#pragma unroll
+    for (int j = 0; j < KD; ++j) {
+        if ((uint32_t)j >= kd) break;
+        const uint32_t m = wave_max_u32(best[j]);
+        if (lane == 0 && m)
+            max_agent(a.school_max + (size_t)((t + j) % (3 * KD)) * a.n_schools + school, m);
+        best[j] = 0u;
+    }
+}
+
+template <int BLOCK, int GPL, bool kNT, int KD>
+__global__ __launch_bounds__(BLOCK) void batch_deep_kernel(BatchArgs a) {
+    constexpr uint32_t WPB = BLOCK / kWave;
+    __shared__ uint32_t M_sh;
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint32_t wave = uniform(blockIdx.x * WPB + threadIdx.x / kWave);
+    const uint32_t n_waves = gridDim.x * WPB;
+    const float H = a.H, Sw = a.S, wmin = a.wmin, wmax = a.wmax;
+    const SwimRule rule{a.rule, a.wmin};
+    const Barrier bar{a.sync, a.ctrl, a.spin_limit};
+    uint32_t phase = 0;
+    const uint32_t t0 = uniform(ld_agent(a.step));
+
+    // Prologue: the first superstep's maxima, from the stored positions.
+    {
+        const uint32_t kd0 = min((uint32_t)KD, a.steps);
+        uint32_t* const queue = queue_of(a, 0);
+        uint32_t best[KD];
+#pragma unroll
+        for (int j = 0; j < KD; ++j) best[j] = 0u;
+        uint32_t run_school = 0u;
+        for (Walk w = first_tile(a, queue, lane, wave); w.tl < a.n_tiles;
+             next_tile(a, queue, lane, n_waves, w)) {
+            const Tile T = a.tiles[w.tl];
+            if (T.school != run_school) {
+                flush_maxima<KD>(a, best, t0, kd0, run_school, lane);
+                run_school = T.school;
+            }
+#pragma unroll
+            for (int q = 0; q < GPL; ++q) {
+                const uint32_t jg = lane + q * kWave;  // group within the tile
+                if (4 * jg >= T.n_fish) break;
+                const uint64_t g = (uint64_t)T.group0 + jg;
+                const uint64_t c4 = T.col4 + jg;
+                const uint32_t nf = min(4u, T.n_fish - 4 * jg);
+                float4 X, Y, C;
+                if (nf == 4) {
+                    X = ldv<kNT>(a.x, c4);
+                    Y = ldv<kNT>(a.y, c4);
+                } else {  // the school's ragged last group: only its own fish are read
+                    for (uint32_t f = 0; f < 4; ++f) {
+                        lane_of(X, f) = f < nf ? a.x[4 * c4 + f] : 0.0f;
+                        lane_of(Y, f) = f < nf ? a.y[4 * c4 + f] : 0.0f;
+                    }
+                }
+#pragma unroll
+                for (int f = 0; f < 4; ++f) lane_of(C, f) = distance(lane_of(X, f), lane_of(Y, f));
+#pragma unroll
+                for (int j = 0; j < KD; ++j) {
+                    if ((uint32_t)j >= kd0) break;
+                    float dx[4], dy[4];
+                    group_draws(Sw, T.k0, T.k1, g, t0 + j, dx, dy);
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) {
+                        const float nc = swim(rule, lane_of(X, f), lane_of(Y, f), dx[f], dy[f], H,
+                                              lane_of(C, f), 1.0f);
+                        if ((uint32_t)f < nf) best[j] = max(best[j], mag_bits(lane_of(C, f) - nc));
+                        lane_of(C, f) = nc;
+                    }
+                }
+            }
+        }
+        flush_maxima<KD>(a, best, t0, kd0, run_school, lane);
+    }
+    if (!barrier_max(bar, 0u, phase, &M_sh)) return;
+
+    uint32_t kd_prev = 0;
+    for (uint32_t k0 = 0; k0 < a.steps; k0 += KD) {
+        const uint32_t s0 = t0 + k0;
+        const uint32_t kd = min((uint32_t)KD, a.steps - k0);
+        const uint32_t kd_next = min((uint32_t)KD, a.steps - k0 - kd);
+        const bool last = kd_next == 0;
+        const uint32_t sweep = k0 / KD + 1u;  // sweep phase (0 = prologue)
+        if (k0 > 0) combine_schools_deep<KD>(a, s0 - kd_prev, kd_prev, wave, n_waves, lane);
+        kd_prev = kd;
+        // this sweep takes phase `sweep`'s counter; the other one (last used by
+        // the previous phase, which every wavefront has left) is cleared for
+        // the next phase
+        uint32_t* const queue = queue_of(a, sweep);
+        if (a.n_chunks && blockIdx.x == 0 && threadIdx.x == 0) st_agent(queue_of(a, sweep + 1u), 0u);
+        uint32_t best[KD];
+#pragma unroll
+        for (int j = 0; j < KD; ++j) best[j] = 0u;
+        float M[KD];
+#pragma unroll
+        for (int j = 0; j < KD; ++j) M[j] = 0.0f;
+        uint32_t run_school = 0xffffffffu;
+        for (Walk w = first_tile(a, queue, lane, wave); w.tl < a.n_tiles;
+             next_tile(a, queue, lane, n_waves, w)) {
+            const Tile T = a.tiles[w.tl];
+            if (T.school != run_school) {
+                if (run_school != 0xffffffffu && !last)
+                    flush_maxima<KD>(a, best, s0 + kd, kd_next, run_school, lane);
+                run_school = T.school;
+                // final since the barrier, and nobody writes these slots this sweep
+#pragma unroll
+                for (int j = 0; j < KD; ++j)
+                    if ((uint32_t)j < kd)
+                        M[j] = __uint_as_float(
+                            a.school_max[(size_t)((s0 + j) % (3 * KD)) * a.n_schools + T.school]);
+            }
+            LaneSums<false> ls[KD];
+#pragma unroll
+            for (int q = 0; q < GPL; ++q) {
+                const uint32_t jg = lane + q * kWave;
+                if (4 * jg >= T.n_fish) break;
+                const uint64_t g = (uint64_t)T.group0 + jg;
+                const uint64_t c4 = T.col4 + jg;
+                const uint32_t nf = min(4u, T.n_fish - 4 * jg);
+                float4 X, Y, W, C, P;
+                if (nf == 4) {
+                    X = ldv<kNT>(a.x, c4);
+                    Y = ldv<kNT>(a.y, c4);
+                    W = ldv<kNT>(a.w, c4);
+                } else {
+                    for (uint32_t f = 0; f < 4; ++f) {
+                        lane_of(X, f) = f < nf ? a.x[4 * c4 + f] : 0.0f;
+                        lane_of(Y, f) = f < nf ? a.y[4 * c4 + f] : 0.0f;
+                        lane_of(W, f) = f < nf ? a.w[4 * c4 + f] : 0.0f;
+                    }
+                }
+#pragma unroll
+                for (int f = 0; f < 4; ++f) lane_of(C, f) = distance(lane_of(X, f), lane_of(Y, f));
+#pragma unroll
+                for (int j = 0; j < KD; ++j) {
+                    if ((uint32_t)j >= kd) break;
+                    float dx[4], dy[4];
+                    group_draws(Sw, T.k0, T.k1, g, s0 + j, dx, dy);
+                    P = C;
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) {
+                        lane_of(C, f) = swim(rule, lane_of(X, f), lane_of(Y, f), dx[f], dy[f], H,
+                                             lane_of(P, f), 1.0f);
+                        lane_of(W, f) = feed(lane_of(W, f), lane_of(P, f) - lane_of(C, f), M[j],
+                                             wmin, wmax);
+                    }
+                    if (nf == 4) {
+                        ls[j].add4(W, X, Y);
+                    } else {
+                        for (uint32_t f = 0; f < nf; ++f)
+                            ls[j].add(lane_of(W, f), lane_of(X, f), lane_of(Y, f));
+                    }
+                }
+                if (nf == 4) {
+                    stv<kNT>(a.x, c4, X);
+                    stv<kNT>(a.y, c4, Y);
+                    stv<kNT>(a.w, c4, W);
+                    if (last) {
+                        stv<kNT>(a.prev, c4, P);
+                        stv<kNT>(a.cur, c4, C);
+                    }
+                } else {
+                    for (uint32_t f = 0; f < nf; ++f) {
+                        a.x[4 * c4 + f] = lane_of(X, f);
+                        a.y[4 * c4 + f] = lane_of(Y, f);
+                        a.w[4 * c4 + f] = lane_of(W, f);
+                        if (last) {
+                            a.prev[4 * c4 + f] = lane_of(P, f);
+                            a.cur[4 * c4 + f] = lane_of(C, f);
+                        }
+                    }
+                }
+                if (!last) {
+#pragma unroll
+                    for (int j = 0; j < KD; ++j) {
+                        if ((uint32_t)j >= kd_next) break;
+                        float dx[4], dy[4];
+                        group_draws(Sw, T.k0, T.k1, g, s0 + kd + j, dx, dy);
+#pragma unroll
+                        for (int f = 0; f < 4; ++f) {
+                            const float nc = swim(rule, lane_of(X, f), lane_of(Y, f), dx[f], dy[f],
+                                                  H, lane_of(C, f), 1.0f);
+                            if ((uint32_t)f < nf)
+                                best[j] = max(best[j], mag_bits(lane_of(C, f) - nc));
+                            lane_of(C, f) = nc;
+                        }
+                    }
+                }
+            }
+            // the tile's partials of each iteration (lane 0 stores)
+#pragma unroll
+            for (int j = 0; j < KD; ++j) {
+                if ((uint32_t)j >= kd) break;
+                double v[3];
+                for (int k = 0; k < 3; ++k) v[k] = csum_value(wave_csum(ls[j].c[k]));
+                if (lane == 0) {
+                    double* part = a.tile_part + (size_t)((s0 + j) % (2 * KD)) * 3 * a.tile_cap;
+                    for (int k = 0; k < 3; ++k) part[(size_t)k * a.tile_cap + w.tl] = v[k];
+                }
+            }
+        }
+        if (run_school != 0xffffffffu && !last)
+            flush_maxima<KD>(a, best, s0 + kd, kd_next, run_school, lane);
+        if (!barrier_max(bar, 0u, phase, &M_sh)) return;
+        if (last) combine_schools_deep<KD>(a, s0, kd, wave, n_waves, lane);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st_agent(a.step, t0 + a.steps);
+}
+
+// ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
 hipError_t launch_batch_init(const BatchArgs& a, uint32_t /*block*/, hipStream_t stream) {
@@ -468,7 +721,7 @@ hipError_t launch_batch_init(const BatchArgs& a, uint32_t /*block*/, hipStream_t
 }
 
 hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t stream) {
-    uint64_t work = 8ull * a.n_schools;
+    uint64_t work = (uint64_t)(a.max_slots > 8 ? a.max_slots : 8) * a.n_schools;
     if (work < kSyncWords) work = kSyncWords;
     uint64_t blocks = (work + 255) / 256;
     if (blocks > 1024) blocks = 1024;
@@ -499,7 +752,24 @@ const void* batch_fn2(uint32_t fpl, uint32_t naive, uint32_t nt, uint32_t lean) 
     }
 }
 
-const void* batch_fn(uint32_t block, uint32_t fpl, uint32_t naive, uint32_t nt, uint32_t lean) {
+template <bool kNT>
+const void* batch_deep_fn(uint32_t fpl) {
+    switch (fpl) {
+        case 4: return reinterpret_cast<const void*>(batch_deep_kernel<256, 1, kNT, kBatchDepth>);
+        case 8: return reinterpret_cast<const void*>(batch_deep_kernel<256, 2, kNT, kBatchDepth>);
+        case 16: return reinterpret_cast<const void*>(batch_deep_kernel<256, 4, kNT, kBatchDepth>);
+        default: return nullptr;
+    }
+}
+
+// The kernel of a shape and variant (null if there is none: the deep variant
+// runs 256-thread blocks and compensated sums only).
+const void* batch_fn(uint32_t block, uint32_t fpl, uint32_t naive, uint32_t nt, uint32_t variant) {
+    if (variant == kBatchDeep) {
+        if (block != 256 || naive) return nullptr;
+        return nt ? batch_deep_fn<true>(fpl) : batch_deep_fn<false>(fpl);
+    }
+    const uint32_t lean = variant == kBatchLean;
     switch (block) {
         case 256: return batch_fn2<256>(fpl, naive, nt, lean);
         case 1024: return batch_fn2<1024>(fpl, naive, nt, lean);
@@ -508,7 +778,7 @@ const void* batch_fn(uint32_t block, uint32_t fpl, uint32_t naive, uint32_t nt, 
 }
 
 hipError_t batch_resident_grid(uint32_t block, uint32_t fish_per_lane, uint32_t naive,
-                               uint32_t* out_grid) {
+                               uint32_t variant, uint32_t* out_grid) {
     *out_grid = 0;
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -516,8 +786,8 @@ hipError_t batch_resident_grid(uint32_t block, uint32_t fish_per_lane, uint32_t 
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     int per_cu = 1 << 30;
-    for (uint32_t v = 0; v < 4; ++v) {  // every variant must fit
-        const void* fn = batch_fn(block, fish_per_lane, naive, v & 1, v >> 1);
+    for (uint32_t nt = 0; nt < 2; ++nt) {  // both cache policies must fit
+        const void* fn = batch_fn(block, fish_per_lane, naive, nt, variant);
         if (!fn) return hipErrorInvalidValue;
         int b = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, (int)block, 0);
@@ -531,9 +801,9 @@ hipError_t batch_resident_grid(uint32_t block, uint32_t fish_per_lane, uint32_t 
 }
 
 hipError_t launch_batch(const BatchArgs& a, uint32_t block, uint32_t fish_per_lane,
-                        uint32_t naive, uint32_t streaming, uint32_t lean, uint32_t grid,
+                        uint32_t naive, uint32_t streaming, uint32_t variant, uint32_t grid,
                         hipStream_t stream) {
-    const void* fn = batch_fn(block, fish_per_lane, naive, streaming, lean);
+    const void* fn = batch_fn(block, fish_per_lane, naive, streaming, variant);
     if (!fn) return hipErrorInvalidValue;
     hipError_t e = launch_batch_reset(a, stream);
     if (e != hipSuccess) return e;

@@ -37,7 +37,7 @@ struct fsb_batch {
     // uploaded chunk table: schedule, chunk size, wavefronts, tile table it cuts
     uint32_t chunk_sched, chunk_tiles, chunk_waves, chunk_fpl;
     hipGraphExec_t graph;
-    uint32_t graph_steps, graph_grid, graph_block, graph_fpl, graph_lean, graph_sched,
+    uint32_t graph_steps, graph_grid, graph_block, graph_fpl, graph_variant, graph_sched,
         graph_chunks, graph_static;
     uint32_t profile_every;  // time every n-th launch (0 = off)
     uint64_t launches;
@@ -87,8 +87,12 @@ int check_tuning(const fsb_tuning* t) {
     if (!valid_fpl(t->fish_per_thread))
         return fail(FSB_ERR_INVALID_ARG, "fish_per_thread must be 4, 8 or 16");
     if (t->steps_per_launch == 0) return fail(FSB_ERR_INVALID_ARG, "steps_per_launch must be >= 1");
-    if (t->variant != 0 && t->variant != FSB_RUN_FUSED_PREV && t->variant != FSB_RUN_FUSED_LEAN)
-        return fail(FSB_ERR_INVALID_ARG, "variant must be 0, FSB_RUN_FUSED_PREV or FSB_RUN_FUSED_LEAN");
+    if (t->variant != 0 && t->variant != FSB_RUN_FUSED_PREV && t->variant != FSB_RUN_FUSED_LEAN &&
+        t->variant != FSB_RUN_FUSED_DEEP)
+        return fail(FSB_ERR_INVALID_ARG,
+                    "variant must be 0, FSB_RUN_FUSED_PREV, FSB_RUN_FUSED_LEAN or FSB_RUN_FUSED_DEEP");
+    if (t->variant == FSB_RUN_FUSED_DEEP && t->block_size != 256)
+        return fail(FSB_ERR_INVALID_ARG, "the deep variant runs 256-thread blocks");
     if (t->schedule != FSB_SCHED_STATIC && t->schedule != FSB_SCHED_DYNAMIC &&
         t->schedule != FSB_SCHED_GUIDED)
         return fail(FSB_ERR_INVALID_ARG, "schedule must be FSB_SCHED_STATIC, _DYNAMIC or _GUIDED");
@@ -97,12 +101,22 @@ int check_tuning(const fsb_tuning* t) {
     return FSB_OK;
 }
 
-// Variant 0: lean once the 32-byte variant's live columns reach the 256 MiB
-// last-level cache (the single-school rule, measured the same way).
-uint32_t use_lean(const fsb_batch* b) {
-    if (b->tuning.variant == FSB_RUN_FUSED_LEAN) return 1;
-    if (b->tuning.variant == FSB_RUN_FUSED_PREV) return 0;
-    return b->total_fish * 16ull >= (256ull << 20) ? 1 : 0;
+// The deep variant needs compensated sums and positions that do not depend on
+// weights (no weighted rule); the workspace of such a batch holds its rings.
+bool deep_capable(const fsb_config& c) {
+    return c.reduce_mode == FSB_REDUCE_COMPENSATED && !(c.swim_rule & FSB_SWIM_WEIGHTED);
+}
+
+// The kernel variant (kBatch*) of the tuning.  Variant 0: deep where it can
+// run (256-thread blocks), else lean once the 32-byte variant's live columns
+// reach the 256 MiB last-level cache (the single-school rule, measured the
+// same way).
+uint32_t batch_variant(const fsb_batch* b) {
+    if (b->tuning.variant == FSB_RUN_FUSED_DEEP) return kBatchDeep;
+    if (b->tuning.variant == FSB_RUN_FUSED_LEAN) return kBatchLean;
+    if (b->tuning.variant == FSB_RUN_FUSED_PREV) return kBatchPrev;
+    if (deep_capable(b->cfg) && b->tuning.block_size == 256) return kBatchDeep;
+    return b->total_fish * 16ull >= (256ull << 20) ? kBatchLean : kBatchPrev;
 }
 
 // Build and upload the tile table for `fpl` fish per lane (synchronises).
@@ -191,7 +205,15 @@ int set_schedule(fsb_batch* b, uint32_t waves) {
 int grid_for(fsb_batch* b, const fsb_tuning& tu, uint32_t* grid) {
     const uint32_t naive = b->cfg.reduce_mode == FSB_REDUCE_NAIVE_F32;
     uint32_t g = 0;
-    FSB_HIP_TRY(batch_resident_grid(tu.block_size, tu.fish_per_thread, naive, &g), "occupancy query");
+    const fsb_tuning saved = b->tuning;
+    b->tuning = tu;
+    const uint32_t variant = batch_variant(b);
+    b->tuning = saved;
+    if (variant == kBatchDeep && !deep_capable(b->cfg))
+        return fail(FSB_ERR_UNSUPPORTED,
+                    "the deep variant needs compensated sums and no weighted swim rule");
+    FSB_HIP_TRY(batch_resident_grid(tu.block_size, tu.fish_per_thread, naive, variant, &g),
+                "occupancy query");
     if (tu.blocks_per_cu) {
         int dev = 0, cus = 0;
         FSB_HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
@@ -221,7 +243,7 @@ int launch_once(fsb_batch* b, uint32_t steps, uint32_t grid) {
     const uint32_t nt = b->total_fish * 16ull > (256ull << 20);
     const BatchArgs a = launch_args(b, steps, grid);
     hipError_t e = launch_batch(a, b->tuning.block_size, b->tuning.fish_per_thread, naive, nt,
-                                use_lean(b), grid, b->stream);
+                                batch_variant(b), grid, b->stream);
     if (e == hipErrorCooperativeLaunchTooLarge)
         return fail(FSB_ERR_UNSUPPORTED, "batched grid cannot be co-resident");
     if (e != hipSuccess) return hip_fail(e, "batched kernel launch");
@@ -232,7 +254,7 @@ int launch_once(fsb_batch* b, uint32_t steps, uint32_t grid) {
 int ensure_graph(fsb_batch* b, uint32_t steps, uint32_t grid) {
     if (b->graph && b->graph_steps == steps && b->graph_grid == grid &&
         b->graph_block == b->tuning.block_size && b->graph_fpl == b->tuning.fish_per_thread &&
-        b->graph_lean == use_lean(b) && b->graph_sched == b->tuning.schedule &&
+        b->graph_variant == batch_variant(b) && b->graph_sched == b->tuning.schedule &&
         b->graph_chunks == b->args.n_chunks && b->graph_static == b->args.static_chunk)
         return FSB_OK;
     if (b->graph) {
@@ -245,7 +267,7 @@ int ensure_graph(fsb_batch* b, uint32_t steps, uint32_t grid) {
     const BatchArgs a = launch_args(b, steps, grid);
     FSB_HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     hipError_t e = launch_batch(a, b->tuning.block_size, b->tuning.fish_per_thread, naive, nt,
-                                use_lean(b), grid, b->capture);
+                                batch_variant(b), grid, b->capture);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->capture, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -262,7 +284,7 @@ int ensure_graph(fsb_batch* b, uint32_t steps, uint32_t grid) {
     b->graph_grid = grid;
     b->graph_block = b->tuning.block_size;
     b->graph_fpl = b->tuning.fish_per_thread;
-    b->graph_lean = use_lean(b);
+    b->graph_variant = batch_variant(b);
     b->graph_sched = b->tuning.schedule;
     b->graph_chunks = b->args.n_chunks;
     b->graph_static = b->args.static_chunk;
@@ -430,7 +452,7 @@ int fsb_batch_workspace_bytes(const fsb_config* common, uint32_t n_schools, cons
     uint64_t cap = 0, total = 0;
     rc = check_schools(n_schools, starts, sizes, &cap, &total);
     if (rc) return rc;
-    *out_bytes = batch_layout(n_schools, cap, common->history_len).total;
+    *out_bytes = batch_layout(n_schools, cap, common->history_len, deep_capable(*common)).total;
     return FSB_OK;
 }
 
@@ -451,7 +473,7 @@ int fsb_batch_init(const fsb_config* common, uint32_t n_schools, const uint64_t*
     if (packed_len < end) return fail(FSB_ERR_INVALID_ARG, "packed columns are shorter than the last school");
     rc = check_columns(packed, packed_len);
     if (rc) return rc;
-    const BatchLayout L = batch_layout(n_schools, cap, common->history_len);
+    const BatchLayout L = batch_layout(n_schools, cap, common->history_len, deep_capable(*common));
     rc = check_workspace(workspace, workspace_bytes, L.total);
     if (rc) return rc;
 
@@ -468,7 +490,7 @@ int fsb_batch_init(const fsb_config* common, uint32_t n_schools, const uint64_t*
     b->ws_bytes = workspace_bytes;
     b->stream = static_cast<hipStream_t>(stream);
     b->L = L;
-    b->tuning = fsb_tuning{1024, 8, 100, 0, 0, FSB_SCHED_STATIC, 0};
+    b->tuning = fsb_tuning{deep_capable(*common) ? 256u : 1024u, 8, 100, 0, 0, FSB_SCHED_STATIC, 0};
 
     char* base = static_cast<char*>(workspace);
     BatchArgs& a = b->args;
@@ -494,6 +516,7 @@ int fsb_batch_init(const fsb_config* common, uint32_t n_schools, const uint64_t*
     a.school_max = reinterpret_cast<uint32_t*>(base + L.school_max);
     a.tile_part = reinterpret_cast<double*>(base + L.tile_part);
     a.tile_cap = L.tile_cap;
+    a.max_slots = deep_capable(*common) ? 3 * kMaxDepth : 3;
     a.school_naive = reinterpret_cast<float*>(base + L.school_naive);
     a.rec = reinterpret_cast<fsb_record*>(base + L.rec);
     a.hist_len = common->history_len;
@@ -595,6 +618,19 @@ int fsb_autotune(fsb_batch* b, uint64_t probe_steps, fsb_tuning* out) {
             best = tu;
         }
     }
+    // the deep variant (256-thread blocks), where it can run
+    if (deep_capable(b->cfg))
+        for (uint32_t fpl : kBatchFishPerLane) {
+            fsb_tuning tu{256, fpl, (uint32_t)probe_steps, 0, FSB_RUN_FUSED_DEEP, FSB_SCHED_STATIC, 0};
+            double ms = 0.0;
+            int rc = probe(b, tu, probe_steps, &ms);
+            if (rc == FSB_ERR_UNSUPPORTED) continue;
+            if (rc) return rc;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = tu;
+            }
+        }
     // work-queue schedules against the static one (one tile per chunk is
     // left out: at CFG5 scale its one atomic per tile saturates the counter)
     const fsb_tuning queues[5] = {{0, 0, 0, 0, 0, FSB_SCHED_DYNAMIC, 4},

@@ -184,9 +184,12 @@ struct BatchArgs {
     Ctrl* ctrl;
     uint32_t* sync;                 // barrier words
     uint32_t* step;                 // device iteration counter (advanced by each launch)
-    uint32_t* school_max;           // [3][S] bits of M of iteration s in slot s % 3
-    double* tile_part;              // [2][3][tile_cap] per-tile binary64 sums, slot s & 1
+    uint32_t* school_max;           // [3][S] bits of M of iteration s in slot s % 3 (deep
+                                    // kernel: [3 kMaxDepth][S], slot s % (3 kBatchDepth))
+    double* tile_part;              // [2][3][tile_cap] per-tile binary64 sums, slot s & 1 (deep
+                                    // kernel: [2 kMaxDepth][3][tile_cap], slot s % (2 kBatchDepth))
     uint32_t tile_cap;
+    uint32_t max_slots;             // slots of the per-school max ring the layout holds
     float* school_naive;            // [2][S][4] float32 atomic sums of the naive mode
     fsb_record* rec;                // [hist_len][S]
     uint32_t hist_len;
@@ -210,17 +213,21 @@ struct BatchLayout {
     uint32_t tile_cap;
 };
 
-inline BatchLayout batch_layout(uint32_t n_schools, uint64_t tile_cap, uint32_t history_len) {
+// `deep`: room for the deep kernel's per-iteration rings (it needs
+// compensated sums and no weighted rule; other configurations never run it).
+inline BatchLayout batch_layout(uint32_t n_schools, uint64_t tile_cap, uint32_t history_len,
+                                bool deep) {
     BatchLayout L;
     const size_t S = n_schools;
+    const size_t part_slots = deep ? 2 * kMaxDepth : 2, max_slots = deep ? 3 * kMaxDepth : 3;
     L.tile_cap = (uint32_t)tile_cap;
     L.ctrl = 0;
     L.sync = align_up(sizeof(Ctrl), kAlign);
     L.tile_begin = align_up(L.sync + kSyncWords * sizeof(uint32_t), kAlign);
     L.tiles = align_up(L.tile_begin + (S + 1) * 4, kAlign);
     L.tile_part = align_up(L.tiles + tile_cap * sizeof(Tile), kAlign);
-    L.school_max = align_up(L.tile_part + 2 * 3 * tile_cap * sizeof(double), kAlign);
-    L.school_naive = align_up(L.school_max + 3 * S * 4, kAlign);
+    L.school_max = align_up(L.tile_part + part_slots * 3 * tile_cap * sizeof(double), kAlign);
+    L.school_naive = align_up(L.school_max + max_slots * S * 4, kAlign);
     L.rec = align_up(L.school_naive + 2 * S * 4 * sizeof(float), kAlign);
     L.chunks = align_up(L.rec + (size_t)history_len * S * sizeof(fsb_record), kAlign);
     L.queue = align_up(L.chunks + (tile_cap + 1) * sizeof(uint32_t), kAlign);
@@ -233,16 +240,23 @@ constexpr uint32_t kBatchBlocks[2] = {256, 1024};
 constexpr uint32_t kBatchFishPerLane[3] = {4, 8, 16};
 constexpr uint32_t kBatchMinTileFish = 64 * 4;
 
+// Batch kernel variants.
+constexpr uint32_t kBatchPrev = 0;  // x, y, w, prev live: 32 B/fish per iteration
+constexpr uint32_t kBatchLean = 1;  // x, y, w live, each swim done twice: 24 B
+constexpr uint32_t kBatchDeep = 2;  // kBatchDepth iterations per barrier (256-thread blocks,
+                                    // compensated sums, no weighted rule): 24 B per superstep
+constexpr uint32_t kBatchDepth = 8;
+
 hipError_t launch_batch_init(const BatchArgs& a, uint32_t block, hipStream_t stream);
 hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t stream);
 // Persistent launch of a.steps iterations; `streaming` selects non-temporal
-// column access, `lean` the 24-byte variant (x, y, w live, each swim done
-// twice).  Cooperative, so the grid is guaranteed co-resident.
+// column access, `variant` one of kBatch*.  Cooperative, so the grid is
+// guaranteed co-resident.
 hipError_t launch_batch(const BatchArgs& a, uint32_t block, uint32_t fish_per_lane,
-                        uint32_t naive, uint32_t streaming, uint32_t lean, uint32_t grid,
+                        uint32_t naive, uint32_t streaming, uint32_t variant, uint32_t grid,
                         hipStream_t stream);
-// Largest co-resident grid for a shape (0 if it cannot run).
+// Largest co-resident grid for a shape and variant (0 if it cannot run).
 hipError_t batch_resident_grid(uint32_t block, uint32_t fish_per_lane, uint32_t naive,
-                               uint32_t* out_grid);
+                               uint32_t variant, uint32_t* out_grid);
 
 }  // namespace fsb

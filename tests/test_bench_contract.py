@@ -70,6 +70,10 @@ def test_persistent_bytes_accounting():
     assert bench.persistent_bytes("deep", n, 16) == n * (8 + 24 * 2 + 8)
     assert bench.persistent_bytes("deep", n, 17) == n * (8 + 24 * 3 + 8)
     assert bench.fused_variant(1 << 26) == "deep"
+    assert bench.batch_bytes("deep", n, 500, 1000, 1) == n * (16 + 24 * 63)
+    assert bench.batch_bytes("deep", n, 20, 8, 3) == n * (16 * 3 + 24 * 3)
+    assert bench.batch_bytes("lean", n, 500, 500, 1) == n * (16 + 24 * 500)
+    assert bench.batch_bytes("prev", n, 10, 10, 1) == n * (20 + 32 * 9 + 24)
     f = bench.fused_variant
     assert f(1 << 21, False) == "regs" and f((1 << 21) + 4, False) == "prev"
     assert f(1 << 24, False) == "lean" and f(1 << 26, False) == "lean"

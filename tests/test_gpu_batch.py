@@ -239,7 +239,10 @@ def test_autotune_and_cache(torch_cuda, tmp_path):
         d = fsb.tuning_dict(tune)
         assert d["block_size"] in (256, 1024) and d["fish_per_thread"] in (4, 8, 16)
         assert d["steps_per_launch"] >= 1
-        assert d["variant"] in (fsb.FSB_RUN_FUSED_PREV, fsb.FSB_RUN_FUSED_LEAN)
+        assert d["variant"] in (fsb.FSB_RUN_FUSED_PREV, fsb.FSB_RUN_FUSED_LEAN,
+                                fsb.FSB_RUN_FUSED_DEEP)
+        if d["variant"] == fsb.FSB_RUN_FUSED_DEEP:
+            assert d["block_size"] == 256
         assert d["schedule"] in (fsb.FSB_SCHED_STATIC, fsb.FSB_SCHED_DYNAMIC,
                                  fsb.FSB_SCHED_GUIDED)
         assert b.t > t0

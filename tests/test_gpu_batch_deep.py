@@ -1,0 +1,174 @@
+"""Deep batched kernel (fsb_tuning.variant = FSB_RUN_FUSED_DEEP): eight
+iterations of every school per grid barrier.  Every school must equal the
+oracle run of that school alone, bit for bit (columns, every iteration's M;
+sums within the 1e-6 gate), for iteration counts that fill the last
+superstep and counts that leave it short, across graph-replayed launches of
+any length, under every tile schedule, and interleaved with the other
+variants."""
+import numpy as np
+import pytest
+
+import paper_2507_20173_amd as fsb
+from oracle.oracle import default
+from paper_2507_20173_amd.workloads import log_uniform_school_sizes, packed_starts, school_seeds
+from parity_util import assert_columns_equal, assert_sums_close, oracle_config
+
+pytestmark = pytest.mark.gpu
+DEEP = fsb.FSB_RUN_FUSED_DEEP
+SIZES = [1, 2, 3, 5, 7, 64, 65, 255, 256, 257, 1000, 4099, 16385, 65537]
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def O():
+    return default()
+
+
+def announce(msg):
+    print(f"[batch deep] {msg}", flush=True)
+
+
+def check_against_oracle(O, b, steps, common, schools=None, what=""):
+    _, sums, mx = b.results()
+    for i in (range(b.n) if schools is None else schools):
+        cfg = fsb.FsbConfig(n_fish=int(b.sizes[i]), seed=int(b.seeds[i]),
+                            pond_half=common.pond_half, swim_step=common.swim_step,
+                            w_min=common.w_min, w_max=common.w_max, swim_rule=common.swim_rule)
+        ocfg = oracle_config(cfg)
+        school = O.init(ocfg)
+        m, s, a = O.run(ocfg, school, 0, steps)
+        assert mx[i].view(np.uint32) == m[-1].view(np.uint32), f"{what} school {i}"
+        assert_sums_close(sums[i], s[-1], a[-1], what=f"{what} school {i}")
+        assert_columns_equal(b.school_state(i), school, f"{what} school {i}")
+        for step in range(max(0, steps - common.history_len), steps):
+            h = b.history(step)
+            assert h["step_lo"][i] == step
+            assert h["max_delta"][i].view(np.uint32) == m[step].view(np.uint32), (what, i, step)
+
+
+@pytest.mark.parametrize("fpl", [4, 8, 16])
+@pytest.mark.parametrize("steps,per_launch", [(8, 8), (11, 11), (11, 3), (17, 8), (5, 100)])
+def test_deep_batch_matches_oracle(torch_cuda, O, fpl, steps, per_launch):
+    announce(f"fpl={fpl} steps={steps} per launch={per_launch}")
+    common = fsb.FsbConfig(n_fish=0, history_len=steps)
+    seeds = [31 * i + 7 for i in range(len(SIZES))]
+    b = fsb.Batch(common, SIZES, seeds, starts=packed_starts(SIZES, 4))
+    b.run(steps, fsb.tuning(256, fpl, per_launch, variant=DEEP))
+    check_against_oracle(O, b, steps, common, what=f"deep fpl={fpl}")
+    b.close()
+
+
+SCHEDULES = [(fsb.FSB_SCHED_STATIC, 0), (fsb.FSB_SCHED_STATIC, 3), (fsb.FSB_SCHED_DYNAMIC, 1),
+             (fsb.FSB_SCHED_DYNAMIC, 16), (fsb.FSB_SCHED_GUIDED, 4)]
+
+
+@pytest.mark.parametrize("sched,chunk", SCHEDULES, ids=[f"s{s}c{c}" for s, c in SCHEDULES])
+def test_deep_schedules_identical_to_lean(torch_cuda, sched, chunk):
+    """Columns and maxima equal the lean variant's bit for bit; the sums are
+    bit-identical across schedules of the deep variant (tile partials folded
+    in tile order)."""
+    announce(f"schedule {sched} chunk {chunk}")
+    common = fsb.FsbConfig(n_fish=0, history_len=10)
+    seeds = list(range(len(SIZES)))
+    ref = fsb.Batch(common, SIZES, seeds)
+    ref.run(10, fsb.tuning(1024, 8, 10, variant=fsb.FSB_RUN_FUSED_LEAN))
+    ref_state = [ref.school_state(i) for i in range(ref.n)]
+    _, _, ref_max = ref.results()
+    ref.close()
+    base = fsb.Batch(common, SIZES, seeds)
+    base.run(10, fsb.tuning(256, 8, 10, variant=DEEP))
+    _, base_sums, _ = base.results()
+    base.close()
+    b = fsb.Batch(common, SIZES, seeds)
+    b.run(10, fsb.tuning(256, 8, 4, variant=DEEP, schedule=sched, chunk_tiles=chunk))
+    _, sums, mx = b.results()
+    assert np.array_equal(mx, ref_max)
+    assert np.array_equal(sums.view(np.uint64), base_sums.view(np.uint64))
+    for i in range(b.n):
+        got = b.school_state(i)
+        for k in got:
+            assert np.array_equal(got[k].view(np.uint32), ref_state[i][k].view(np.uint32)), (i, k)
+    b.close()
+
+
+def test_deep_batch_interleaved_with_other_variants(torch_cuda, O):
+    announce("interleaved")
+    common = fsb.FsbConfig(n_fish=0, history_len=19)
+    sizes = [3, 1000, 4099, 65537]
+    seeds = [11, 12, 13, 14]
+    b = fsb.Batch(common, sizes, seeds)
+    b.run(3, fsb.tuning(1024, 8, 3, variant=fsb.FSB_RUN_FUSED_LEAN))
+    b.run(9, fsb.tuning(256, 16, 9, variant=DEEP))
+    b.run(2, fsb.tuning(256, 4, 2, variant=fsb.FSB_RUN_FUSED_PREV))
+    b.run(5, fsb.tuning(256, 8, 2, variant=DEEP))
+    check_against_oracle(O, b, 19, common, what="interleaved")
+    b.close()
+
+
+def test_deep_batch_greedy_rule(torch_cuda, O):
+    announce("greedy")
+    common = fsb.FsbConfig(n_fish=0, swim_step=0.5, swim_rule=fsb.FSB_SWIM_GREEDY, history_len=9)
+    sizes = [5, 257, 4099, 16385]
+    b = fsb.Batch(common, sizes, [1, 2, 3, 4])
+    b.run(9, fsb.tuning(256, 8, 9, variant=DEEP))
+    check_against_oracle(O, b, 9, common, what="greedy")
+    b.close()
+
+
+def test_deep_batch_gaps_untouched(torch_cuda):
+    announce("gaps")
+    sizes = [5, 9, 1, 130]
+    starts = [0, 16, 40, 48]
+    b = fsb.Batch(fsb.FsbConfig(n_fish=0), sizes, [1, 2, 3, 4], starts=starts)
+    b.sync()
+    mask = np.ones(b.cols["x"].numel(), bool)
+    for a, n in zip(starts, sizes):
+        mask[a:a + n] = False
+    for v in b.cols.values():
+        v[torch_cuda.from_numpy(mask).to(v.device)] = 12345.0
+    b.run(10, fsb.tuning(256, 4, 10, variant=DEEP))
+    b.sync()
+    for k, v in b.cols.items():
+        assert (v.cpu().numpy()[mask] == 12345.0).all(), k
+    b.close()
+
+
+def test_deep_cfg5_full_shape(torch_cuda, O):
+    """The 4096-school shape for 11 iterations (a full and a short superstep):
+    the smallest schools and two mid-sized ones against the oracle."""
+    sizes = log_uniform_school_sizes(4096)
+    seeds = school_seeds(4096)
+    steps = 11
+    announce(f"cfg5 deep {int(sizes.sum())} fish, {steps} iterations")
+    common = fsb.FsbConfig(n_fish=0, history_len=steps)
+    b = fsb.Batch(common, sizes, seeds)
+    b.run(steps, fsb.tuning(256, 8, steps, variant=DEEP, schedule=fsb.FSB_SCHED_DYNAMIC,
+                            chunk_tiles=16))
+    _, sums, mx = b.results()
+    assert (mx > 0).all() and (mx <= 0.1 * np.sqrt(2) + 1e-4).all()
+    order = np.argsort(sizes)
+    check_against_oracle(O, b, steps, common, schools=list(order[:4]) + list(order[2048:2050]),
+                         what="cfg5 deep")
+    b.close()
+
+
+def test_deep_batch_refusals(torch_cuda):
+    b = fsb.Batch(fsb.FsbConfig(n_fish=0), [10, 20], [1, 2])
+    with pytest.raises(fsb.FsbError) as e:
+        b.run(2, fsb.tuning(1024, 8, 2, variant=DEEP))
+    assert e.value.code == fsb._lib.FSB_ERR_INVALID_ARG
+    b.run(2, fsb.tuning(256, 8, 2, variant=DEEP))  # the handle still works
+    b.close()
+    for cfg in (dict(reduce_mode=fsb.FSB_REDUCE_NAIVE_F32), dict(swim_rule=fsb.FSB_SWIM_WEIGHTED)):
+        b = fsb.Batch(fsb.FsbConfig(n_fish=0, **cfg), [10, 20], [1, 2])
+        with pytest.raises(fsb.FsbError) as e:
+            b.run(2, fsb.tuning(256, 8, 2, variant=DEEP))
+        assert e.value.code == fsb._lib.FSB_ERR_UNSUPPORTED
+        b.run(2, fsb.tuning(256, 8, 2))  # the library's choice still runs
+        b.close()

@@ -186,13 +186,15 @@ for mode in (fsb.FSB_RUN_FUSED_REGS, fsb.FSB_RUN_FUSED_LEAN, fsb.FSB_RUN_FUSED_D
     except fsb.FsbError as e:
         out.append(f"fused {e.code} {e}")
     s.close()
-b = fsb.Batch(fsb.FsbConfig(n_fish=0), [1000] * 64, list(range(64)))
-b.run(20, fsb.tuning(1024, 8, 20))
-try:
-    b.sync()
-    out.append("batch ok")
-except fsb.FsbError as e:
-    out.append(f"batch {e.code} {e}")
+for tune in (fsb.tuning(1024, 8, 20), fsb.tuning(256, 8, 20, variant=fsb.FSB_RUN_FUSED_DEEP)):
+    b = fsb.Batch(fsb.FsbConfig(n_fish=0), [1000] * 64, list(range(64)))
+    b.run(20, tune)
+    try:
+        b.sync()
+        out.append("batch ok")
+    except fsb.FsbError as e:
+        out.append(f"batch {e.code} {e}")
+    b.close()
 print("|".join(out), flush=True)
 """
 
@@ -214,12 +216,13 @@ def test_barrier_timeout_is_reported(torch_cuda):
     r = subprocess.run([sys.executable, "-c", CHILD_TIMEOUT, root], env=env, capture_output=True,
                        text=True, timeout=240)
     assert r.returncode == 0, r.stderr[-2000:]
-    *fused, batch = r.stdout.strip().splitlines()[-1].split("|")
+    parts = r.stdout.strip().splitlines()[-1].split("|")
     code = str(fsb._lib.FSB_ERR_DEVICE)
-    assert len(fused) == 3  # register-resident, lean, deep
-    for f in fused:
-        assert f.startswith(f"fused {code}") and "timed out" in f, f
-    assert batch.startswith(f"batch {code}") and "timed out" in batch, batch
+    assert len(parts) == 5  # register-resident, lean, deep; batches lean and deep
+    for p in parts[:3]:
+        assert p.startswith(f"fused {code}") and "timed out" in p, p
+    for p in parts[3:]:
+        assert p.startswith(f"batch {code}") and "timed out" in p, p
 
 
 @pytest.mark.parametrize("grid", [1, 2, 16, 17, 100, 0])
