@@ -463,7 +463,9 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
 // maxima of iteration t live in slot t mod 3 KD of the max ring (written by
 // the previous superstep's look-ahead, read by this one, cleared by the next
 // one's combine), the tile partials of iteration t in slot t mod 2 KD.
-// Compensated sums only; 256-thread blocks (a lane needs ~230 registers).
+// Compensated sums only; 256-thread blocks.  Registers are capped at 168 per
+// lane so that three waves share each SIMD (its 512 registers per lane / 3):
+// at 169 the occupancy drops to two waves and an iteration takes ~18% longer.
 // ---------------------------------------------------------------------------
 template <int KD>
 __device__ void combine_schools_deep(const BatchArgs& a, uint32_t t0, uint32_t count,
@@ -509,15 +511,17 @@ __device__ __forceinline__ void flush_maxima(const BatchArgs& a, uint32_t (&best
     }
 }
 
-template <int BLOCK, int GPL, bool kNT, int KD>
-__global__ __launch_bounds__(BLOCK) void batch_deep_kernel(BatchArgs a) {
+template <int BLOCK, int GPL, bool kNT, int KD, uint32_t kRule>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3)))
+void batch_deep_kernel(BatchArgs a) {
+    static_assert((kRule & kSwimWeighted) == 0, "the deep kernel never runs the weighted rule");
     constexpr uint32_t WPB = BLOCK / kWave;
     __shared__ uint32_t M_sh;
     const uint32_t lane = threadIdx.x % kWave;
     const uint32_t wave = uniform(blockIdx.x * WPB + threadIdx.x / kWave);
     const uint32_t n_waves = gridDim.x * WPB;
     const float H = a.H, Sw = a.S, wmin = a.wmin, wmax = a.wmax;
-    const SwimRule rule{a.rule, a.wmin};
+    const SwimRule rule{kRule, a.wmin};  // compile-time flags: no run-time rule tests
     const Barrier bar{a.sync, a.ctrl, a.spin_limit};
     uint32_t phase = 0;
     const uint32_t t0 = uniform(ld_agent(a.step));
@@ -549,9 +553,10 @@ __global__ __launch_bounds__(BLOCK) void batch_deep_kernel(BatchArgs a) {
                     X = ldv<kNT>(a.x, c4);
                     Y = ldv<kNT>(a.y, c4);
                 } else {  // the school's ragged last group: only its own fish are read
-                    for (uint32_t f = 0; f < 4; ++f) {
-                        lane_of(X, f) = f < nf ? a.x[4 * c4 + f] : 0.0f;
-                        lane_of(Y, f) = f < nf ? a.y[4 * c4 + f] : 0.0f;
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) {
+                        lane_of(X, f) = (uint32_t)f < nf ? a.x[4 * c4 + f] : 0.0f;
+                        lane_of(Y, f) = (uint32_t)f < nf ? a.y[4 * c4 + f] : 0.0f;
                     }
                 }
 #pragma unroll
@@ -607,10 +612,10 @@ __global__ __launch_bounds__(BLOCK) void batch_deep_kernel(BatchArgs a) {
 #pragma unroll
                 for (int j = 0; j < KD; ++j)
                     if ((uint32_t)j < kd)
-                        M[j] = __uint_as_float(
-                            a.school_max[(size_t)((s0 + j) % (3 * KD)) * a.n_schools + T.school]);
+                        M[j] = __uint_as_float(uniform(
+                            a.school_max[(size_t)((s0 + j) % (3 * KD)) * a.n_schools + T.school]));
             }
-            LaneSums<false> ls[KD];
+            LaneSumsF64 ls[KD];
 #pragma unroll
             for (int q = 0; q < GPL; ++q) {
                 const uint32_t jg = lane + q * kWave;
@@ -623,11 +628,14 @@ __global__ __launch_bounds__(BLOCK) void batch_deep_kernel(BatchArgs a) {
                     X = ldv<kNT>(a.x, c4);
                     Y = ldv<kNT>(a.y, c4);
                     W = ldv<kNT>(a.w, c4);
-                } else {
-                    for (uint32_t f = 0; f < 4; ++f) {
-                        lane_of(X, f) = f < nf ? a.x[4 * c4 + f] : 0.0f;
-                        lane_of(Y, f) = f < nf ? a.y[4 * c4 + f] : 0.0f;
-                        lane_of(W, f) = f < nf ? a.w[4 * c4 + f] : 0.0f;
+                } else {  // every index below is a constant once the loops unroll, so the
+                          // float4 state stays in registers (a run-time lane index would
+                          // move it to memory for the whole loop)
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) {
+                        lane_of(X, f) = (uint32_t)f < nf ? a.x[4 * c4 + f] : 0.0f;
+                        lane_of(Y, f) = (uint32_t)f < nf ? a.y[4 * c4 + f] : 0.0f;
+                        lane_of(W, f) = (uint32_t)f < nf ? a.w[4 * c4 + f] : 0.0f;
                     }
                 }
 #pragma unroll
@@ -648,8 +656,9 @@ __global__ __launch_bounds__(BLOCK) void batch_deep_kernel(BatchArgs a) {
                     if (nf == 4) {
                         ls[j].add4(W, X, Y);
                     } else {
-                        for (uint32_t f = 0; f < nf; ++f)
-                            ls[j].add(lane_of(W, f), lane_of(X, f), lane_of(Y, f));
+#pragma unroll
+                        for (int f = 0; f < 4; ++f)
+                            if ((uint32_t)f < nf) ls[j].add(lane_of(W, f), lane_of(X, f), lane_of(Y, f));
                     }
                 }
                 if (nf == 4) {
@@ -661,7 +670,9 @@ __global__ __launch_bounds__(BLOCK) void batch_deep_kernel(BatchArgs a) {
                         stv<kNT>(a.cur, c4, C);
                     }
                 } else {
-                    for (uint32_t f = 0; f < nf; ++f) {
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) {
+                        if ((uint32_t)f >= nf) break;
                         a.x[4 * c4 + f] = lane_of(X, f);
                         a.y[4 * c4 + f] = lane_of(Y, f);
                         a.w[4 * c4 + f] = lane_of(W, f);
@@ -688,12 +699,16 @@ __global__ __launch_bounds__(BLOCK) void batch_deep_kernel(BatchArgs a) {
                     }
                 }
             }
-            // the tile's partials of each iteration (lane 0 stores)
+            // the tile's partials of each iteration (lane 0 stores): a
+            // binary64 butterfly over the wave, whose six roundings are far
+            // below the lanes' own binary32 error; a tile is one wave's work,
+            // so this runs KD x 3 times per tile and costs a third of what a
+            // TwoSum butterfly does
 #pragma unroll
             for (int j = 0; j < KD; ++j) {
                 if ((uint32_t)j >= kd) break;
                 double v[3];
-                for (int k = 0; k < 3; ++k) v[k] = csum_value(wave_csum(ls[j].c[k]));
+                for (int k = 0; k < 3; ++k) v[k] = wave_sum_f64(ls[j].v[k]);
                 if (lane == 0) {
                     double* part = a.tile_part + (size_t)((s0 + j) % (2 * KD)) * 3 * a.tile_cap;
                     for (int k = 0; k < 3; ++k) part[(size_t)k * a.tile_cap + w.tl] = v[k];
@@ -752,22 +767,25 @@ const void* batch_fn2(uint32_t fpl, uint32_t naive, uint32_t nt, uint32_t lean) 
     }
 }
 
-template <bool kNT>
+template <bool kNT, uint32_t kRule>
 const void* batch_deep_fn(uint32_t fpl) {
     switch (fpl) {
-        case 4: return reinterpret_cast<const void*>(batch_deep_kernel<256, 1, kNT, kBatchDepth>);
-        case 8: return reinterpret_cast<const void*>(batch_deep_kernel<256, 2, kNT, kBatchDepth>);
-        case 16: return reinterpret_cast<const void*>(batch_deep_kernel<256, 4, kNT, kBatchDepth>);
+        case 4: return reinterpret_cast<const void*>(batch_deep_kernel<256, 1, kNT, kBatchDepth, kRule>);
+        case 8: return reinterpret_cast<const void*>(batch_deep_kernel<256, 2, kNT, kBatchDepth, kRule>);
+        case 16: return reinterpret_cast<const void*>(batch_deep_kernel<256, 4, kNT, kBatchDepth, kRule>);
         default: return nullptr;
     }
 }
 
 // The kernel of a shape and variant (null if there is none: the deep variant
-// runs 256-thread blocks and compensated sums only).
-const void* batch_fn(uint32_t block, uint32_t fpl, uint32_t naive, uint32_t nt, uint32_t variant) {
+// runs 256-thread blocks, compensated sums only, and the plain or greedy rule).
+const void* batch_fn(uint32_t block, uint32_t fpl, uint32_t naive, uint32_t nt, uint32_t variant,
+                     uint32_t rule) {
     if (variant == kBatchDeep) {
-        if (block != 256 || naive) return nullptr;
-        return nt ? batch_deep_fn<true>(fpl) : batch_deep_fn<false>(fpl);
+        if (block != 256 || naive || (rule & kSwimWeighted)) return nullptr;
+        if (rule & kSwimGreedy)
+            return nt ? batch_deep_fn<true, kSwimGreedy>(fpl) : batch_deep_fn<false, kSwimGreedy>(fpl);
+        return nt ? batch_deep_fn<true, 0u>(fpl) : batch_deep_fn<false, 0u>(fpl);
     }
     const uint32_t lean = variant == kBatchLean;
     switch (block) {
@@ -786,14 +804,15 @@ hipError_t batch_resident_grid(uint32_t block, uint32_t fish_per_lane, uint32_t 
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     int per_cu = 1 << 30;
-    for (uint32_t nt = 0; nt < 2; ++nt) {  // both cache policies must fit
-        const void* fn = batch_fn(block, fish_per_lane, naive, nt, variant);
-        if (!fn) return hipErrorInvalidValue;
-        int b = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, (int)block, 0);
-        if (e != hipSuccess) return e;
-        per_cu = b < per_cu ? b : per_cu;
-    }
+    for (uint32_t nt = 0; nt < 2; ++nt)  // both cache policies and both rules must fit
+        for (uint32_t rule : {0u, kSwimGreedy}) {
+            const void* fn = batch_fn(block, fish_per_lane, naive, nt, variant, rule);
+            if (!fn) return hipErrorInvalidValue;
+            int b = 0;
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, (int)block, 0);
+            if (e != hipSuccess) return e;
+            per_cu = b < per_cu ? b : per_cu;
+        }
     uint64_t g = (uint64_t)cus * (uint64_t)(per_cu > 0 ? per_cu : 0);
     if (g > kMaxBarrierBlocks) g = kMaxBarrierBlocks;
     *out_grid = (uint32_t)g;
@@ -803,7 +822,7 @@ hipError_t batch_resident_grid(uint32_t block, uint32_t fish_per_lane, uint32_t 
 hipError_t launch_batch(const BatchArgs& a, uint32_t block, uint32_t fish_per_lane,
                         uint32_t naive, uint32_t streaming, uint32_t variant, uint32_t grid,
                         hipStream_t stream) {
-    const void* fn = batch_fn(block, fish_per_lane, naive, streaming, variant);
+    const void* fn = batch_fn(block, fish_per_lane, naive, streaming, variant, a.rule);
     if (!fn) return hipErrorInvalidValue;
     hipError_t e = launch_batch_reset(a, stream);
     if (e != hipSuccess) return e;

@@ -98,28 +98,28 @@ __device__ __forceinline__ void block_sums(const SchoolArgs& a, LaneSums<kNaive>
     }
 }
 
-// The same for KD iterations of the deep kernel at once (compensated sums
-// only): ls[j] holds iteration t0 + j, for j < kd.
+// The same for KD iterations of the deep kernel at once (its binary64 lane
+// sums, merged in binary64): ls[j] holds iteration t0 + j, for j < kd.
 template <int KD, int BLOCK>
-__device__ __forceinline__ void block_sums_deep(const SchoolArgs& a, LaneSums<false> (&ls)[KD],
+__device__ __forceinline__ void block_sums_deep(const SchoolArgs& a, LaneSumsF64 (&ls)[KD],
                                                 uint32_t t0, uint32_t kd) {
     constexpr int W = BLOCK / kWave;
-    __shared__ CSum wave_cs[KD][3][W];
+    __shared__ double wave_v[KD][3][W];
     const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
 #pragma unroll
     for (int j = 0; j < KD; ++j) {
         if ((uint32_t)j >= kd) break;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const CSum v = wave_csum(ls[j].c[k]);
-            if (lane == 0) wave_cs[j][k][wid] = v;
+            const double v = wave_sum_f64(ls[j].v[k]);
+            if (lane == 0) wave_v[j][k][wid] = v;
         }
     }
     __syncthreads();
     if (threadIdx.x < kd * 3) {  // one thread per (iteration, sum)
         const uint32_t j = threadIdx.x / 3, k = threadIdx.x % 3;
         double v = 0.0;
-        for (int w = 0; w < W; ++w) v += csum_value(wave_cs[j][k][w]);
+        for (int w = 0; w < W; ++w) v += wave_v[j][k][w];
         deep_slot(a, t0 + j, (int)k)[blockIdx.x] = v;
     }
 }
@@ -768,18 +768,21 @@ __global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, F
 // Columns: 24 B per fish per superstep, 24 / KD per fish-iteration; each swim
 // is computed twice, as in the lean kernel.  Every operation of a fish is the
 // plain path's, in the same order, so the bits are the same.  Compensated
-// sums only; the host never picks it under the weighted rule.  Blocks of 512
-// threads (two waves per SIMD, 256 registers each): the KD unrolled swims and
-// KD sets of lane sums spill at 128.
+// sums only; the host never picks it under the weighted rule.  The rule is a
+// template argument (kRule: 0 or kSwimGreedy), so the plain swim carries no
+// run-time tests or selects of the other rules.  Blocks of 512 threads (two
+// waves per SIMD, 256 registers each): the KD unrolled swims and KD sets of
+// lane sums spill at 128.
 // ---------------------------------------------------------------------------
 constexpr int kDeepBlock = 512;
 
-template <int KD, bool kNT>
+template <int KD, bool kNT, uint32_t kRule>
 __global__ __launch_bounds__(kDeepBlock) void fused_deep_kernel(SchoolArgs a, FusedArgs f) {
+    static_assert((kRule & kSwimWeighted) == 0, "the deep kernel never runs the weighted rule");
     constexpr int B = kDeepBlock;
     __shared__ uint32_t M_sh[KD];
     const float H = a.H, wmin = a.wmin, wmax = a.wmax;
-    const SwimRule rule{a.rule, a.wmin};
+    const SwimRule rule{kRule, a.wmin};
     const uint32_t grid = gridDim.x;
     const uint64_t n4 = a.n >> 2;
     const uint64_t stride = (uint64_t)grid * B;
@@ -861,7 +864,7 @@ __global__ __launch_bounds__(kDeepBlock) void fused_deep_kernel(SchoolArgs a, Fu
         for (int j = 0; j < KD; ++j) M_prev[j] = M_bits[j];
         kd_prev = kd;
 
-        LaneSums<false> ls[KD];
+        LaneSumsF64 ls[KD];
         uint32_t best[KD];
 #pragma unroll
         for (int j = 0; j < KD; ++j) best[j] = 0u;
@@ -1204,17 +1207,21 @@ const void* pick_fused(uint32_t naive, uint32_t streaming, uint32_t lean) {
     return streaming ? fused_fn<false, true>(lean) : fused_fn<false, false>(lean);
 }
 
-template <bool kNT>
+template <bool kNT, uint32_t kRule>
 const void* deep_fn(uint32_t depth) {
     switch (depth) {
-        case 2: return reinterpret_cast<const void*>(fused_deep_kernel<2, kNT>);
-        case 4: return reinterpret_cast<const void*>(fused_deep_kernel<4, kNT>);
-        default: return reinterpret_cast<const void*>(fused_deep_kernel<8, kNT>);
+        case 2: return reinterpret_cast<const void*>(fused_deep_kernel<2, kNT, kRule>);
+        case 4: return reinterpret_cast<const void*>(fused_deep_kernel<4, kNT, kRule>);
+        default: return reinterpret_cast<const void*>(fused_deep_kernel<8, kNT, kRule>);
     }
 }
 
-const void* pick_deep(uint32_t streaming, uint32_t depth) {
-    return streaming ? deep_fn<true>(depth) : deep_fn<false>(depth);
+// The deep kernel of a cache policy, depth and swim rule (greedy or plain;
+// the host never asks for the weighted rule).
+const void* pick_deep(uint32_t streaming, uint32_t depth, uint32_t rule) {
+    if (rule & kSwimGreedy)
+        return streaming ? deep_fn<true, kSwimGreedy>(depth) : deep_fn<false, kSwimGreedy>(depth);
+    return streaming ? deep_fn<true, 0u>(depth) : deep_fn<false, 0u>(depth);
 }
 
 hipError_t deep_resident_grid(uint32_t* out_grid) {
@@ -1225,12 +1232,14 @@ hipError_t deep_resident_grid(uint32_t* out_grid) {
     if (e != hipSuccess) return e;
     int per_cu = 1 << 30;
     for (uint32_t depth : {2u, 4u, 8u})  // every instance must fit
-        for (uint32_t nt = 0; nt < 2; ++nt) {
-            int b = 0;
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, pick_deep(nt, depth), kDeepBlock, 0);
-            if (e != hipSuccess) return e;
-            per_cu = b < per_cu ? b : per_cu;
-        }
+        for (uint32_t nt = 0; nt < 2; ++nt)
+            for (uint32_t rule : {0u, kSwimGreedy}) {
+                int b = 0;
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, pick_deep(nt, depth, rule),
+                                                                 kDeepBlock, 0);
+                if (e != hipSuccess) return e;
+                per_cu = b < per_cu ? b : per_cu;
+            }
     uint64_t g = (uint64_t)cus * (uint64_t)(per_cu > 0 ? per_cu : 0);
     if (g > kMaxBarrierBlocks) g = kMaxBarrierBlocks;
     *out_grid = (uint32_t)g;
@@ -1382,7 +1391,7 @@ hipError_t launch_fused(const SchoolArgs& a, const FusedArgs& f, uint32_t grid,
     FusedArgs fa = f;
     void* args[] = {&sa, &fa};
     const void* fn = f.regs   ? pick_regs(f.naive, f.regs)
-                     : f.deep ? pick_deep(f.streaming, f.deep)
+                     : f.deep ? pick_deep(f.streaming, f.deep, a.rule)
                               : pick_fused(f.naive, f.streaming, f.lean);
     const uint32_t block = f.regs ? kRegsBlock : f.deep ? kDeepBlock : kFusedBlock;
     return launch_persistent(fn, dim3(grid), dim3(block), args, stream);

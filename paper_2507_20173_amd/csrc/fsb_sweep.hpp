@@ -111,6 +111,31 @@ struct LaneSums {
     }
 };
 
+// The deep kernels' lane sums: each float4 group's four terms are added
+// pairwise in binary32 exactly as in the compensated LaneSums (error at most
+// gamma_2 times the group's |terms|), and the group totals are accumulated in
+// binary64, whose rounding (2^-53 relative per add) is far below that of the
+// group totals themselves: as accurate as the TwoSum accumulator, in two
+// instructions per sum instead of seven, in the same two registers.  The
+// wave and block merges that follow stay in binary64.
+struct LaneSumsF64 {
+    double v[3] = {0.0, 0.0, 0.0};
+    __device__ __forceinline__ void add(float w, float x, float y) {
+        const float wx = w * x;
+        const float wy = w * y;
+        v[0] += (double)w;
+        v[1] += (double)wx;
+        v[2] += (double)wy;
+    }
+    __device__ __forceinline__ void add4(float4 w, float4 x, float4 y) {
+        const float wx0 = w.x * x.x, wx1 = w.y * x.y, wx2 = w.z * x.z, wx3 = w.w * x.w;
+        const float wy0 = w.x * y.x, wy1 = w.y * y.y, wy2 = w.z * y.z, wy3 = w.w * y.w;
+        v[0] += (double)((w.x + w.y) + (w.z + w.w));
+        v[1] += (double)((wx0 + wx1) + (wx2 + wx3));
+        v[2] += (double)((wy0 + wy1) + (wy2 + wy3));
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Grid barrier of the persistent kernels, which also reduces a max.
 //
