@@ -26,10 +26,6 @@
 
 namespace fsb {
 
-__device__ __forceinline__ uint32_t uniform(uint32_t v) {
-    return __builtin_amdgcn_readfirstlane(v);
-}
-
 // ---------------------------------------------------------------------------
 // Tile schedule of one sweep, for one wavefront (all of its lanes call these
 // together; every value here is uniform across the wavefront).

@@ -852,7 +852,7 @@ __global__ __launch_bounds__(kDeepBlock) void fused_deep_kernel(SchoolArgs a, Fu
         uint32_t M_bits[KD];
 #pragma unroll
         for (int j = 0; j < KD; ++j) {
-            M_bits[j] = M_sh[j];
+            M_bits[j] = uniform(M_sh[j]);
             M[j] = __uint_as_float(M_bits[j]);
         }
         // Records of the previous superstep, each by a rotating block.

@@ -111,6 +111,13 @@ struct LaneSums {
     }
 };
 
+// A value the caller knows to be the same in every lane, moved to a scalar
+// register: the compiler cannot prove that of a value read from memory, and
+// would otherwise hold one copy per lane in vector registers.
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
 // The deep kernels' lane sums: each float4 group's four terms are added
 // pairwise in binary32 exactly as in the compensated LaneSums (error at most
 // gamma_2 times the group's |terms|), and the group totals are accumulated in
