@@ -124,7 +124,17 @@ def run_form(n: int, steps: int, mode: int, warmup: int = 2, swim_rule: int = 0)
 REGS_MAX_FISH = 4 * 4 * 512 * 256 + 3
 
 
-DEEP_DEPTH = 8  # iterations per grid barrier of the deep kernel
+DEEP_WIDE_FISH = 1 << 23  # above this the single-school deep kernel runs four iterations per barrier
+BATCH_DEEP_DEPTH = 8  # iterations per grid barrier of the batched deep kernel
+
+
+def deep_depth(n: int) -> int:
+    """Iterations per grid barrier of the single-school deep kernel for a
+    school of n fish, as the library picks them (include/fsb.h)."""
+    forced = os.environ.get("FSB_DEEP_DEPTH", "")
+    if forced in ("2", "4", "8"):
+        return int(forced)
+    return 4 if n > DEEP_WIDE_FISH else 8
 
 
 def fused_variant(n: int, deep_ok: bool = True) -> str:
@@ -144,7 +154,7 @@ def persistent_bytes(variant: str, n: int, steps: int) -> int:
     if variant == "regs":  # x, y, w read once, all five columns written once
         return n * (12 + 20)
     if variant == "deep":  # prologue reads x, y; 24 B per superstep; the last adds prev, cur
-        return n * (8 + 24 * -(-steps // DEEP_DEPTH) + 8)
+        return n * (8 + 24 * -(-steps // deep_depth(n)) + 8)
     if variant == "lean":  # prologue reads x, y; sweeps 24 B; the last also writes prev, cur
         return n * (8 + 24 * steps + 8)
     return n * (20 + 32 * (steps - 1) + 24)  # prologue 20 B, sweeps 32 B, last sweep 24 B
@@ -168,9 +178,9 @@ def batch_bytes(variant: str, fish: int, steps: int, per_launch: int, launches: 
     `per_launch` (the last one shorter if it does not divide)."""
     if variant == "lean":  # prologue reads x, y; 24 B per iteration; the last sweep writes prev, cur
         return fish * (16 * launches + 24 * steps)
-    if variant == "deep":  # the same per launch; 24 B per superstep of DEEP_DEPTH iterations
+    if variant == "deep":  # the same per launch; 24 B per superstep of BATCH_DEEP_DEPTH iterations
         full, rest = divmod(steps, per_launch)
-        supersteps = full * -(-per_launch // DEEP_DEPTH) + -(-rest // DEEP_DEPTH)
+        supersteps = full * -(-per_launch // BATCH_DEEP_DEPTH) + -(-rest // BATCH_DEEP_DEPTH)
         return fish * (16 * launches + 24 * supersteps)
     return fish * (44 * launches + 32 * (steps - launches))  # prologue 20 B, last sweep 24 B
 
@@ -197,13 +207,16 @@ def fused_vs_plain(n: int, steps: int, label: str):
             key, fused_variant(n))
         kernel_s = ms[fsb.FSB_KERNEL_FUSED] / 1e3
         nbytes = persistent_bytes(variant, n, steps)
-        per_step = {"lean": 24, "prev": 32, "regs": 32 / steps, "deep": 24 / DEEP_DEPTH}[variant]
+        per_step = {"lean": 24, "prev": 32, "regs": 32 / steps, "deep": 24 / deep_depth(n)}[variant]
+        barriers_per_step = 1.0 / deep_depth(n) if variant == "deep" else 1.0
         out[key] = {"variant": variant, "value": n * steps / wall, "ms_per_step": wall / steps * 1e3,
                     "launches": int(counts[fsb.FSB_KERNEL_FUSED]),
                     "algorithmic_bytes_per_fish_step": per_step,
                     "kernel_achieved_GBs": nbytes / kernel_s / 1e9,
                     "kernel_hbm_frac": nbytes / kernel_s / 1e9 / HBM_PEAK_GBS,
-                    "barrier_share": us * 1e-3 / (wall / steps * 1e3)}
+                    "barrier_share": us * barriers_per_step * 1e-3 / (wall / steps * 1e3)}
+        if variant == "deep":
+            out[key]["iterations_per_barrier"] = deep_depth(n)
         if key == "fused" and steps >= 4:
             # per-iteration cost as the slope between a launch of steps/2 and one
             # of steps iterations (the launch and its prologue drop out)
@@ -473,7 +486,7 @@ def batched_form(n_schools: int, steps: int, probe_steps: int, baseline_schools:
         "tuning": fsb.tuning_dict(tune), "autotune_probe_steps": probe_steps,
         "value": value, "ms_per_step": wall / steps * 1e3, "launches": int(launches),
         "variant": variant,
-        "algorithmic_bytes_per_fish_step": {"lean": 24, "prev": 32, "deep": 24 / DEEP_DEPTH}[variant],
+        "algorithmic_bytes_per_fish_step": {"lean": 24, "prev": 32, "deep": 24 / BATCH_DEEP_DEPTH}[variant],
         "kernel_achieved_GBs": bytes_total / (ms / 1e3) / 1e9,
         "kernel_hbm_frac": bytes_total / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
         "baseline_per_school_plain": {"schools": baseline_schools, "fish": base_fish,

@@ -108,8 +108,11 @@ extern "C" {
                                  differences of the next iterations are formed before
                                  their maxima are known; each swim is computed twice,
                                  24 B per fish per barrier.  8 iterations per barrier
-                                 (the environment variable FSB_DEEP_DEPTH, read once,
-                                 may say 2 or 4): 3 B per fish-iteration.
+                                 (3 B per fish-iteration) for schools of up to 2^23
+                                 fish, 4 above (6 B per fish-iteration, in blocks that
+                                 keep three waves per SIMD: faster there on MI355X);
+                                 the environment variable FSB_DEEP_DEPTH, read once,
+                                 may force 2, 4 or 8.
                                  FSB_ERR_UNSUPPORTED under the weighted swim rule or a
                                  reduce_mode other than FSB_REDUCE_COMPENSATED */
 
@@ -227,7 +230,8 @@ int fsb_step(fsb_school *h);
 
 /* n_steps iterations.  FSB_RUN_PLAIN issues fsb_step n_steps times;
  * the FSB_RUN_FUSED* modes run them in one persistent launch with a grid
- * barrier per iteration (per 8 iterations for FSB_RUN_FUSED_DEEP).  All give bit-identical columns and maxima (the sums agree to
+ * barrier per iteration (per 4 or 8 iterations for FSB_RUN_FUSED_DEEP).  All give
+ * bit-identical columns and maxima (the sums agree to
  * rounding; each mode is deterministic).  Asynchronous; FSB_ERR_UNSUPPORTED
  * if the fused grid cannot be co-resident, for FSB_RUN_FUSED_REGS on a
  * school too large for it, or for a fused mode under FSB_REDUCE_CRITICAL_F32. */

@@ -34,7 +34,7 @@ struct fsb_school {
     uint64_t launches[FSB_KERNEL_KINDS];
     uint32_t resident[2];  // co-resident grid of the persistent kernel (per reduce mode; 0 = unknown)
     uint32_t resident_regs[2];  // the same for the register-resident kernel
-    uint32_t resident_deep;     // the same for the deep kernel (compensated sums only)
+    uint32_t resident_deep[3];  // the same for the deep kernel of depth 2, 4, 8 (compensated sums only)
     Timer timers[FSB_KERNEL_KINDS];
 };
 
@@ -185,7 +185,7 @@ int run_fused(fsb_school* h, uint64_t n_steps, uint32_t mode) {
     // FSB_RUN_FUSED takes the deep kernel whenever it can run (compensated sums,
     // no weighted rule): measured on MI355X it is the fastest persistent form at
     // every size from 2^10 to 2^26 fish (3.9 us per iteration at 2^16 against
-    // 5.6 for registers; 261 us at 2^26 against 334 for lean).  Otherwise the
+    // 5.6 for registers; 205 us at 2^26 against 332 for lean).  Otherwise the
     // register-resident kernel for a school it holds (1.4-1.6x faster than the
     // streaming variants from 2^12 to 2^21 fish), else lean or store-prev.
     const bool deep_ok = !naive && !(h->cfg.swim_rule & FSB_SWIM_WEIGHTED);
@@ -206,12 +206,12 @@ int run_fused(fsb_school* h, uint64_t n_steps, uint32_t mode) {
             return fail(FSB_ERR_UNSUPPORTED,
                         "the deep kernel needs compensated sums and positions that do not depend "
                         "on weights (no weighted swim rule)");
-        depth = deep_depth();
-        if (h->resident_deep == 0)
-            FSB_HIP_TRY(deep_resident_grid(&h->resident_deep), "occupancy query");
-        if (h->resident_deep == 0)
+        depth = deep_depth(h->cfg.n_fish);
+        uint32_t& resident = h->resident_deep[depth == 2 ? 0 : depth == 4 ? 1 : 2];
+        if (resident == 0) FSB_HIP_TRY(deep_resident_grid(depth, &resident), "occupancy query");
+        if (resident == 0)
             return fail(FSB_ERR_UNSUPPORTED, "the deep kernel cannot be resident on this device");
-        grid = deep_grid(h->cfg.n_fish, h->resident_deep);
+        grid = deep_grid(h->cfg.n_fish, depth, resident);
     }
     int rc = finish_pending(h);
     if (rc) return rc;

@@ -134,13 +134,20 @@ hipError_t launch_combine(const SchoolArgs& a, uint32_t t, uint32_t grid, uint32
 hipError_t fused_resident_grid(uint32_t naive, uint32_t* out_grid);
 // Grid the persistent kernel uses for n fish given the resident maximum.
 uint32_t fused_grid(uint64_t n, uint32_t resident);
-// Iterations per grid barrier of the deep kernel: kDeepDepth unless the
-// environment variable FSB_DEEP_DEPTH (read once) says 2, 4 or 8.
-constexpr uint32_t kDeepDepth = 8;
-uint32_t deep_depth();
-// Largest co-resident grid of the deep kernels, and the grid for n fish.
-hipError_t deep_resident_grid(uint32_t* out_grid);
-uint32_t deep_grid(uint64_t n, uint32_t resident);
+// Iterations per grid barrier of the deep kernel for a school of n fish:
+// eight up to kDeepWideFish fish, four above, unless the environment variable
+// FSB_DEEP_DEPTH (read once) says 2, 4 or 8.  Eight unrolled iterations need
+// ~230 registers per lane, so that instance runs 512-thread blocks (two waves
+// per SIMD); four need ~150, so those instances run 768-thread blocks, three
+// waves per SIMD, which hide more latency but barrier twice as often: the
+// faster choice above ~2^23 fish, measured on MI355X.
+constexpr uint64_t kDeepWideFish = 1ull << 23;
+uint32_t deep_depth(uint64_t n);
+// Threads per block of the deep kernel of a depth.
+inline uint32_t deep_block(uint32_t depth) { return depth == 8 ? 512u : 768u; }
+// Largest co-resident grid of the deep kernels of a depth, and the grid for n fish.
+hipError_t deep_resident_grid(uint32_t depth, uint32_t* out_grid);
+uint32_t deep_grid(uint64_t n, uint32_t depth, uint32_t resident);
 // Largest co-resident grid of the register-resident kernels (0 if they cannot run).
 hipError_t regs_resident_grid(uint32_t naive, uint32_t* out_grid);
 // Launch plan of the register-resident kernel for n fish: its grid, and in

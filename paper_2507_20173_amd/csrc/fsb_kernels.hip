@@ -770,16 +770,18 @@ __global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, F
 // plain path's, in the same order, so the bits are the same.  Compensated
 // sums only; the host never picks it under the weighted rule.  The rule is a
 // template argument (kRule: 0 or kSwimGreedy), so the plain swim carries no
-// run-time tests or selects of the other rules.  Blocks of 512 threads (two
-// waves per SIMD, 256 registers each): the KD unrolled swims and KD sets of
-// lane sums spill at 128.
+// run-time tests or selects of the other rules.  Blocks of 512 threads for
+// KD = 8 (two waves per SIMD, 256 registers each: the eight unrolled swims and
+// eight sets of lane sums take ~230) and of 768 threads for KD <= 4 (three
+// waves per SIMD, at most 168 registers: four take ~150).
 // ---------------------------------------------------------------------------
-constexpr int kDeepBlock = 512;
+template <int KD>
+constexpr int kDeepBlockOf = KD == 8 ? 512 : 768;
 
 template <int KD, bool kNT, uint32_t kRule>
-__global__ __launch_bounds__(kDeepBlock) void fused_deep_kernel(SchoolArgs a, FusedArgs f) {
+__global__ __launch_bounds__(kDeepBlockOf<KD>) void fused_deep_kernel(SchoolArgs a, FusedArgs f) {
     static_assert((kRule & kSwimWeighted) == 0, "the deep kernel never runs the weighted rule");
-    constexpr int B = kDeepBlock;
+    constexpr int B = kDeepBlockOf<KD>;
     __shared__ uint32_t M_sh[KD];
     const float H = a.H, wmin = a.wmin, wmax = a.wmax;
     const SwimRule rule{kRule, a.wmin};
@@ -1224,42 +1226,43 @@ const void* pick_deep(uint32_t streaming, uint32_t depth, uint32_t rule) {
     return streaming ? deep_fn<true, 0u>(depth) : deep_fn<false, 0u>(depth);
 }
 
-hipError_t deep_resident_grid(uint32_t* out_grid) {
+hipError_t deep_resident_grid(uint32_t depth, uint32_t* out_grid) {
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     int per_cu = 1 << 30;
-    for (uint32_t depth : {2u, 4u, 8u})  // every instance must fit
-        for (uint32_t nt = 0; nt < 2; ++nt)
-            for (uint32_t rule : {0u, kSwimGreedy}) {
-                int b = 0;
-                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, pick_deep(nt, depth, rule),
-                                                                 kDeepBlock, 0);
-                if (e != hipSuccess) return e;
-                per_cu = b < per_cu ? b : per_cu;
-            }
+    for (uint32_t nt = 0; nt < 2; ++nt)  // both cache policies and both rules must fit
+        for (uint32_t rule : {0u, kSwimGreedy}) {
+            int b = 0;
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, pick_deep(nt, depth, rule),
+                                                             (int)deep_block(depth), 0);
+            if (e != hipSuccess) return e;
+            per_cu = b < per_cu ? b : per_cu;
+        }
     uint64_t g = (uint64_t)cus * (uint64_t)(per_cu > 0 ? per_cu : 0);
     if (g > kMaxBarrierBlocks) g = kMaxBarrierBlocks;
     *out_grid = (uint32_t)g;
     return hipSuccess;
 }
 
-uint32_t deep_grid(uint64_t n, uint32_t resident) {
-    uint64_t g = ((n >> 2) + kDeepBlock - 1) / kDeepBlock;
+uint32_t deep_grid(uint64_t n, uint32_t depth, uint32_t resident) {
+    const uint64_t block = deep_block(depth);
+    uint64_t g = ((n >> 2) + block - 1) / block;
     if (g < 1) g = 1;
     if (g > resident) g = resident;
     return (uint32_t)g;
 }
 
-uint32_t deep_depth() {
-    static const uint32_t depth = [] {
+uint32_t deep_depth(uint64_t n) {
+    static const uint32_t forced = [] {
         const char* v = std::getenv("FSB_DEEP_DEPTH");
-        const unsigned long d = v && *v ? std::strtoul(v, nullptr, 10) : kDeepDepth;
-        return d == 2 || d == 4 || d == 8 ? (uint32_t)d : kDeepDepth;
+        const unsigned long d = v && *v ? std::strtoul(v, nullptr, 10) : 0;
+        return d == 2 || d == 4 || d == 8 ? (uint32_t)d : 0u;
     }();
-    return depth;
+    if (forced) return forced;
+    return n > kDeepWideFish ? 4u : 8u;
 }
 
 template <bool kNaive>
@@ -1393,7 +1396,7 @@ hipError_t launch_fused(const SchoolArgs& a, const FusedArgs& f, uint32_t grid,
     const void* fn = f.regs   ? pick_regs(f.naive, f.regs)
                      : f.deep ? pick_deep(f.streaming, f.deep, a.rule)
                               : pick_fused(f.naive, f.streaming, f.lean);
-    const uint32_t block = f.regs ? kRegsBlock : f.deep ? kDeepBlock : kFusedBlock;
+    const uint32_t block = f.regs ? kRegsBlock : f.deep ? deep_block(f.deep) : kFusedBlock;
     return launch_persistent(fn, dim3(grid), dim3(block), args, stream);
 }
 

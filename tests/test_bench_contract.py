@@ -69,6 +69,9 @@ def test_persistent_bytes_accounting():
     assert bench.persistent_bytes("regs", n, 10) == n * 32
     assert bench.persistent_bytes("deep", n, 16) == n * (8 + 24 * 2 + 8)
     assert bench.persistent_bytes("deep", n, 17) == n * (8 + 24 * 3 + 8)
+    big = (1 << 23) + 4  # above 2^23 fish the single-school deep kernel runs four per barrier
+    assert bench.persistent_bytes("deep", 1 << 23, 16) == (1 << 23) * (8 + 24 * 2 + 8)
+    assert bench.persistent_bytes("deep", big, 16) == big * (8 + 24 * 4 + 8)
     assert bench.fused_variant(1 << 26) == "deep"
     assert bench.batch_bytes("deep", n, 500, 1000, 1) == n * (16 + 24 * 63)
     assert bench.batch_bytes("deep", n, 20, 8, 3) == n * (16 * 3 + 24 * 3)
@@ -128,3 +131,18 @@ def test_json_line_contract():
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0 and cb["sample"]
     assert cb["single_thread"]["value"] > 0 and cb["host"]["usable_cpus"] >= 1
     assert d["config"]["infinity_cache"]["columns_MiB"] == 320
+
+
+def test_deep_depth_follows_the_library_rule(monkeypatch):
+    """Eight iterations per barrier up to 2^23 fish, four above, unless
+    FSB_DEEP_DEPTH says 2, 4 or 8 (anything else is ignored), as
+    include/fsb.h documents for FSB_RUN_FUSED_DEEP."""
+    monkeypatch.delenv("FSB_DEEP_DEPTH", raising=False)
+    assert bench.deep_depth(1000) == 8 and bench.deep_depth(1 << 23) == 8
+    assert bench.deep_depth((1 << 23) + 1) == 4 and bench.deep_depth(1 << 26) == 4
+    monkeypatch.setenv("FSB_DEEP_DEPTH", "2")
+    assert bench.deep_depth(1 << 26) == 2 and bench.deep_depth(1000) == 2
+    monkeypatch.setenv("FSB_DEEP_DEPTH", "3")
+    assert bench.deep_depth(1 << 26) == 4
+    header = open(os.path.join(os.path.dirname(__file__), "..", "include", "fsb.h")).read()
+    assert "2^23" in header

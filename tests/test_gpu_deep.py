@@ -117,6 +117,68 @@ def test_deep_cfg4_full_size_prefix(torch_cuda, O):
               "deep cfg4 prefix")
 
 
+def test_deep_wide_school_several_supersteps(torch_cuda, O):
+    """Above 2^23 fish the library runs four iterations per barrier in
+    768-thread blocks: supersteps of 4, 4 and 1, then interleaved with plain."""
+    n = (1 << 23) + 5
+    announce(f"wide n={n}")
+    cfg = fsb.FsbConfig(n_fish=n, seed=77, history_len=13)
+    check_run(O, cfg, [(9, DEEP), (1, fsb.FSB_RUN_PLAIN), (3, DEEP)], "deep wide")
+
+
+CHILD_DEPTH = r"""
+import sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+import paper_2507_20173_amd as fsb
+out = {}
+for i, (n, steps, rule) in enumerate(CASES):
+    s = fsb.School(fsb.FsbConfig(n_fish=n, seed=400 + i, swim_step=0.5 if rule else 0.1,
+                                 swim_rule=rule, history_len=steps))
+    s.run(steps, fsb.FSB_RUN_FUSED_DEEP)
+    h = s.history(0, steps)
+    out[f"max{i}"] = h["max_delta"]
+    out[f"sums{i}"] = np.stack([h["sum_w"], h["sum_wx"], h["sum_wy"]], 1)
+    st = s.state()
+    for k in fsb.COLUMNS:
+        out[f"{k}{i}"] = st[k]
+    s.close()
+np.savez(sys.argv[2], **out)
+"""
+DEPTH_CASES = [(1, 3, 0), (7, 5, 0), (4097, 9, 0), (65539, 6, 0), ((1 << 20) + 3, 11, 0),
+               (300_007, 7, fsb.FSB_SWIM_GREEDY)]
+
+
+@pytest.mark.parametrize("depth", ["2", "4"])
+def test_forced_depth_in_a_child(torch_cuda, O, tmp_path, depth):
+    """FSB_DEEP_DEPTH (read once per process) forces two or four iterations per
+    barrier, the 768-thread instances, at sizes the library would run eight:
+    every case still equals the oracle bit for bit.  The child launches the
+    persistent kernels ordinarily (a cooperative launch from a second process
+    while this one holds the GPU is refused with hipErrorIllegalState); the
+    grid is the same co-resident one."""
+    import os
+    import subprocess
+    import sys
+    announce(f"FSB_DEEP_DEPTH={depth} in a child process")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = tmp_path / f"depth{depth}.npz"
+    env = dict(os.environ, FSB_DEEP_DEPTH=depth, FSB_PERSISTENT_LAUNCH="regular")
+    child = CHILD_DEPTH.replace("CASES", repr(DEPTH_CASES))
+    subprocess.run([sys.executable, "-c", child, root, str(out)], env=env, check=True, timeout=240)
+    got = np.load(out)
+    for i, (n, steps, rule) in enumerate(DEPTH_CASES):
+        cfg = fsb.FsbConfig(n_fish=n, seed=400 + i, swim_step=0.5 if rule else 0.1,
+                            swim_rule=rule, history_len=steps)
+        ocfg = oracle_config(cfg)
+        school = O.init(ocfg)
+        m, s, a = O.run(ocfg, school, 0, steps)
+        what = f"depth {depth} n={n} steps={steps}"
+        assert np.array_equal(got[f"max{i}"].view(np.uint32), m.view(np.uint32)), what
+        assert_sums_close(got[f"sums{i}"], s, a, what=what)
+        assert_columns_equal({k: got[f"{k}{i}"] for k in fsb.COLUMNS}, school, what)
+
+
 @pytest.mark.parametrize("cfg", [dict(swim_rule=fsb.FSB_SWIM_WEIGHTED),
                                  dict(reduce_mode=fsb.FSB_REDUCE_NAIVE_F32),
                                  dict(reduce_mode=fsb.FSB_REDUCE_CRITICAL_F32)],
