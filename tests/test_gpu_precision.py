@@ -43,3 +43,29 @@ def test_cfg3_full_size_compensated_vs_naive(torch_cuda):
           flush=True)
     assert (comp <= 1e-6).all()
     assert comp.max() < naive.max()
+
+
+@pytest.mark.parametrize("n", [1 << 23, 1 << 26], ids=["2^23-eight-deep", "2^26-four-deep"])
+def test_deep_kernel_sums_are_compensated_grade(torch_cuda, n):
+    """The deep kernel's lane sums (pairwise float4 group totals accumulated in
+    binary64, binary64 wave and block merges) keep every iteration's sums at
+    the compensated reduction's accuracy, far inside the 1e-6 gate: over
+    supersteps of the eight- and the four-deep shapes (9 iterations)."""
+    steps = 9
+    print(f"[precision] deep N={n} steps={steps}", flush=True)
+    O = default()
+    cfg = fsb.FsbConfig(n_fish=n, seed=3, history_len=steps)
+    ocfg = oracle_config(cfg)
+    school = O.init(ocfg)
+    m, s, a = O.run(ocfg, school, 0, steps)
+    sch = fsb.School(cfg)
+    sch.run(steps, fsb.FSB_RUN_FUSED)
+    h = sch.history(0, steps)
+    assert np.array_equal(h["max_delta"], m)
+    got = np.stack([h["sum_w"], h["sum_wx"], h["sum_wy"]], 1)
+    err = sum_errors(got, s, a)
+    print(f"[precision] deep N={n} max error {err.max():.3e}", flush=True)
+    assert (err <= 1e-9).all(), err
+    sch.close()
+    del sch
+    torch_cuda.cuda.empty_cache()
