@@ -34,7 +34,8 @@ def test_c_consumer_usage_error():
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("n,steps,mode", [(4099, 7, RUN_PLAIN), (65_539, 5, RUN_FUSED),
-                                          (100_003, 4, RUN_FUSED_LEAN)])
+                                          (100_003, 4, RUN_FUSED_LEAN),
+                                          ((1 << 23) + 7, 6, RUN_FUSED)])
 def test_c_consumer_matches_oracle(tmp_path, n, steps, mode):
     print(f"[c consumer] n={n} steps={steps} mode={mode}", flush=True)
     out = tmp_path / "columns.bin"
