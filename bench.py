@@ -27,8 +27,9 @@ BYTES_PER_FISH = {
     "swim_eval": 8 + 16,   # reads x, y; writes x, y, prev, cur
     "feed_bary": 16 + 4,   # reads prev, w, x, y; writes w
 }
-# Every PROFILE_EVERY-th launch of each kernel is bracketed by HIP events
-# inside the timed region (sampling keeps the event packets off the others).
+# Every PROFILE_EVERY-th launch of each kernel is timed by HIP events inside
+# the timed region (the plain passes' launches record them themselves; the
+# persistent launches are bracketed by them).
 PROFILE_EVERY = 8
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2507_20173_amd", "csrc", "fsb_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plain_n16777216.json")

@@ -341,9 +341,11 @@ int fsb_batch_destroy(fsb_batch *b);
 /* ---- instrumentation --------------------------------------------------- */
 
 /* Kernel timing: with every = n > 0, every n-th launch of each kernel kind
- * (the 1st, the (n+1)-th, ...) is bracketed by HIP events on the handle's
- * stream (n = 1 times every launch; sampling keeps the event packets' own
- * cost out of the other launches); every = 0 turns timing off.
+ * (the 1st, the (n+1)-th, ...) is timed by HIP events on the handle's
+ * stream: the plain passes' launches record a start and a stop event
+ * themselves (the kernel's own execution), the other launches are bracketed
+ * by them (n = 1 times every launch; sampling keeps the events' own cost out
+ * of the other launches); every = 0 turns timing off.
  * fsb_kernel_times synchronises and returns, per kernel kind
  * (FSB_KERNEL_*), the number of timed launches and their summed duration in
  * milliseconds since the previous read (reading resets the counts). */

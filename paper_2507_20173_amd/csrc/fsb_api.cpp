@@ -53,6 +53,18 @@ int timed(fsb_school* h, int kind, const char* what, F&& fn) {
     return FSB_OK;
 }
 
+// The same for a launch that records the events itself (the plain passes):
+// fn(start, stop) gets the kind's next pair, or two nulls when this launch is
+// not timed.
+template <class F>
+int timed_by_launch(fsb_school* h, int kind, const char* what, F&& fn) {
+    std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
+    if (h->profile_every && h->launches[kind]++ % h->profile_every == 0)
+        FSB_HIP_TRY(h->timers[kind].next(&ev), "hipEventCreate");
+    FSB_HIP_TRY(fn(ev ? ev->first : nullptr, ev ? ev->second : nullptr), what);
+    return FSB_OK;
+}
+
 SchoolArgs make_args(const fsb_config& c, const fsb_state& st, void* ws, const Layout& L) {
     SchoolArgs a{};
     char* base = static_cast<char*>(ws);
@@ -147,13 +159,17 @@ int do_step(fsb_school* h, const float* dx, const float* dy) {
     s.critical = h->cfg.reduce_mode == FSB_REDUCE_CRITICAL_F32;
     s.dx = dx;
     s.dy = dy;
-    int rc = timed(h, FSB_KERNEL_SWIM_EVAL, "swim pass launch",
-                   [&] { return launch_swim_eval(h->args, s, h->stream); });
+    int rc = timed_by_launch(h, FSB_KERNEL_SWIM_EVAL, "swim pass launch",
+                             [&](hipEvent_t e0, hipEvent_t e1) {
+                                 return launch_swim_eval(h->args, s, h->stream, e0, e1);
+                             });
     if (rc) return rc;
     h->pending = false;
     const uint32_t fgrid = feed_grid(h->cfg.n_fish);
-    rc = timed(h, FSB_KERNEL_FEED_BARY, "feed pass launch",
-               [&] { return launch_feed_bary(h->args, s, fgrid, h->stream); });
+    rc = timed_by_launch(h, FSB_KERNEL_FEED_BARY, "feed pass launch",
+                         [&](hipEvent_t e0, hipEvent_t e1) {
+                             return launch_feed_bary(h->args, s, fgrid, h->stream, e0, e1);
+                         });
     if (rc) return rc;
     h->pending = true;
     h->pending_t = (uint32_t)h->t;

@@ -125,9 +125,13 @@ uint32_t plain_grid(uint64_t n);  // swim pass (and init)
 uint32_t feed_grid(uint64_t n);   // feed pass
 hipError_t launch_reset(const SchoolArgs& a, hipStream_t stream);
 hipError_t launch_init(const SchoolArgs& a, float wlo, float whi, hipStream_t stream);
-hipError_t launch_swim_eval(const SchoolArgs& a, const StepArgs& s, hipStream_t stream);
+// The plain passes; with a start and a stop event the launch records them
+// itself, around the kernel's own execution.
+hipError_t launch_swim_eval(const SchoolArgs& a, const StepArgs& s, hipStream_t stream,
+                            hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 hipError_t launch_feed_bary(const SchoolArgs& a, const StepArgs& s, uint32_t grid,
-                            hipStream_t stream);
+                            hipStream_t stream, hipEvent_t start = nullptr,
+                            hipEvent_t stop = nullptr);
 hipError_t launch_combine(const SchoolArgs& a, uint32_t t, uint32_t grid, uint32_t naive,
                           hipStream_t stream);
 // Largest co-resident grid of the persistent kernel (0 if it cannot run).

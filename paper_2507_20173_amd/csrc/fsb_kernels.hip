@@ -32,6 +32,8 @@
 // (one float4 per column): two Philox calls, for fish pairs 2g and 2g+1.
 // The n % 4 fish past the last full group are handled one by one by the last
 // block.  A thread keeps the same fish in every sweep of a launch.
+#include <hip/hip_ext.h>
+
 #include <cstdlib>
 #include <cstring>
 
@@ -1168,28 +1170,34 @@ const void* feed_fn(int pol) {
     }
 }
 
+// With start and stop events, the launch itself records them (hipExtLaunchKernel):
+// the elapsed time is the kernel's own, with no marker packets of its own in
+// the stream to stretch it.
 hipError_t launch_plain(const void* fn, uint32_t grid, const SchoolArgs& a, const StepArgs& s,
-                        hipStream_t stream) {
+                        hipStream_t stream, hipEvent_t start, hipEvent_t stop) {
     SchoolArgs aa = a;
     StepArgs ss = s;
     void* args[] = {&aa, &ss};
+    if (start && stop)
+        return hipExtLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, stream, start, stop, 0);
     return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, stream);
 }
 
-hipError_t launch_swim_eval(const SchoolArgs& a, const StepArgs& s, hipStream_t stream) {
+hipError_t launch_swim_eval(const SchoolArgs& a, const StepArgs& s, hipStream_t stream,
+                            hipEvent_t start, hipEvent_t stop) {
     const int pol = plain_policy(a.n);
     const void* fn = s.critical ? (s.dx ? swim_fn<true, true>(pol) : swim_fn<false, true>(pol))
                                 : (s.dx ? swim_fn<true, false>(pol) : swim_fn<false, false>(pol));
-    return launch_plain(fn, s.swim_grid, a, s, stream);
+    return launch_plain(fn, s.swim_grid, a, s, stream, start, stop);
 }
 
 hipError_t launch_feed_bary(const SchoolArgs& a, const StepArgs& s, uint32_t grid,
-                            hipStream_t stream) {
+                            hipStream_t stream, hipEvent_t start, hipEvent_t stop) {
     const int pol = plain_policy(a.n);
     const void* fn = s.critical ? feed_fn<kRedCritical>(pol)
                      : s.naive  ? feed_fn<kRedNaive>(pol)
                                 : feed_fn<kRedCompensated>(pol);
-    return launch_plain(fn, grid, a, s, stream);
+    return launch_plain(fn, grid, a, s, stream, start, stop);
 }
 
 hipError_t launch_combine(const SchoolArgs& a, uint32_t t, uint32_t grid, uint32_t naive,
