@@ -448,10 +448,113 @@ def pin_swim_rules(O):
     assert a.tobytes() == b.tobytes(), "weighted rule with mobility 1 differs from the plain swim"
 
 
+# --------------------------------------------------------------------------
+# binary64 drift variant
+# --------------------------------------------------------------------------
+
+def pin_init_f64(O):
+    """The binary64 initial state rounds to the binary32 one, bit for bit.
+
+    x = H * v(a): v(a) = (k - 2^23) 2^-23 has at most 24 significant bits and
+    so has H, so the product is exact in binary64 and binary32 rounds it
+    once: float32(x_f64) is the binary32 product.  The weight lo + (hi - lo)
+    u(a) is exact in binary64; in binary32 only its last addition rounds when
+    hi - lo and (hi - lo) u are exact there (hi - lo a power of two), so the
+    two agree after rounding.  The objective is the Euclidean distance
+    (Sec. 2.1.1): within four binary64 ulps of math.hypot (the binary64
+    square root of a sum of rounded squares is within two, hypot within one).  The binary32 init
+    is itself pinned to ATen's words, so a wrong sub-stream, word or sign in
+    the binary64 init fails here."""
+    for cfg in (Config(numFish=1001, seed=987654321987),
+                Config(numFish=64, seed=3, pondHalf=1.0, initWeightLo=0.5, initWeightHi=4.5)):
+        s32 = O.init(cfg)
+        s64 = O.init_f64(cfg)
+        for k in ("x", "y", "weight"):
+            assert np.array_equal(s64[k].astype(np.float32), s32[k]), f"init_f64 {k}"
+        hyp = np.array([math.hypot(x, y) for x, y in zip(s64["x"], s64["y"])])
+        assert (np.abs(s64["currentObjective"] - hyp) <= 4 * np.spacing(hyp)).all(), (
+            "init_f64 objective is not the distance from the centre")
+        assert np.array_equal(s64["prevObjective"], s64["currentObjective"])
+
+
+def pin_step_f64_drawn(O):
+    """Drawn binary64 iterations take the documented words and stay within the
+    binary32 trajectory's rounding bound.
+
+    One iteration from the binary64 initial state moves each fish away from
+    the walls by S * v of ATen's words for counter (i >> 1, t, swim domain),
+    added in binary64 (S * v is exact there: two 24-bit factors).  Over k
+    iterations, every binary32 position differs from the binary64 one by at
+    most k (ulp32(H) / 2 + ulp32(S) / 2): each binary32 iteration rounds the
+    displacement and the addition once, clamping is 1-Lipschitz and the
+    binary64 roundings are far smaller (the initial positions already differ
+    by up to ulp32(H) / 2).  A wrong word, sign or iteration
+    index in the binary64 draw moves a fish by O(S) and fails both checks."""
+    cfg = Config(numFish=257, seed=12345)
+    s64 = O.init_f64(cfg)
+    s32 = O.init(cfg)
+    t = 0
+    before = s64.copy()
+    m, _ = O.step_f64(cfg, s64, t)
+    O.step(cfg, s32, t)
+    i = np.arange(cfg.numFish)
+    j = 2 * (i & 1)
+    w = aten_words([cfg.seed] * cfg.numFish, [t | (DOMAIN_SWIM << 32)] * cfg.numFish, i >> 1)
+    S = float(f32(cfg.swimStep))
+    dx = S * _v_from_word(w[i, j])
+    dy = S * _v_from_word(w[i, j + 1])
+    inside = (np.abs(before["x"]) < 99) & (np.abs(before["y"]) < 99)
+    assert inside.sum() > 200
+    assert np.array_equal(s64["x"][inside], (before["x"] + dx)[inside])
+    assert np.array_equal(s64["y"][inside], (before["y"] + dy)[inside])
+    assert 0 < m <= S * math.sqrt(2) * (1 + 1e-15)
+    diff = s64["prevObjective"] - s64["currentObjective"]
+    assert m == np.abs(diff).max()
+    k_max = 12
+    per = float(np.spacing(f32(cfg.pondHalf))) / 2 + float(np.spacing(f32(S))) / 2
+    for k in range(1, k_max):
+        O.step_f64(cfg, s64, k)
+        O.step(cfg, s32, k)
+        bound = ((k + 1) * per + float(np.spacing(f32(cfg.pondHalf))) / 2) * (1 + 1e-6)
+        for f in ("x", "y"):
+            d = np.abs(s32[f].astype(np.float64) - s64[f]).max()
+            assert d <= bound, f"binary64 {f} drifted {d:.3e} > {bound:.3e} after {k + 1} iterations"
+
+
+def pin_f64_invariants(O):
+    """The binary64 iteration keeps the method's invariants: positions in the
+    pond, weights within the limits, the objective is the distance (math.hypot
+    within four ulps), maxDiff is the attained max |diff|, the weight change
+    follows the sign of diff unless a limit stops it, and the sums equal
+    math.fsum of the binary64 terms."""
+    cfg = Config(numFish=999, seed=77, swimStep=1.5)
+    s = O.init_f64(cfg)
+    for t in range(5):
+        before = s.copy()
+        m, sums = O.step_f64(cfg, s, t)
+        H = cfg.pondHalf
+        assert (np.abs(s["x"]) <= H).all() and (np.abs(s["y"]) <= H).all()
+        w = s["weight"]
+        assert (w >= cfg.weightMin).all() and (w <= cfg.weightMax).all()
+        hyp = np.array([math.hypot(x, y) for x, y in zip(s["x"], s["y"])])
+        assert (np.abs(s["currentObjective"] - hyp) <= 4 * np.spacing(hyp)).all()
+        assert np.array_equal(s["prevObjective"], before["currentObjective"])
+        diff = s["prevObjective"] - s["currentObjective"]
+        assert m == np.abs(diff).max() and m > 0
+        dw = w - before["weight"]
+        at_bound = (w == cfg.weightMin) | (w == cfg.weightMax)
+        assert ((dw > 0) | at_bound)[diff > 0].all() and ((dw < 0) | at_bound)[diff < 0].all()
+        assert (np.abs(dw) <= 1 + 1e-12).all()
+        for got, terms in ((sums[0], w), (sums[1], w * s["x"]), (sums[2], w * s["y"])):
+            ref = math.fsum(terms)
+            assert abs(got - ref) <= 1e-14 * np.abs(terms).sum(), f"f64 sums {got} vs {ref}"
+
+
 ALL_PINS = (pin_philox_matches_aten, pin_fish_word_layout, pin_unit_map_exhaustive,
             pin_philox_statistics, pin_worked_examples, pin_zero_swim,
             pin_uniform_weights_mean, pin_symmetric_school_exact, pin_init_stream,
-            pin_swim_stream, pin_invariants, pin_exact_sums, pin_composition, pin_swim_rules)
+            pin_swim_stream, pin_invariants, pin_exact_sums, pin_composition, pin_swim_rules,
+            pin_init_f64, pin_step_f64_drawn, pin_f64_invariants)
 
 
 def run_all(O) -> list[str]:

@@ -64,6 +64,28 @@ MUTANTS = [
      "oracle_fish_words(cfg->seed, i, 0u, ORACLE_DOMAIN_INIT, &a, &b);\n        f->weight = lo + (hi - lo) * oracle_unit(a);"),
     ("init_prev_zero", "        f->prevObjective = f->currentObjective;\n    }\n}\n\n/* Move",
      "        f->prevObjective = 0.0f;\n    }\n}\n\n/* Move"),
+    # the binary64 drift variant
+    ("init_f64_sign", "f->x = H * (2.0 * unit_f64(a) - 1.0);", "f->x = H * (1.0 - 2.0 * unit_f64(a));"),
+    ("init_f64_same_word", "f->y = H * (2.0 * unit_f64(b) - 1.0);", "f->y = H * (2.0 * unit_f64(a) - 1.0);"),
+    ("init_f64_weight_word", "f->weight = lo + (hi - lo) * unit_f64(a);",
+     "f->weight = lo + (hi - lo) * unit_f64(b);"),
+    ("init_f64_weight_substream",
+     "oracle_fish_words(cfg->seed, i, 1u, ORACLE_DOMAIN_INIT, &a, &b);\n        f->weight = lo + (hi - lo) * unit_f64(a);",
+     "oracle_fish_words(cfg->seed, i, 0u, ORACLE_DOMAIN_INIT, &a, &b);\n        f->weight = lo + (hi - lo) * unit_f64(a);"),
+    ("init_f64_objective_term", "f->currentObjective = sqrt(f->x * f->x + f->y * f->y);",
+     "f->currentObjective = sqrt(f->x * f->x + f->y * f->x);"),
+    ("step_f64_off_by_one", "(uint32_t)t, ORACLE_DOMAIN_SWIM, &a, &b);\n        swim_fish_f64",
+     "(uint32_t)(t + 1), ORACLE_DOMAIN_SWIM, &a, &b);\n        swim_fish_f64"),
+    ("step_f64_words_swapped", "S * (2.0 * unit_f64(a) - 1.0),\n                      S * (2.0 * unit_f64(b) - 1.0));",
+     "S * (2.0 * unit_f64(b) - 1.0),\n                      S * (2.0 * unit_f64(a) - 1.0));"),
+    ("step_f64_sign", "S * (2.0 * unit_f64(a) - 1.0),\n", "S * (1.0 - 2.0 * unit_f64(a)),\n"),
+    ("step_f64_no_clamp", "double x = clampd(f->x + dx, -H, H);", "double x = f->x + dx;"),
+    ("f64_signed_max", "double mag = fabs(school[i].prevObjective - school[i].currentObjective);",
+     "double mag = school[i].prevObjective - school[i].currentObjective;"),
+    ("f64_feed_sign", "double diff = f->prevObjective - f->currentObjective;\n            f->weight = clampd",
+     "double diff = f->currentObjective - f->prevObjective;\n            f->weight = clampd"),
+    ("f64_sums_drop_weight", "neumaier_add(&sx, school[i].weight * school[i].x);",
+     "neumaier_add(&sx, school[i].x);"),
 ]
 
 
