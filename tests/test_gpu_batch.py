@@ -222,7 +222,7 @@ def test_cfg5_full_shape(torch_cuda, O):
     assert (mx > 0).all() and (mx <= 0.1 * np.sqrt(2) + 1e-4).all()
     assert (sums[:, 0] >= sizes * 1.0 * (1 - 1e-9)).all() and (sums[:, 0] <= sizes * 4.0).all()
     order = np.argsort(sizes)
-    picked = list(order[:6]) + list(order[2048:2050])
+    picked = list(order[:6]) + list(order[2048:2050]) + [order[-1]]  # and the largest school
     check_batch_against_oracle(O, b, steps, schools=picked, what="cfg5")
     b.close()
 

@@ -153,8 +153,42 @@ def test_deep_cfg5_full_shape(torch_cuda, O):
     _, sums, mx = b.results()
     assert (mx > 0).all() and (mx <= 0.1 * np.sqrt(2) + 1e-4).all()
     order = np.argsort(sizes)
-    check_against_oracle(O, b, steps, common, schools=list(order[:4]) + list(order[2048:2050]),
+    check_against_oracle(O, b, steps, common,
+                         schools=list(order[:4]) + list(order[2048:2050]) + [order[-1]],
                          what="cfg5 deep")
+    b.close()
+
+
+def test_deep_batch_long_run_rings_wrap(torch_cuda, O):
+    """The batched form as the benchmark runs it (the tuning the autotuner
+    picks for the 4096-school batch: 256 threads, 16 fish per lane, dynamic
+    chunks of 4 tiles, launches of up to 1000 iterations), for 500 iterations
+    in one graph launch on 64 schools, one of them 10^6 fish: the per-school
+    max ring (slot t mod 24) and the tile-partial ring (slot t mod 16) wrap
+    many times.  Every school's every record and final columns against the
+    oracle's run of that school alone."""
+    steps = 500
+    sizes = np.concatenate([[1_000_000], log_uniform_school_sizes(63, lo=1_000, hi=10_000,
+                                                                  meta_seed=5)]).astype(np.uint64)
+    seeds = school_seeds(64, base=9000)
+    announce(f"long run: 64 schools, {int(sizes.sum())} fish, {steps} iterations, one launch")
+    common = fsb.FsbConfig(n_fish=0, history_len=steps)
+    b = fsb.Batch(common, sizes, seeds)
+    b.run(steps, fsb.tuning(256, 16, 1000, variant=DEEP, schedule=fsb.FSB_SCHED_DYNAMIC,
+                            chunk_tiles=4))
+    hist = [b.history(t) for t in range(steps)]
+    for i in range(b.n):
+        cfg = fsb.FsbConfig(n_fish=int(sizes[i]), seed=int(seeds[i]))
+        ocfg = oracle_config(cfg)
+        school = O.init(ocfg)
+        m, s, a = O.run(ocfg, school, 0, steps)
+        rec = np.array([h[i] for h in hist])
+        what = f"long run school {i} ({int(sizes[i])} fish)"
+        assert np.array_equal(rec["step_lo"], np.arange(steps)), what
+        assert np.array_equal(rec["max_delta"].view(np.uint32), m.view(np.uint32)), what
+        assert_sums_close(np.stack([rec["sum_w"], rec["sum_wx"], rec["sum_wy"]], 1), s, a,
+                          what=what)
+        assert_columns_equal(b.school_state(i), school, what)
     b.close()
 
 

@@ -110,11 +110,25 @@ def test_deep_is_deterministic(torch_cuda):
 
 
 def test_deep_cfg4_full_size_prefix(torch_cuda, O):
-    """N = 2^26, 5 iterations (one full superstep and a short one)."""
-    n, steps = 1 << 26, 5
+    """N = 2^26 (the persistent benchmark's school) through FSB_RUN_FUSED, 21
+    iterations in one launch: five full supersteps of four and a short one,
+    so the partials' ring (slot t mod 16) wraps."""
+    n, steps = 1 << 26, 21
     announce(f"cfg4 N={n} prefix {steps}")
-    check_run(O, fsb.FsbConfig(n_fish=n, seed=0, history_len=steps), [(steps, DEEP)],
+    check_run(O, fsb.FsbConfig(n_fish=n, seed=0, history_len=steps), [(steps, fsb.FSB_RUN_FUSED)],
               "deep cfg4 prefix")
+
+
+@pytest.mark.parametrize("n,steps", [((1 << 23) + 5, 41), (10_007, 2000), ((1 << 21) + 1, 100)])
+def test_deep_long_launch_ring_wraps(torch_cuda, O, n, steps):
+    """One FSB_RUN_FUSED launch of many iterations, every record and the final
+    columns against the oracle: above 2^23 fish four iterations per barrier
+    in 768-thread blocks (41 iterations: the slot-t-mod-16 partials ring wraps
+    twice), below eight per barrier (2000 iterations on 10^4 fish, as in the
+    benchmark's launch length)."""
+    announce(f"long launch n={n} steps={steps}")
+    check_run(O, fsb.FsbConfig(n_fish=n, seed=2024 + steps, history_len=steps),
+              [(steps, fsb.FSB_RUN_FUSED)], f"long launch n={n}")
 
 
 def test_deep_wide_school_several_supersteps(torch_cuda, O):
@@ -146,7 +160,7 @@ for i, (n, steps, rule) in enumerate(CASES):
 np.savez(sys.argv[2], **out)
 """
 DEPTH_CASES = [(1, 3, 0), (7, 5, 0), (4097, 9, 0), (65539, 6, 0), ((1 << 20) + 3, 11, 0),
-               (300_007, 7, fsb.FSB_SWIM_GREEDY)]
+               (300_007, 7, fsb.FSB_SWIM_GREEDY), (10_007, 2000, 0)]
 
 
 @pytest.mark.parametrize("depth", ["2", "4"])

@@ -19,18 +19,31 @@ def torch_cuda():
 
 
 def test_cfg3_full_size_compensated_vs_naive(torch_cuda):
-    n, steps = 1 << 27, 2
+    """N = 2^27, 20 iterations: every iteration's three sums against the
+    oracle's binary64 (Neumaier) sums of that iteration, for the compensated
+    reduction and the naive float32-atomic baseline.  The compensated sums
+    stay within the 1e-6 gate at every iteration; the baseline's errors are
+    reported beside them (they stay below the gate too, but orders of
+    magnitude above the compensated ones)."""
+    n, steps = 1 << 27, 20
     print(f"[precision] N={n} steps={steps}", flush=True)
     O = default()
     ocfg = oracle_config(fsb.FsbConfig(n_fish=n, seed=0))
     school = O.init(ocfg)
-    m, s, a = O.run(ocfg, school, 0, steps)
+    ms, ss, as_ = [], [], []
+    for t in range(steps):
+        m, s, a = O.step(ocfg, school, t)
+        ms.append(m)
+        ss.append(s)
+        as_.append(a)
+        print(f"[precision] oracle iteration {t} done", flush=True)
+    m, s, a = np.array(ms, np.float32), np.array(ss), np.array(as_)
     errs = {}
     for mode in (fsb.FSB_REDUCE_COMPENSATED, fsb.FSB_REDUCE_NAIVE_F32):
         sch = fsb.School(fsb.FsbConfig(n_fish=n, seed=0, reduce_mode=mode, history_len=steps))
         sch.run(steps)
         h = sch.history(0, steps)
-        assert np.array_equal(h["max_delta"], m)
+        assert np.array_equal(h["max_delta"].view(np.uint32), m.view(np.uint32))
         got = np.stack([h["sum_w"], h["sum_wx"], h["sum_wy"]], 1)
         errs[mode] = sum_errors(got, s, a)
         if mode == fsb.FSB_REDUCE_COMPENSATED:
@@ -39,9 +52,10 @@ def test_cfg3_full_size_compensated_vs_naive(torch_cuda):
         del sch
         torch_cuda.cuda.empty_cache()
     comp, naive = errs[fsb.FSB_REDUCE_COMPENSATED], errs[fsb.FSB_REDUCE_NAIVE_F32]
-    print(f"[precision] compensated max error {comp.max():.3e}, naive {naive.max():.3e}",
-          flush=True)
-    assert (comp <= 1e-6).all()
+    for t in range(steps):
+        print(f"[precision] iteration {t}: compensated {comp[t].max():.3e}, "
+              f"naive {naive[t].max():.3e}", flush=True)
+    assert (comp <= 1e-6).all(), comp
     assert comp.max() < naive.max()
 
 
