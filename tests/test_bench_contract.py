@@ -131,6 +131,20 @@ def test_json_line_contract():
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0 and cb["sample"]
     assert cb["single_thread"]["value"] > 0 and cb["host"]["usable_cpus"] >= 1
     assert d["config"]["infinity_cache"]["columns_MiB"] == 320
+    assert "20 iterations" in d["config"]["workload"]
+    assert rl["cache_assisted"] is True
+    hr = d["roofline_hbm_resident"]
+    assert hr["n_fish"] == 1 << 26 and not hr["infinity_cache"]["live_columns_fit"]
+    assert 0 < hr["swim_frac"] < 1 and 0 < hr["feed_frac"] < 1
+    dr = cb["drift_f64"]
+    assert dr["max_position_drift"] <= dr["position_bound_last_iteration"]
+
+
+def test_drift_report_stays_within_the_rounding_bound():
+    d = bench.drift_report(n=257, steps=6)
+    assert 0 < d["max_position_drift"] <= d["position_bound_last_iteration"]
+    assert d["max_weight_drift"] >= 0 and d["max_relative_M_drift"] < 1e-3
+    assert "information only" in d["note"]
 
 
 def test_deep_depth_follows_the_library_rule(monkeypatch):
