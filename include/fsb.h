@@ -228,7 +228,10 @@ int fsb_attach(const fsb_config *cfg, fsb_state state, void *workspace,
  * FSB_ERR_INVALID_ARG once t reaches 2^32 (the counter word is 32 bits). */
 int fsb_step(fsb_school *h);
 
-/* n_steps iterations.  FSB_RUN_PLAIN issues fsb_step n_steps times;
+/* n_steps iterations of the simulation loop (Sec. 2.1.3: the total
+ * iteration count is a Config parameter; each iteration swims every fish,
+ * Sec. 2.1.2, then runs eat(), Sec. 2.3.2).  FSB_RUN_PLAIN issues fsb_step
+ * n_steps times;
  * the FSB_RUN_FUSED* modes run them in one persistent launch with a grid
  * barrier per iteration (per 4 or 8 iterations for FSB_RUN_FUSED_DEEP).  All give
  * bit-identical columns and maxima (the sums agree to
@@ -244,11 +247,18 @@ int fsb_step_displaced(fsb_school *h, const float *dx, const float *dy);
 
 /* Barycentre of the last completed iteration: out_xy = (sum w*x / sum w,
  * sum w*y / sum w) in binary64; out_sums3 (nullable) = the three sums.
+ * The paper defines no barycentre: this weight-weighted centre of the
+ * school's post-feed positions is a reading added to the method, with the
+ * fish record of Sec. 2.1.1 as its terms (all weights equal: the plain mean
+ * position).
  * Synchronises the stream.  FSB_ERR_STATE before the first iteration;
  * FSB_ERR_DEVICE if a kernel reported a failure. */
 int fsb_barycentre(fsb_school *h, double out_xy[2], double *out_sums3);
 
-/* M = max |diff| of the last completed iteration.  Synchronises. */
+/* M = max |diff| of the last completed iteration: the school-wide maximum
+ * that eat() takes with the Reduction Construct (Sec. 2.3.2, Experiment 3),
+ * of diff = prevObjective - currentObjective, read as a magnitude (a signed
+ * maximum can be 0 or negative and would invert feeding).  Synchronises. */
 int fsb_max_delta(fsb_school *h, float *out_max);
 
 /* Records of iterations [first, first + count): each must still be in the
@@ -304,7 +314,9 @@ int fsb_batch_init(const fsb_config *common, uint32_t n_schools,
                    void *workspace, size_t workspace_bytes, void *stream,
                    fsb_batch **out);
 
-/* n_steps iterations of every school: persistent launches of
+/* n_steps iterations of every school (the loop of Sec. 2.1.3 and eat() of
+ * Sec. 2.3.2 run on each school independently; batching many schools is an
+ * addition of this library, not part of the paper): persistent launches of
  * steps_per_launch iterations (one grid barrier per iteration), each launch
  * a replay of a captured HIP graph.  tuning NULL keeps the handle's tuning;
  * otherwise it becomes the handle's tuning.  Per-fish state and maxima do
@@ -313,10 +325,21 @@ int fsb_batch_run(fsb_batch *b, uint64_t n_steps, const fsb_tuning *tuning);
 
 /* Results of the last completed iteration, per school: out_xy[2*n_schools]
  * barycentres (nullable), out_sums[3*n_schools] (sum w, sum w*x, sum w*y;
- * nullable), out_max[n_schools] (M; nullable).  Synchronises.
- * FSB_ERR_STATE before the first iteration. */
+ * nullable), out_max[n_schools] (M, the maximum eat() takes, Sec. 2.3.2;
+ * nullable).  The barycentre is not in the paper (see fsb_barycentre).
+ * Host arrays, caller-owned.  Synchronises.  FSB_ERR_STATE before the first
+ * iteration. */
 int fsb_batch_results(fsb_batch *b, double *out_xy, double *out_sums,
                       float *out_max);
+
+/* Barycentre of every school after the last completed iteration (the
+ * single-school fsb_barycentre, per school): out_xy[2*n_schools] = (sum w*x
+ * / sum w, sum w*y / sum w) of school s at 2s, 2s+1 (required);
+ * out_sums[3*n_schools] the three sums (nullable).  Host arrays,
+ * caller-owned.  The paper defines no barycentre: a reading added to the
+ * method.  Synchronises.  FSB_ERR_INVALID_ARG for a NULL handle or out_xy,
+ * FSB_ERR_STATE before the first iteration. */
+int fsb_batch_barycentre(fsb_batch *b, double *out_xy, double *out_sums);
 
 /* Records of iteration `step` for every school (out[n_schools]); the
  * iteration must still be in the history ring.  Synchronises. */

@@ -209,6 +209,16 @@ def fsb_batch_results(b, n_schools: int):
     return xy, sums, mx
 
 
+def fsb_batch_barycentre(b, n_schools: int) -> tuple[np.ndarray, np.ndarray]:
+    """Per-school barycentres (n_schools, 2) and sums (n_schools, 3) of the
+    last completed iteration."""
+    xy = np.zeros((n_schools, 2), np.float64)
+    sums = np.zeros((n_schools, 3), np.float64)
+    check(lib().fsb_batch_barycentre(b, xy.ctypes.data_as(_lib._DP),
+                                     sums.ctypes.data_as(_lib._DP)))
+    return xy, sums
+
+
 def fsb_batch_history(b, step: int, n_schools: int) -> np.ndarray:
     out = np.zeros(n_schools, RECORD)
     check(lib().fsb_batch_history(b, step, out.ctypes.data_as(ctypes.POINTER(_lib.fsb_record))))
@@ -371,6 +381,9 @@ class Batch:
 
     def results(self):
         return fsb_batch_results(self.h, self.n)
+
+    def barycentre(self):
+        return fsb_batch_barycentre(self.h, self.n)
 
     def history(self, step: int):
         return fsb_batch_history(self.h, step, self.n)

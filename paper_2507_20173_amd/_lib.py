@@ -106,6 +106,7 @@ PROTOTYPES = {
                             ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
     "fsb_batch_run": (_I, [_P, _U64, ctypes.POINTER(fsb_tuning)]),
     "fsb_batch_results": (_I, [_P, _DP, _DP, ctypes.POINTER(ctypes.c_float)]),
+    "fsb_batch_barycentre": (_I, [_P, _DP, _DP]),
     "fsb_batch_history": (_I, [_P, _U64, ctypes.POINTER(fsb_record)]),
     "fsb_autotune": (_I, [_P, _U64, ctypes.POINTER(fsb_tuning)]),
     "fsb_batch_get_tuning": (_I, [_P, ctypes.POINTER(fsb_tuning)]),

@@ -91,6 +91,24 @@ SchoolArgs make_args(const fsb_config& c, const fsb_state& st, void* ws, const L
     return a;
 }
 
+// A handle's fields for a school whose arguments have been checked (no
+// allocation: the handle may live on the caller's stack).
+void fill_school(fsb_school* h, const fsb_config& cfg, const fsb_state& state, void* ws,
+                 size_t ws_bytes, void* stream, const Layout& L, uint64_t t) {
+    h->cfg = cfg;
+    h->st = state;
+    h->ws = ws;
+    h->ws_bytes = ws_bytes;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->L = L;
+    h->args = make_args(cfg, state, ws, L);
+    h->t = t;
+    h->first_valid = t;
+    h->has_result = false;
+    h->pending = false;
+    h->profile_every = 0;
+}
+
 int new_school(const fsb_config* cfg, fsb_state state, void* ws, size_t ws_bytes, void* stream,
                uint64_t t, fsb_school** out) {
     int rc = check_config(cfg, true);
@@ -104,18 +122,7 @@ int new_school(const fsb_config* cfg, fsb_state state, void* ws, size_t ws_bytes
     if (t >= kStepLimit) return fail(FSB_ERR_INVALID_ARG, "iteration index must be < 2^32");
     fsb_school* h = new (std::nothrow) fsb_school();
     if (!h) return fail(FSB_ERR_INVALID_ARG, "out of host memory");
-    h->cfg = *cfg;
-    h->st = state;
-    h->ws = ws;
-    h->ws_bytes = ws_bytes;
-    h->stream = static_cast<hipStream_t>(stream);
-    h->L = L;
-    h->args = make_args(*cfg, state, ws, L);
-    h->t = t;
-    h->first_valid = t;
-    h->has_result = false;
-    h->pending = false;
-    h->profile_every = 0;
+    fill_school(h, *cfg, state, ws, ws_bytes, stream, L, t);
     hipError_t e = launch_reset(h->args, h->stream);
     if (e != hipSuccess) {
         delete h;
@@ -249,9 +256,7 @@ int run_fused(fsb_school* h, uint64_t n_steps, uint32_t mode) {
         FSB_HIP_TRY(hipEventRecord(ev->first, h->stream), "hipEventRecord");
     }
     hipError_t e = launch_fused(h->args, f, grid, h->stream);
-    if (e == hipErrorCooperativeLaunchTooLarge)
-        return fail(FSB_ERR_UNSUPPORTED, "persistent grid cannot be co-resident");
-    if (e != hipSuccess) return hip_fail(e, "persistent kernel launch");
+    if (e != hipSuccess) return persistent_launch_fail(e, "persistent kernel launch");
     if (ev) FSB_HIP_TRY(hipEventRecord(ev->second, h->stream), "hipEventRecord");
     // The deep kernel writes every record itself; the others leave the last
     // iteration's partials for a combine launch.
@@ -425,7 +430,12 @@ int fsb_set_step_index(fsb_school* h, uint64_t t) {
 
 int fsb_destroy(fsb_school* h) {
     if (!h) return fail(FSB_ERR_INVALID_ARG, "handle is NULL");
+    // The timers' events are released only once the handle's stream has
+    // drained (a timed launch may still be in flight); the handle is freed
+    // even if the stream reports an error.
+    const hipError_t e = hipStreamSynchronize(h->stream);
     delete h;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize before destroying the school");
     return FSB_OK;
 }
 
@@ -460,8 +470,7 @@ int fsb_barrier_probe(fsb_school* h, uint32_t grid, uint32_t n_barriers, double*
     if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
     if (e == hipSuccess) {
         e = launch_barrier_probe(h->args, f, grid, h->stream);
-        if (e == hipErrorCooperativeLaunchTooLarge) rc = fail(FSB_ERR_UNSUPPORTED, "probe grid cannot be co-resident");
-        else if (e != hipSuccess) rc = hip_fail(e, "barrier probe launch");
+        if (e != hipSuccess) rc = persistent_launch_fail(e, "barrier probe launch");
     } else {
         rc = hip_fail(e, "hipEvent");
     }

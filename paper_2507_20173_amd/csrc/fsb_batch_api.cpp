@@ -14,6 +14,7 @@
 #include "fsb.h"
 #include "fsb_host.hpp"
 #include "fsb_internal.hpp"
+#include "fsb_plan.hpp"
 
 using namespace fsb;
 
@@ -50,57 +51,6 @@ struct fsb_batch {
 
 namespace {
 
-uint64_t tiles_for(uint64_t fish, uint32_t fpl) {
-    const uint64_t groups = (fish + 3) / 4;
-    const uint64_t per_tile = 64ull * (fpl / 4);
-    return (groups + per_tile - 1) / per_tile;
-}
-
-bool valid_fpl(uint32_t fpl) { return fpl == 4 || fpl == 8 || fpl == 16; }
-bool valid_block(uint32_t b) { return b == 256 || b == 1024; }
-
-int check_schools(uint32_t n, const uint64_t* starts, const uint64_t* sizes, uint64_t* cap,
-                  uint64_t* total) {
-    if (n == 0 || n > (1u << 24)) return fail(FSB_ERR_INVALID_ARG, "n_schools must be in [1, 2^24]");
-    if (!starts || !sizes) return fail(FSB_ERR_INVALID_ARG, "starts/sizes are NULL");
-    uint64_t c = 0, tot = 0, end = 0;
-    for (uint32_t s = 0; s < n; ++s) {
-        if (sizes[s] == 0) return fail(FSB_ERR_INVALID_ARG, "school " + std::to_string(s) + " is empty");
-        if (sizes[s] > (1ull << 34))
-            return fail(FSB_ERR_INVALID_ARG, "school " + std::to_string(s) + " exceeds 2^34 fish");
-        if (starts[s] % 4) return fail(FSB_ERR_INVALID_ARG, "starts must be multiples of 4");
-        if (starts[s] < end)
-            return fail(FSB_ERR_INVALID_ARG, "schools must be increasing and not overlap");
-        end = starts[s] + sizes[s];
-        c += tiles_for(sizes[s], 4);
-        tot += sizes[s];
-    }
-    if (tot > kMaxFish) return fail(FSB_ERR_INVALID_ARG, "more than 2^40 fish in the batch");
-    if (c >= (1ull << 32)) return fail(FSB_ERR_INVALID_ARG, "too many tiles");
-    *cap = c;
-    *total = tot;
-    return FSB_OK;
-}
-
-int check_tuning(const fsb_tuning* t) {
-    if (!valid_block(t->block_size)) return fail(FSB_ERR_INVALID_ARG, "block_size must be 256 or 1024");
-    if (!valid_fpl(t->fish_per_thread))
-        return fail(FSB_ERR_INVALID_ARG, "fish_per_thread must be 4, 8 or 16");
-    if (t->steps_per_launch == 0) return fail(FSB_ERR_INVALID_ARG, "steps_per_launch must be >= 1");
-    if (t->variant != 0 && t->variant != FSB_RUN_FUSED_PREV && t->variant != FSB_RUN_FUSED_LEAN &&
-        t->variant != FSB_RUN_FUSED_DEEP)
-        return fail(FSB_ERR_INVALID_ARG,
-                    "variant must be 0, FSB_RUN_FUSED_PREV, FSB_RUN_FUSED_LEAN or FSB_RUN_FUSED_DEEP");
-    if (t->variant == FSB_RUN_FUSED_DEEP && t->block_size != 256)
-        return fail(FSB_ERR_INVALID_ARG, "the deep variant runs 256-thread blocks");
-    if (t->schedule != FSB_SCHED_STATIC && t->schedule != FSB_SCHED_DYNAMIC &&
-        t->schedule != FSB_SCHED_GUIDED)
-        return fail(FSB_ERR_INVALID_ARG, "schedule must be FSB_SCHED_STATIC, _DYNAMIC or _GUIDED");
-    if (t->schedule != FSB_SCHED_STATIC && t->chunk_tiles == 0)
-        return fail(FSB_ERR_INVALID_ARG, "chunk_tiles must be >= 1 for a dynamic or guided schedule");
-    return FSB_OK;
-}
-
 // The deep variant needs compensated sums and positions that do not depend on
 // weights (no weighted rule); the workspace of such a batch holds its rings.
 bool deep_capable(const fsb_config& c) {
@@ -123,25 +73,8 @@ uint32_t batch_variant(const fsb_batch* b) {
 int upload_tiles(fsb_batch* b, uint32_t fpl) {
     if (b->table_fpl == fpl) return FSB_OK;
     std::vector<Tile> tiles;
-    std::vector<uint32_t> begin(b->n + 1);
-    const uint32_t per_tile = 64u * (fpl / 4);
-    for (uint32_t s = 0; s < b->n; ++s) {
-        begin[s] = (uint32_t)tiles.size();
-        const uint64_t groups = (b->size[s] + 3) / 4;
-        for (uint64_t g0 = 0; g0 < groups; g0 += per_tile) {
-            const uint64_t fish_left = b->size[s] - 4 * g0;
-            const uint64_t cap = 4ull * per_tile;
-            Tile t{};
-            t.col4 = b->start[s] / 4 + g0;
-            t.school = s;
-            t.group0 = (uint32_t)g0;
-            t.n_fish = (uint32_t)(fish_left < cap ? fish_left : cap);
-            t.k0 = (uint32_t)b->seed[s];
-            t.k1 = (uint32_t)(b->seed[s] >> 32);
-            tiles.push_back(t);
-        }
-    }
-    begin[b->n] = (uint32_t)tiles.size();
+    std::vector<uint32_t> begin;
+    build_tile_table(b->n, b->start.data(), b->size.data(), b->seed.data(), fpl, tiles, begin);
     if (tiles.size() > b->L.tile_cap) return fail(FSB_ERR_INVALID_ARG, "tile table exceeds its capacity");
     char* base = static_cast<char*>(b->ws);
     FSB_HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
@@ -177,17 +110,7 @@ int set_schedule(fsb_batch* b, uint32_t waves) {
         b->chunk_waves == waves && b->chunk_fpl == b->table_fpl)
         return FSB_OK;
     std::vector<uint32_t> start;
-    const uint64_t n = b->n_tiles;
-    for (uint64_t p = 0; p < n;) {
-        start.push_back((uint32_t)p);
-        uint64_t len = tu.chunk_tiles;
-        if (tu.schedule == FSB_SCHED_GUIDED) {
-            const uint64_t share = (n - p + waves - 1) / waves;
-            if (share > len) len = share;
-        }
-        p = p + len < n ? p + len : n;
-    }
-    start.push_back((uint32_t)n);
+    build_chunk_starts(b->n_tiles, tu.schedule, tu.chunk_tiles, waves, start);
     if (start.size() > (size_t)b->L.tile_cap + 1)
         return fail(FSB_ERR_INVALID_ARG, "chunk table exceeds its capacity");
     char* base = static_cast<char*>(b->ws);
@@ -244,9 +167,7 @@ int launch_once(fsb_batch* b, uint32_t steps, uint32_t grid) {
     const BatchArgs a = launch_args(b, steps, grid);
     hipError_t e = launch_batch(a, b->tuning.block_size, b->tuning.fish_per_thread, naive, nt,
                                 batch_variant(b), grid, b->stream);
-    if (e == hipErrorCooperativeLaunchTooLarge)
-        return fail(FSB_ERR_UNSUPPORTED, "batched grid cannot be co-resident");
-    if (e != hipSuccess) return hip_fail(e, "batched kernel launch");
+    if (e != hipSuccess) return persistent_launch_fail(e, "batched kernel launch");
     return FSB_OK;
 }
 
@@ -389,12 +310,8 @@ bool cache_lookup(const std::string& key, fsb_tuning* out) {
     char line[512];
     bool found = false;
     while (std::fgets(line, sizeof(line), f)) {
-        char k[300];
         fsb_tuning t;
-        if (std::sscanf(line, "%299s %u %u %u %u %u %u %u", k, &t.block_size, &t.fish_per_thread,
-                        &t.steps_per_launch, &t.blocks_per_cu, &t.variant, &t.schedule,
-                        &t.chunk_tiles) == 8 &&
-            key == k && check_tuning(&t) == FSB_OK) {
+        if (parse_cache_line(line, key, &t)) {  // the last matching line wins
             *out = t;
             found = true;
         }
@@ -408,8 +325,7 @@ void cache_store(const std::string& key, const fsb_tuning& t) {
     if (!path || !*path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %u %u %u %u %u %u %u\n", key.c_str(), t.block_size, t.fish_per_thread,
-                 t.steps_per_launch, t.blocks_per_cu, t.variant, t.schedule, t.chunk_tiles);
+    std::fputs(format_cache_line(key, t).c_str(), f);
     std::fclose(f);
 }
 
@@ -569,6 +485,12 @@ int fsb_batch_results(fsb_batch* b, double* out_xy, double* out_sums, float* out
     return FSB_OK;
 }
 
+int fsb_batch_barycentre(fsb_batch* b, double* out_xy, double* out_sums) {
+    if (!b) return fail(FSB_ERR_INVALID_ARG, "handle is NULL");
+    if (!out_xy) return fail(FSB_ERR_INVALID_ARG, "out_xy is NULL");
+    return fsb_batch_results(b, out_xy, out_sums, nullptr);
+}
+
 int fsb_batch_history(fsb_batch* b, uint64_t step, fsb_record* out) {
     if (!b || !out) return fail(FSB_ERR_INVALID_ARG, "NULL argument");
     if (step >= b->t || b->t - step > b->cfg.history_len)
@@ -694,7 +616,13 @@ int fsb_batch_sync(fsb_batch* b) {
 
 int fsb_batch_destroy(fsb_batch* b) {
     if (!b) return fail(FSB_ERR_INVALID_ARG, "handle is NULL");
+    // The graph exec, the capture stream and the timer's events are released
+    // only once the handle's stream has drained: a replay still in flight
+    // reads the exec's kernel arguments, and the timer's events are still to
+    // be recorded.  The handle is freed even if the stream reports an error.
+    const hipError_t e = hipStreamSynchronize(b->stream);
     delete b;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize before destroying the batch");
     return FSB_OK;
 }
 

@@ -30,6 +30,24 @@ inline int hip_fail(hipError_t e, const char* what) {
     return FSB_ERR_HIP;
 }
 
+// A failed persistent (cooperative) launch.  Two statuses mean that the grid
+// cannot be guaranteed co-resident, which the caller can act on, rather than
+// a runtime failure: the grid is larger than the device holds at once, or
+// (hipErrorIllegalState) the runtime refuses cooperative launches while
+// another process has work on the same GPU.  Both become
+// FSB_ERR_UNSUPPORTED with a message naming the cause; the plain mode
+// (per-iteration launches) is unaffected.  Every other status is FSB_ERR_HIP.
+inline int persistent_launch_fail(hipError_t e, const char* what) {
+    if (e == hipErrorCooperativeLaunchTooLarge)
+        return fail(FSB_ERR_UNSUPPORTED,
+                    std::string(what) + ": the persistent grid cannot be co-resident on this device");
+    if (e == hipErrorIllegalState)
+        return fail(FSB_ERR_UNSUPPORTED,
+                    std::string(what) + ": the runtime refused the cooperative launch (another "
+                                        "process is using the GPU); FSB_RUN_PLAIN still works");
+    return hip_fail(e, what);
+}
+
 #define FSB_HIP_TRY(expr, what)                 \
     do {                                        \
         hipError_t e_ = (expr);                 \

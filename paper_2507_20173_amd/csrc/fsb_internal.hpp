@@ -60,10 +60,10 @@ struct Layout {
 };
 constexpr uint32_t kDeepSlots = 2 * kMaxDepth;
 
-inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-inline Layout school_layout(uint32_t history_len) {
-    Layout L;
+constexpr Layout school_layout(uint32_t history_len) {
+    Layout L{};
     L.ctrl = 0;
     L.hist = align_up(L.ctrl + sizeof(Ctrl), kAlign);
     L.blockmax = align_up(L.hist + (size_t)history_len * sizeof(fsb_record), kAlign);

@@ -23,10 +23,26 @@ def declared():
     return sorted(set(DECL.findall(text)))
 
 
+# The boundary's calls: one school (init, step, run, barycentre, max |diff|,
+# sync, step index, resume, destroy, error text) and the batch (init, run,
+# per-school barycentres, autotune, destroy).
+BOUNDARY = ("fsb_workspace_bytes", "fsb_init", "fsb_step", "fsb_run", "fsb_barycentre",
+            "fsb_max_delta", "fsb_sync", "fsb_step_index", "fsb_set_step_index", "fsb_destroy",
+            "fsb_strerror", "fsb_batch_init", "fsb_batch_run", "fsb_batch_barycentre",
+            "fsb_autotune", "fsb_batch_destroy")
+
+
 def test_header_declares_entry_points():
     names = declared()
-    for must in ("fsb_init", "fsb_step", "fsb_run", "fsb_barycentre"):
-        assert must in names
+    missing = [n for n in BOUNDARY if n not in names]
+    assert not missing, f"boundary calls not declared: {missing}"
+
+
+def test_batch_barycentre_rejects_null_arguments():
+    lib = _lib.lib()
+    xy = (ctypes.c_double * 2)()
+    assert lib.fsb_batch_barycentre(None, xy, None) == _lib.FSB_ERR_INVALID_ARG
+    assert lib.fsb_batch_barycentre(ctypes.c_void_p(8), None, None) == _lib.FSB_ERR_INVALID_ARG
 
 
 def test_library_exports_every_declared_symbol():
@@ -219,3 +235,4 @@ def test_every_reduce_mode_has_a_workspace():
                  _lib.FSB_REDUCE_CRITICAL_F32):
         rc, b = ws_bytes(cfg(reduce_mode=mode))
         assert rc == 0 and b > 0
+
