@@ -35,16 +35,21 @@ def _run(cmd):
 
 
 def build(output: str = LIBRARY, extra: list[str] | None = None) -> str:
-    """Compile every source and link the shared library (always rebuilds)."""
+    """Compile every source (in parallel) and link the shared library (always
+    rebuilds)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     build_dir = os.path.join(PKG, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    objs = []
+    jobs = []
     for src in SOURCES:
         obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        _run([HIPCC, *COMMON, *DEVICE, *(extra or []), *lang, "-c",
-              os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+        jobs.append(([HIPCC, *COMMON, *DEVICE, *(extra or []), *lang, "-c",
+                      os.path.join(CSRC, src), "-o", obj], obj))
+    with ThreadPoolExecutor(max_workers=len(jobs)) as pool:
+        list(pool.map(_run, [cmd for cmd, _ in jobs]))
+    objs = [obj for _, obj in jobs]
     tmp = output + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, output)
