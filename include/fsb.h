@@ -361,6 +361,41 @@ int fsb_batch_step_index(const fsb_batch *b, uint64_t *out_t);
 int fsb_batch_sync(fsb_batch *b);
 int fsb_batch_destroy(fsb_batch *b);
 
+/* ---- allocation-free entry point --------------------------------------- */
+
+/* For callers that cannot allocate device memory, not even a workspace ahead
+ * of time: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation.  Runs iterations t .. t + n_steps - 1 of the school held
+ * in `state` exactly as fsb_attach(cfg, state, workspace, t) followed by
+ * fsb_run(h, n_steps, mode) would (the same kernels and launch shapes, so the
+ * same bits in the columns and the records), with a scratch array inside
+ * the library in place of the workspace.  The scratch is 1 MiB of device
+ * memory per GPU, held from the first call on that GPU until the process
+ * ends; its use does not grow with n_fish, n_steps or history_len (the
+ * record ring is the caller's), so no accepted size exceeds it.
+ *   cfg      as for fsb_attach (history_len = the length of `records`).
+ *   state    the five columns at iteration t (device, caller-owned; cur must
+ *            equal sqrtf(x*x + y*y) as after any iteration), updated in place.
+ *   records  device array of cfg->history_len records (caller-owned, 8-byte
+ *            aligned): the record of iteration s goes to records[s mod
+ *            history_len].
+ *   status   device word (nullable, caller-owned): receives the kernels'
+ *            failure flags of this call, 0 if none (bit 0: a persistent
+ *            kernel's grid barrier timed out; the records are then
+ *            incomplete).
+ *   stream   a stream of the current device; everything is enqueued on it and
+ *            the call returns without waiting.
+ * Calls no hipMalloc, hipFree or other allocating routine.  Every call on a
+ * GPU uses that GPU's one scratch: calls that overlap on one GPU (concurrent
+ * streams, or host threads) race and give wrong results; serialise them.
+ * Each call clears the scratch's control words itself.  Errors: as
+ * fsb_attach and fsb_run (FSB_ERR_INVALID_ARG for NULL records, a misaligned
+ * records or status, an unknown mode or t + n_steps > 2^32; all checked
+ * before any HIP call). */
+int fsb_run_static(const fsb_config *cfg, fsb_state state, uint64_t t,
+                   uint64_t n_steps, uint32_t mode, fsb_record *records,
+                   uint32_t *status, void *stream);
+
 /* ---- instrumentation --------------------------------------------------- */
 
 /* Kernel timing: with every = n > 0, every n-th launch of each kernel kind

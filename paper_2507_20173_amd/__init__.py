@@ -147,6 +147,18 @@ def fsb_destroy(h) -> None:
     check(lib().fsb_destroy(h))
 
 
+def fsb_run_static(cfg: FsbConfig, cols: dict, t: int, n_steps: int, mode: int, records,
+                   status=None, stream=None) -> None:
+    """Iterations t .. t + n_steps - 1 of the school in ``cols`` with the
+    library's static scratch (no workspace): ``records`` is a device uint8
+    tensor of cfg.history_len records, ``status`` an optional device int32
+    word for the kernels' failure flags."""
+    assert records.numel() * records.element_size() >= cfg.history_len * RECORD.itemsize
+    c = cfg.c()
+    check(lib().fsb_run_static(ctypes.byref(c), state_struct(cols), t, n_steps, mode,
+                               _ptr(records), _ptr(status), _stream_handle(stream)))
+
+
 def fsb_profile_enable(h, every: int = 1) -> None:
     """Time every `every`-th launch of each kernel kind (0 = off)."""
     check(lib().fsb_profile_enable(h, int(every)))

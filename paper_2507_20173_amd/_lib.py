@@ -98,6 +98,8 @@ PROTOTYPES = {
     "fsb_step_index": (_I, [_P, ctypes.POINTER(_U64)]),
     "fsb_set_step_index": (_I, [_P, _U64]),
     "fsb_destroy": (_I, [_P]),
+    "fsb_run_static": (_I, [ctypes.POINTER(fsb_config), fsb_state, _U64, _U64, _U32, _P, _P,
+                            _P]),
     "fsb_profile_enable": (_I, [_P, _I]),
     "fsb_kernel_times": (_I, [_P, ctypes.POINTER(_U64), _DP]),
     "fsb_batch_workspace_bytes": (_I, [ctypes.POINTER(fsb_config), _U32, _P, _P,

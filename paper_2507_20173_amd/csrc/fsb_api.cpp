@@ -439,6 +439,35 @@ int fsb_destroy(fsb_school* h) {
     return FSB_OK;
 }
 
+int fsb_run_static(const fsb_config* cfg, fsb_state state, uint64_t t, uint64_t n_steps,
+                   uint32_t mode, fsb_record* records, uint32_t* status, void* stream) {
+    // Every check comes before the first HIP call.
+    int rc = check_config(cfg, true);
+    if (rc) return rc;
+    rc = check_columns(state, cfg->n_fish);
+    if (rc) return rc;
+    if (!records) return fail(FSB_ERR_INVALID_ARG, "records is NULL");
+    if (!aligned(records, alignof(fsb_record)))
+        return fail(FSB_ERR_INVALID_ARG, "records is not 8-byte aligned");
+    if (status && !aligned(status, 4)) return fail(FSB_ERR_INVALID_ARG, "status is not 4-byte aligned");
+    if (mode > FSB_RUN_FUSED_DEEP) return fail(FSB_ERR_INVALID_ARG, "unknown run mode");
+    if (t >= kStepLimit || n_steps > kStepLimit - t)
+        return fail(FSB_ERR_INVALID_ARG, "iterations must stay below 2^32");
+    if (kStaticLayout.total > kStaticScratchBytes)  // the layout is fixed; checked at compile time
+        return fail(FSB_ERR_UNSUPPORTED, "the static scratch is smaller than a school's workspace");
+    void* ws = nullptr;
+    FSB_HIP_TRY(static_scratch(&ws), "address of the static scratch");
+    // A handle on the stack over the scratch, with the caller's ring.
+    fsb_school h{};
+    fill_school(&h, *cfg, state, ws, kStaticScratchBytes, stream, kStaticLayout, t);
+    h.args.hist = records;
+    FSB_HIP_TRY(launch_reset(h.args, h.stream), "reset launch");
+    rc = n_steps ? fsb_run(&h, n_steps, mode) : FSB_OK;
+    if (!rc) rc = finish_pending(&h);
+    if (!rc && status) FSB_HIP_TRY(launch_copy_error(h.args, status, h.stream), "status copy");
+    return rc;
+}
+
 int fsb_profile_enable(fsb_school* h, int every) {
     if (!h) return fail(FSB_ERR_INVALID_ARG, "handle is NULL");
     if (every < 0) return fail(FSB_ERR_INVALID_ARG, "every must be >= 0");

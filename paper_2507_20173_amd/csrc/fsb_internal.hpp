@@ -75,6 +75,21 @@ constexpr Layout school_layout(uint32_t history_len) {
     return L;
 }
 
+// Device scratch of the allocation-free entry point (fsb_run_static): every
+// area of one school's workspace except the record ring, which that call's
+// caller passes.  None of them grows with the school, the iteration count or
+// the ring, so one fixed array serves any call.  A file-scope array in the
+// kernel translation unit; each GPU holds its own copy until the process
+// ends.
+constexpr size_t kStaticScratchBytes = 1u << 20;
+constexpr Layout kStaticLayout = school_layout(0);
+static_assert(kStaticLayout.total <= kStaticScratchBytes, "the static scratch holds a school");
+// Device address of the current device's copy (looked up once per device).
+hipError_t static_scratch(void** out);
+// Copies the control block's error flags to *out (a device word), on the stream.
+struct SchoolArgs;
+hipError_t launch_copy_error(const SchoolArgs& a, uint32_t* out, hipStream_t stream);
+
 // Everything a single-school kernel needs, passed by value.
 struct SchoolArgs {
     float *x, *y, *w, *prev, *cur;

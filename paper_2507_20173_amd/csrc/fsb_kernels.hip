@@ -36,6 +36,7 @@
 
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "fsb_sweep.hpp"
 
@@ -1113,6 +1114,41 @@ __global__ __launch_bounds__(kBlock) void eval_sqrt_kernel(const float* in, floa
 // restart at 1 in every launch).
 __global__ void reset_sync_kernel(uint32_t* sync) {
     for (uint32_t i = threadIdx.x; i < kSyncWords; i += blockDim.x) sync[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free entry point.  In host code the array's name
+// is only a stand-in for the symbol: kernels get the device address that
+// hipGetSymbolAddress returns for the current device, never the name itself.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch(void** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));  // with device `dev` current
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
+
+__global__ void copy_error_kernel(const Ctrl* ctrl, uint32_t* out) {
+    if (threadIdx.x == 0) *out = ctrl->error;
+}
+
+hipError_t launch_copy_error(const SchoolArgs& a, uint32_t* out, hipStream_t stream) {
+    hipLaunchKernelGGL(copy_error_kernel, dim3(1), dim3(64), 0, stream, a.ctrl, out);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

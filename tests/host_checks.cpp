@@ -98,6 +98,7 @@ static void layout_checks() {
         CHECK(L.total >= L.deep + (size_t)kDeepSlots * 3 * kMaxBarrierBlocks * 8);
         CHECK(L.total % kAlign == 0 && L.hist % kAlign == 0 && L.deep % kAlign == 0);
     }
+    CHECK(kStaticLayout.total <= kStaticScratchBytes);
     for (bool deep : {false, true}) {
         const BatchLayout B = batch_layout(4096, 600000, 500, deep);
         CHECK(B.tile_begin >= B.sync + kSyncWords * 4);

@@ -236,3 +236,31 @@ def test_every_reduce_mode_has_a_workspace():
         rc, b = ws_bytes(cfg(reduce_mode=mode))
         assert rc == 0 and b > 0
 
+
+def run_static(c, st, t=0, n=1, mode=0, records=FAKE + (16 << 20), status=0):
+    return _lib.lib().fsb_run_static(ctypes.byref(c), st, t, n, mode, records, status, None)
+
+
+@pytest.mark.parametrize("case", ["null_records", "misaligned_records", "misaligned_status",
+                                  "bad_mode", "t_limit", "steps_limit", "bad_config",
+                                  "null_col"])
+def test_run_static_rejects_before_any_hip_call(case):
+    c, st, kw = cfg(), cols(), {}
+    if case == "null_records":
+        kw["records"] = 0
+    elif case == "misaligned_records":
+        kw["records"] = FAKE + (16 << 20) + 4
+    elif case == "misaligned_status":
+        kw["status"] = FAKE + (17 << 20) + 2
+    elif case == "bad_mode":
+        kw["mode"] = 6
+    elif case == "t_limit":
+        kw["t"] = 1 << 32
+    elif case == "steps_limit":
+        kw.update(t=(1 << 32) - 5, n=6)
+    elif case == "bad_config":
+        c = cfg(history_len=0)
+    elif case == "null_col":
+        st = cols(cur=0)
+    assert run_static(c, st, **kw) == _lib.FSB_ERR_INVALID_ARG
+    assert _lib.lib().fsb_last_error()
