@@ -242,6 +242,7 @@ int run_fused(fsb_school* h, uint64_t n_steps, uint32_t mode) {
     FusedArgs f{};
     f.regs = groups;
     f.deep = depth;
+    f.look_theta = depth ? look_theta(h->cfg.n_fish) : 0.0f;
     f.t0 = (uint32_t)h->t;
     f.steps = (uint32_t)n_steps;
     f.naive = naive;

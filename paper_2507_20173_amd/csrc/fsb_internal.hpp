@@ -132,7 +132,22 @@ struct FusedArgs {
                           // fish per thread (1, 2 or 4); streaming and lean are then unused
     uint32_t deep;        // > 0: the deep kernel, `deep` iterations per grid barrier (lean is
                           // then unused)
+    float look_theta;     // deep kernel, plain swim: > 0 lets the look-ahead skip the objective
+                          // of a fish that cannot reach theta times the smallest maximum of
+                          // the current superstep (0 = every objective is formed)
 };
+
+// Schools from this size on run the deep kernel's look-ahead with the skip
+// test (smaller schools' maxima vary more from one iteration to the next, so
+// the recomputation a wrong guess costs would come more often).
+constexpr uint64_t kLookFilterFish = 1ull << 20;
+// Fraction of the current maxima below which a look-ahead objective is skipped.
+constexpr float kLookTheta = 1.0f - 0x1p-7f;
+// theta for a school of n fish: kLookTheta from kLookFilterFish fish on, else
+// 0; the environment variable FSB_LOOKAHEAD_FILTER (read once) may say "off"
+// (never skip) or "redo" (theta 2: every guess fails and every superstep's
+// maxima are recomputed, for tests of that path).
+float look_theta(uint64_t n);
 
 // Launchers (fsb_kernels.hip).  All enqueue on `stream` and return the HIP
 // status of the launch.

@@ -812,9 +812,10 @@ __global__ __launch_bounds__(kDeepBlockOf<KD>) void fused_deep_kernel(SchoolArgs
         }
     };
 
-    // Prologue: maxima of the first superstep's iterations.
-    {
-        const uint32_t kd0 = min((uint32_t)KD, f.steps);
+    // Exact maxima of iterations t .. t + kd0 - 1 from the stored positions,
+    // reduced by one grid barrier: the prologue's, and the recomputation when
+    // a skip test guessed too high (below).
+    auto exact_maxima = [&](uint32_t t, uint32_t kd0) -> bool {
         uint32_t best[KD];
 #pragma unroll
         for (int j = 0; j < KD; ++j) best[j] = 0u;
@@ -827,7 +828,7 @@ __global__ __launch_bounds__(kDeepBlockOf<KD>) void fused_deep_kernel(SchoolArgs
             for (int j = 0; j < KD; ++j) {
                 if ((uint32_t)j >= kd0) break;
                 float dx[4], dy[4];
-                group_draws(a.S, a.k0, a.k1, g, f.t0 + j, dx, dy);
+                group_draws(a.S, a.k0, a.k1, g, t + j, dx, dy);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const float nc = swim(rule, lane_of(X, q), lane_of(Y, q), dx[q], dy[q], H,
@@ -839,12 +840,13 @@ __global__ __launch_bounds__(kDeepBlockOf<KD>) void fused_deep_kernel(SchoolArgs
         }
         if (has_tail) {
             const float x = a.x[tail_i], y = a.y[tail_i];
-            look_ahead(x, y, distance(x, y), tail_i, f.t0, kd0, best);
+            look_ahead(x, y, distance(x, y), tail_i, t, kd0, best);
         }
         uint32_t m[KD];
         block_max_k<KD, B>(best, m);
-        if (!barrier_maxima<KD>(bar, m, phase, M_sh)) return;
-    }
+        return barrier_maxima<KD>(bar, m, phase, M_sh);
+    };
+    if (!exact_maxima(f.t0, min((uint32_t)KD, f.steps))) return;
 
     uint32_t M_prev[KD];
     uint32_t kd_prev = 0;
@@ -868,6 +870,26 @@ __global__ __launch_bounds__(kDeepBlockOf<KD>) void fused_deep_kernel(SchoolArgs
 #pragma unroll
         for (int j = 0; j < KD; ++j) M_prev[j] = M_bits[j];
         kd_prev = kd;
+
+        // Under the plain swim, the look-ahead forms a fish's objectives only
+        // when its move could reach T, a guess just below this superstep's
+        // maxima (the maxima of a large school change little between
+        // iterations); the other fish cannot carry the maxima if these are at
+        // least T, which the barrier's published maxima then show, else they
+        // are recomputed exactly.
+        bool filtered = false;
+        float T = 0.0f, skip_limit = 0.0f;
+        if constexpr (kRule == 0) {
+            if (f.look_theta > 0.0f && !last) {
+                float m_min = M[0];
+#pragma unroll
+                for (int j = 1; j < KD; ++j)
+                    if ((uint32_t)j < kd) m_min = fminf(m_min, M[j]);
+                T = f.look_theta * m_min;
+                skip_limit = look_skip_limit(T, H, a.S);
+                filtered = true;
+            }
+        }
 
         LaneSumsF64 ls[KD];
         uint32_t best[KD];
@@ -899,6 +921,32 @@ __global__ __launch_bounds__(kDeepBlockOf<KD>) void fused_deep_kernel(SchoolArgs
             if (last) {
                 stv<kNT>(a.prev, g, P);
                 stv<kNT>(a.cur, g, C);
+            } else if (filtered) {
+                // The plain swim's own operations; C[q] is the objective of
+                // the current position only while fresh[q] holds.
+                bool fresh[4] = {true, true, true, true};
+#pragma unroll
+                for (int j = 0; j < KD; ++j) {
+                    if ((uint32_t)j >= kd_next) break;
+                    float dx[4], dy[4];
+                    group_draws(a.S, a.k0, a.k1, g, s0 + kd + j, dx, dy);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const float ox = lane_of(X, q), oy = lane_of(Y, q);
+                        lane_of(X, q) = clamp_to(ox + dx[q], -H, H);
+                        lane_of(Y, q) = clamp_to(oy + dy[q], -H, H);
+                        if (__builtin_fmaf(dx[q], dx[q], dy[q] * dy[q]) >= skip_limit) {
+                            float oc = lane_of(C, q);
+                            if (!fresh[q]) oc = distance(ox, oy);
+                            const float nc = distance(lane_of(X, q), lane_of(Y, q));
+                            best[j] = max(best[j], mag_bits(oc - nc));
+                            lane_of(C, q) = nc;
+                            fresh[q] = true;
+                        } else {
+                            fresh[q] = false;
+                        }
+                    }
+                }
             } else {
 #pragma unroll
                 for (int j = 0; j < KD; ++j) {
@@ -944,6 +992,14 @@ __global__ __launch_bounds__(kDeepBlockOf<KD>) void fused_deep_kernel(SchoolArgs
         uint32_t m[KD];
         block_max_k<KD, B>(best, m);
         if (!barrier_maxima<KD>(bar, m, phase, M_sh)) return;
+        if (filtered) {
+            // Every skipped fish's |diff| is below T: a published maximum of at
+            // least T is exact.  Any below T: recompute them all exactly (the
+            // same decision in every block: all see the same published words).
+            bool redo = false;
+            for (uint32_t j = 0; j < kd_next; ++j) redo |= __uint_as_float(M_sh[j]) < T;
+            if (redo && !exact_maxima(s0 + kd, kd_next)) return;
+        }
         if (last) {
             for (uint32_t j = 0; j < kd; ++j) {
                 const uint32_t t = s0 + j;
@@ -1297,6 +1353,18 @@ uint32_t deep_grid(uint64_t n, uint32_t depth, uint32_t resident) {
     if (g < 1) g = 1;
     if (g > resident) g = resident;
     return (uint32_t)g;
+}
+
+float look_theta(uint64_t n) {
+    static const int mode = [] {
+        const char* v = std::getenv("FSB_LOOKAHEAD_FILTER");
+        if (v && std::strcmp(v, "off") == 0) return 0;
+        if (v && std::strcmp(v, "redo") == 0) return 2;
+        return 1;
+    }();
+    if (mode == 0) return 0.0f;
+    if (mode == 2) return 2.0f;
+    return n >= kLookFilterFish ? kLookTheta : 0.0f;
 }
 
 uint32_t deep_depth(uint64_t n) {

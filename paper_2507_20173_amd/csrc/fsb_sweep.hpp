@@ -111,6 +111,27 @@ struct LaneSums {
     }
 };
 
+// Skip threshold of the deep kernels' look-ahead.  A plain swim by (dx, dy)
+// from objective c to nc changes it by |RN(c - nc)| <= (sqrt(dx^2 + dy^2) + K)
+// (1 + u), u = 2^-24, where K bounds every rounding on the way: each
+// coordinate sum x + dx rounds by at most u (H + S) (the clamp only shortens
+// the move), and each objective RN(sqrt(RN(RN(x^2) + RN(y^2)))) lies within
+// 2.01 u r of the true distance r <= H sqrt 2.  So K = u sqrt 2 (H + S) +
+// 4.02 u sqrt 2 H, taken here as 1.5 u (5.1 H + S) + 2^-60.  The fish's test
+// value q = fma(dx, dx, RN(dy * dy)) is at least (dx^2 + dy^2) (1 - u)^2.
+// Hence q < L, L = RD(((T - 2^-60) / (1 + 2u) - K)^2 (1 - 4u)), implies
+// |diff| < T: the fish cannot carry a maximum that is at least T.  L = 0 (no
+// fish skipped) when T is too small.
+__device__ __forceinline__ float look_skip_limit(float T, float H, float S) {
+    const double K = 0x1p-24 * 1.5 * (5.1 * (double)H + (double)S) + 0x1p-60;
+    const double root = ((double)T - 0x1p-60) / (1.0 + 0x1p-23) - K;
+    if (!(root > 0.0)) return 0.0f;
+    const double L = root * root * (1.0 - 0x1p-22);
+    float Lf = (float)L;
+    if ((double)Lf > L) Lf = __uint_as_float(__float_as_uint(Lf) - 1u);  // round down
+    return Lf;
+}
+
 // A value the caller knows to be the same in every lane, moved to a scalar
 // register: the compiler cannot prove that of a value read from memory, and
 // would otherwise hold one copy per lane in vector registers.

@@ -203,3 +203,58 @@ def test_deep_refuses_what_it_cannot_run(torch_cuda, cfg):
         sch.run(2, DEEP)
     assert e.value.code == fsb._lib.FSB_ERR_UNSUPPORTED
     sch.close()
+
+
+CHILD_FILTER = r"""
+import sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+import paper_2507_20173_amd as fsb
+out = {}
+for i, (n, runs) in enumerate(CASES):
+    total = sum(k for k, _ in runs)
+    s = fsb.School(fsb.FsbConfig(n_fish=n, seed=900 + i, history_len=total))
+    for k, mode in runs:
+        s.run(k, mode)
+    h = s.history(0, total)
+    out[f"max{i}"] = h["max_delta"]
+    out[f"sums{i}"] = np.stack([h["sum_w"], h["sum_wx"], h["sum_wy"]], 1)
+    st = s.state()
+    for k in fsb.COLUMNS:
+        out[f"{k}{i}"] = st[k]
+    s.close()
+np.savez(sys.argv[2], **out)
+"""
+FILTER_CASES = [((1 << 20) + 3, [(13, fsb.FSB_RUN_FUSED)]),
+                ((1 << 23) + 5, [(9, fsb.FSB_RUN_FUSED), (1, fsb.FSB_RUN_PLAIN),
+                                 (6, fsb.FSB_RUN_FUSED)])]
+
+
+@pytest.mark.parametrize("setting", ["redo", "off"])
+def test_lookahead_skip_settings_in_a_child(torch_cuda, O, tmp_path, setting):
+    """The deep kernel's look-ahead skips the objectives of fish whose move
+    cannot reach a guess just below the current maxima, and recomputes the
+    maxima exactly when a published one falls below the guess.  With
+    FSB_LOOKAHEAD_FILTER=redo (read once per process) every guess is too high,
+    so every superstep takes the recomputation; with "off" nothing is
+    skipped.  Both equal the oracle bit for bit."""
+    import os
+    import subprocess
+    import sys
+    announce(f"FSB_LOOKAHEAD_FILTER={setting} in a child process")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = tmp_path / f"filter_{setting}.npz"
+    env = dict(os.environ, FSB_LOOKAHEAD_FILTER=setting, FSB_PERSISTENT_LAUNCH="regular")
+    child = CHILD_FILTER.replace("CASES", repr(FILTER_CASES))
+    subprocess.run([sys.executable, "-c", child, root, str(out)], env=env, check=True, timeout=240)
+    got = np.load(out)
+    for i, (n, runs) in enumerate(FILTER_CASES):
+        total = sum(k for k, _ in runs)
+        cfg = fsb.FsbConfig(n_fish=n, seed=900 + i, history_len=total)
+        ocfg = oracle_config(cfg)
+        school = O.init(ocfg)
+        m, s, a = O.run(ocfg, school, 0, total)
+        what = f"filter {setting} n={n}"
+        assert np.array_equal(got[f"max{i}"].view(np.uint32), m.view(np.uint32)), what
+        assert_sums_close(got[f"sums{i}"], s, a, what=what)
+        assert_columns_equal({k: got[f"{k}{i}"] for k in fsb.COLUMNS}, school, what)
