@@ -22,6 +22,9 @@
 // single-school persistent kernel; schools differ only in key and range.
 // The first iteration index is read from a device counter that each launch
 // advances, so one captured launch can be replayed as a graph.
+#include <cstdlib>
+#include <cstring>
+
 #include "fsb_sweep.hpp"
 
 namespace fsb {
@@ -132,7 +135,9 @@ __global__ void batch_reset_kernel(BatchArgs a) {
     for (uint32_t i = tid; i < kSyncWords; i += nth) a.sync[i] = 0u;
     for (uint32_t i = tid; i < a.max_slots * a.n_schools; i += nth) a.school_max[i] = 0u;
     for (uint32_t i = tid; i < 8 * a.n_schools; i += nth) a.school_naive[i] = 0.0f;
+    for (uint32_t i = tid; i < a.n_schools; i += nth) a.school_flag[i] = 0u;
     if (tid < 2) a.queue[tid * kLineWords] = 0u;
+    if (tid < 2) a.ctrl->redo[tid] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -576,20 +581,35 @@ void batch_deep_kernel(BatchArgs a) {
     }
     if (!barrier_max(bar, 0u, phase, &M_sh)) return;
 
+    // A sweep replays a superstep and swims the next one ahead.  Under the
+    // plain swim the look-ahead of a large school forms a fish's objectives
+    // only when its move can reach a guess just below the school's current
+    // maxima (look_skip_limit); the guess is checked after the barrier, and
+    // a school whose next maxima fall below it is swept once more, with no
+    // replay and an exact look-ahead, before the next superstep.
     uint32_t kd_prev = 0;
-    for (uint32_t k0 = 0; k0 < a.steps; k0 += KD) {
+    uint32_t sweep = 0;       // sweep phase (0 = prologue)
+    bool redo_sweep = false;  // this sweep only redoes flagged schools' look-ahead
+    for (uint32_t k0 = 0; k0 < a.steps;) {
         const uint32_t s0 = t0 + k0;
         const uint32_t kd = min((uint32_t)KD, a.steps - k0);
         const uint32_t kd_next = min((uint32_t)KD, a.steps - k0 - kd);
         const bool last = kd_next == 0;
-        const uint32_t sweep = k0 / KD + 1u;  // sweep phase (0 = prologue)
-        if (k0 > 0) combine_schools_deep<KD>(a, s0 - kd_prev, kd_prev, wave, n_waves, lane);
+        ++sweep;
+        if (k0 > 0 && !redo_sweep)
+            combine_schools_deep<KD>(a, s0 - kd_prev, kd_prev, wave, n_waves, lane);
         kd_prev = kd;
         // this sweep takes phase `sweep`'s counter; the other one (last used by
         // the previous phase, which every wavefront has left) is cleared for
         // the next phase
         uint32_t* const queue = queue_of(a, sweep);
         if (a.n_chunks && blockIdx.x == 0 && threadIdx.x == 0) st_agent(queue_of(a, sweep + 1u), 0u);
+        // the redo word of this phase's parity: last read after the check two
+        // phases ago, which every block has left
+        uint32_t* const redo = &a.ctrl->redo[sweep & 1u];
+        if (blockIdx.x == 0 && threadIdx.x == 0) st_agent(redo, 0u);
+        bool filt = false;
+        float skip_limit = 0.0f;
         uint32_t best[KD];
 #pragma unroll
         for (int j = 0; j < KD; ++j) best[j] = 0u;
@@ -600,6 +620,7 @@ void batch_deep_kernel(BatchArgs a) {
         for (Walk w = first_tile(a, queue, lane, wave); w.tl < a.n_tiles;
              next_tile(a, queue, lane, n_waves, w)) {
             const Tile T = a.tiles[w.tl];
+            if (redo_sweep && !uniform(ld_agent(a.school_flag + T.school))) continue;
             if (T.school != run_school) {
                 if (run_school != 0xffffffffu && !last)
                     flush_maxima<KD>(a, best, s0 + kd, kd_next, run_school, lane);
@@ -610,6 +631,17 @@ void batch_deep_kernel(BatchArgs a) {
                     if ((uint32_t)j < kd)
                         M[j] = __uint_as_float(uniform(
                             a.school_max[(size_t)((s0 + j) % (3 * KD)) * a.n_schools + T.school]));
+                if constexpr (kRule == 0) {
+                    filt = !redo_sweep && a.look_theta > 0.0f && !last &&
+                           a.tile_begin[T.school + 1] - a.tile_begin[T.school] >= a.look_min_tiles;
+                    if (filt) {
+                        float m_min = M[0];
+#pragma unroll
+                        for (int j = 1; j < KD; ++j)
+                            if ((uint32_t)j < kd) m_min = fminf(m_min, M[j]);
+                        skip_limit = look_skip_limit(a.look_theta * m_min, H, Sw);
+                    }
+                }
             }
             LaneSumsF64 ls[KD];
 #pragma unroll
@@ -638,7 +670,7 @@ void batch_deep_kernel(BatchArgs a) {
                 for (int f = 0; f < 4; ++f) lane_of(C, f) = distance(lane_of(X, f), lane_of(Y, f));
 #pragma unroll
                 for (int j = 0; j < KD; ++j) {
-                    if ((uint32_t)j >= kd) break;
+                    if ((uint32_t)j >= kd || redo_sweep) break;  // a redo sweep replays nothing
                     float dx[4], dy[4];
                     group_draws(Sw, T.k0, T.k1, g, s0 + j, dx, dy);
                     P = C;
@@ -657,7 +689,9 @@ void batch_deep_kernel(BatchArgs a) {
                             if ((uint32_t)f < nf) ls[j].add(lane_of(W, f), lane_of(X, f), lane_of(Y, f));
                     }
                 }
-                if (nf == 4) {
+                if (redo_sweep) {
+                    // the columns stay as stored
+                } else if (nf == 4) {
                     stv<kNT>(a.x, c4, X);
                     stv<kNT>(a.y, c4, Y);
                     stv<kNT>(a.w, c4, W);
@@ -678,7 +712,34 @@ void batch_deep_kernel(BatchArgs a) {
                         }
                     }
                 }
-                if (!last) {
+                if (!last && filt) {
+                    // the plain swim's operations; C[f] is the objective of the
+                    // current position only while fresh[f] holds
+                    bool fresh[4] = {true, true, true, true};
+#pragma unroll
+                    for (int j = 0; j < KD; ++j) {
+                        if ((uint32_t)j >= kd_next) break;
+                        float dx[4], dy[4];
+                        group_draws(Sw, T.k0, T.k1, g, s0 + kd + j, dx, dy);
+#pragma unroll
+                        for (int f = 0; f < 4; ++f) {
+                            const float ox = lane_of(X, f), oy = lane_of(Y, f);
+                            lane_of(X, f) = clamp_to(ox + dx[f], -H, H);
+                            lane_of(Y, f) = clamp_to(oy + dy[f], -H, H);
+                            if ((uint32_t)f < nf &&
+                                __builtin_fmaf(dx[f], dx[f], dy[f] * dy[f]) >= skip_limit) {
+                                float oc = lane_of(C, f);
+                                if (!fresh[f]) oc = distance(ox, oy);
+                                const float nc = distance(lane_of(X, f), lane_of(Y, f));
+                                best[j] = max(best[j], mag_bits(oc - nc));
+                                lane_of(C, f) = nc;
+                                fresh[f] = true;
+                            } else {
+                                fresh[f] = false;
+                            }
+                        }
+                    }
+                } else if (!last) {
 #pragma unroll
                     for (int j = 0; j < KD; ++j) {
                         if ((uint32_t)j >= kd_next) break;
@@ -702,7 +763,7 @@ void batch_deep_kernel(BatchArgs a) {
             // TwoSum butterfly does
 #pragma unroll
             for (int j = 0; j < KD; ++j) {
-                if ((uint32_t)j >= kd) break;
+                if ((uint32_t)j >= kd || redo_sweep) break;
                 double v[3];
                 for (int k = 0; k < 3; ++k) v[k] = wave_sum_f64(ls[j].v[k]);
                 if (lane == 0) {
@@ -714,7 +775,42 @@ void batch_deep_kernel(BatchArgs a) {
         if (run_school != 0xffffffffu && !last)
             flush_maxima<KD>(a, best, s0 + kd, kd_next, run_school, lane);
         if (!barrier_max(bar, 0u, phase, &M_sh)) return;
-        if (last) combine_schools_deep<KD>(a, s0, kd, wave, n_waves, lane);
+        bool again = false;
+        if (kRule == 0 && !redo_sweep && a.look_theta > 0.0f && !last) {
+            // Every skipped |diff| is below the school's guess, so a published
+            // maximum of at least the guess is exact.  One wavefront per
+            // skipping school checks the next maxima against the guess, formed
+            // from the same words as in the sweep; a school with one below it
+            // is flagged.  After one more barrier, if any school is flagged,
+            // the next sweep redoes those schools' look-ahead exactly (their
+            // atomic maxima then reach the exact values: the skipping sweep's
+            // are never above them).
+            const size_t S = a.n_schools;
+            for (uint32_t c = wave; c < a.n_schools; c += n_waves) {
+                if (a.tile_begin[c + 1] - a.tile_begin[c] < a.look_min_tiles) continue;
+                if (lane == 0) {
+                    const uint32_t* mx = a.school_max + c;
+                    float m_min = __uint_as_float(ld_agent(mx + (size_t)(s0 % (3 * KD)) * S));
+                    for (uint32_t j = 1; j < kd; ++j)
+                        m_min = fminf(m_min, __uint_as_float(
+                                                 ld_agent(mx + (size_t)((s0 + j) % (3 * KD)) * S)));
+                    const float guess = a.look_theta * m_min;
+                    uint32_t fail = 0u;
+                    for (uint32_t j = 0; j < kd_next; ++j)
+                        fail |= __uint_as_float(
+                                    ld_agent(mx + (size_t)((s0 + kd + j) % (3 * KD)) * S)) < guess;
+                    st_agent(a.school_flag + c, fail);
+                    if (fail) st_agent(redo, 1u);
+                }
+            }
+            if (!barrier_max(bar, 0u, phase, &M_sh)) return;
+            again = ld_agent(redo) != 0u;  // the same superstep's look-ahead again
+        }
+        redo_sweep = again;
+        if (!again) {
+            if (last) combine_schools_deep<KD>(a, s0, kd, wave, n_waves, lane);
+            k0 += KD;
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) st_agent(a.step, t0 + a.steps);
 }
@@ -722,6 +818,16 @@ void batch_deep_kernel(BatchArgs a) {
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
+float batch_look_theta() {
+    static const float theta = [] {
+        const char* v = std::getenv("FSB_LOOKAHEAD_FILTER");
+        if (v && std::strcmp(v, "off") == 0) return 0.0f;
+        if (v && std::strcmp(v, "redo") == 0) return 2.0f;
+        return kBatchLookTheta;
+    }();
+    return theta;
+}
+
 hipError_t launch_batch_init(const BatchArgs& a, uint32_t /*block*/, hipStream_t stream) {
     uint64_t waves = a.n_tiles;
     uint64_t blocks = (waves + 3) / 4;

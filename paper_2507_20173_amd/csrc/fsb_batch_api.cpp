@@ -158,6 +158,13 @@ BatchArgs launch_args(const fsb_batch* b, uint32_t steps, uint32_t grid) {
     BatchArgs a = b->args;
     a.steps = steps;
     a.spin_limit = barrier_spin_limit();
+    // the deep variant's look-ahead skip test: plain swim, schools of at least
+    // kBatchLookFish fish (in whole tiles of this shape)
+    const uint32_t tile_fish = 64u * b->tuning.fish_per_thread;
+    a.look_theta = batch_variant(b) == kBatchDeep && !(b->cfg.swim_rule & FSB_SWIM_GREEDY)
+                       ? batch_look_theta()
+                       : 0.0f;
+    a.look_min_tiles = (uint32_t)((kBatchLookFish + tile_fish - 1) / tile_fish);
     return a;
 }
 
@@ -438,6 +445,7 @@ int fsb_batch_init(const fsb_config* common, uint32_t n_schools, const uint64_t*
     a.hist_len = common->history_len;
     a.chunk_start = reinterpret_cast<const uint32_t*>(base + L.chunks);
     a.queue = reinterpret_cast<uint32_t*>(base + L.queue);
+    a.school_flag = reinterpret_cast<uint32_t*>(base + L.school_flag);
 
     auto cleanup = [&](int code) {
         delete b;

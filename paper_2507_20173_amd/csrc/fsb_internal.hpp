@@ -22,7 +22,9 @@ struct Ctrl {
     uint32_t probe_max;       // M of the last barrier of a barrier probe
     float naive_acc[2][4];    // float32 atomic sums of the naive and critical modes, slot t & 1
     uint32_t crit_max[2];     // critical mode: max |diff| bits by per-fish atomics, slot t & 1
-    uint32_t pad[50];
+    uint32_t redo[2];         // deep batches: some school's look-ahead guess failed in the sweep
+                              // of this parity, its maxima are recomputed
+    uint32_t pad[48];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl is one aligned block");
 
@@ -245,12 +247,27 @@ struct BatchArgs {
     const uint32_t* chunk_start;    // [n_chunks + 1]
     uint32_t n_chunks;
     uint32_t* queue;                // two counters, one 256-byte line each
+    // Deep kernel's look-ahead skip test (plain swim): schools of at least
+    // look_min_tiles tiles skip the objectives of fish whose move cannot reach
+    // look_theta times the school's smallest current maximum (0 = never).
+    float look_theta;
+    uint32_t look_min_tiles;
+    uint32_t* school_flag;          // [S] 1: the school's next maxima must be recomputed
 };
+
+// Fraction of a school's current maxima under which the batched look-ahead
+// skips an objective.  A school of 2^16 fish or more; smaller schools' maxima
+// vary by several percent between iterations and are not skipped.
+constexpr float kBatchLookTheta = 0.98f;
+constexpr uint64_t kBatchLookFish = 1ull << 16;
+// theta of the batched look-ahead: kBatchLookTheta, or as FSB_LOOKAHEAD_FILTER
+// (read once) says: "off" 0, "redo" 2 (every guess fails, for tests).
+float batch_look_theta();
 
 // Workspace of a batch (offsets in bytes).
 struct BatchLayout {
     size_t ctrl, sync, tile_begin, tiles, tile_part, school_max, school_naive, rec, chunks,
-        queue, total;
+        queue, school_flag, total;
     uint32_t tile_cap;
 };
 
@@ -272,7 +289,8 @@ inline BatchLayout batch_layout(uint32_t n_schools, uint64_t tile_cap, uint32_t 
     L.rec = align_up(L.school_naive + 2 * S * 4 * sizeof(float), kAlign);
     L.chunks = align_up(L.rec + (size_t)history_len * S * sizeof(fsb_record), kAlign);
     L.queue = align_up(L.chunks + (tile_cap + 1) * sizeof(uint32_t), kAlign);
-    L.total = align_up(L.queue + 2 * kLineWords * sizeof(uint32_t), kAlign);
+    L.school_flag = align_up(L.queue + 2 * kLineWords * sizeof(uint32_t), kAlign);
+    L.total = align_up(L.school_flag + S * sizeof(uint32_t), kAlign);
     return L;
 }
 

@@ -206,3 +206,59 @@ def test_deep_batch_refusals(torch_cuda):
         assert e.value.code == fsb._lib.FSB_ERR_UNSUPPORTED
         b.run(2, fsb.tuning(256, 8, 2))  # the library's choice still runs
         b.close()
+
+
+CHILD_FILTER = r"""
+import sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+import paper_2507_20173_amd as fsb
+sizes, seeds, steps = SIZES_SEEDS_STEPS
+b = fsb.Batch(fsb.FsbConfig(n_fish=0, history_len=steps), sizes, seeds)
+b.run(steps, fsb.tuning(256, 16, 1000, variant=fsb.FSB_RUN_FUSED_DEEP,
+                        schedule=fsb.FSB_SCHED_DYNAMIC, chunk_tiles=4))
+out = {}
+for t in range(steps):
+    h = b.history(t)
+    out[f"max{t}"] = h["max_delta"]
+    out[f"sums{t}"] = np.stack([h["sum_w"], h["sum_wx"], h["sum_wy"]], 1)
+for i in range(b.n):
+    st = b.school_state(i)
+    for k in fsb.COLUMNS:
+        out[f"{k}{i}"] = st[k]
+b.close()
+np.savez(sys.argv[2], **out)
+"""
+
+
+@pytest.mark.parametrize("setting", ["redo", "off"])
+def test_deep_batch_lookahead_skip_settings_in_a_child(torch_cuda, O, tmp_path, setting):
+    """Schools of 2^16 fish or more skip look-ahead objectives that cannot
+    reach a guess just below their current maxima; a school whose next maxima
+    fall below the guess is swept once more with an exact look-ahead.  With
+    FSB_LOOKAHEAD_FILTER=redo (read once per process) every guess fails, so
+    every superstep takes that extra sweep for every large school; with
+    "off" nothing is skipped.  Both equal the oracle, school by school."""
+    import os
+    import subprocess
+    import sys
+    sizes = [70_001, 200_003, 1_000, 5, 131_072]
+    seeds = [41, 42, 43, 44, 45]
+    steps = 19
+    announce(f"FSB_LOOKAHEAD_FILTER={setting} batch in a child process")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = tmp_path / f"batch_filter_{setting}.npz"
+    env = dict(os.environ, FSB_LOOKAHEAD_FILTER=setting, FSB_PERSISTENT_LAUNCH="regular")
+    child = CHILD_FILTER.replace("SIZES_SEEDS_STEPS", repr((sizes, seeds, steps)))
+    subprocess.run([sys.executable, "-c", child, root, str(out)], env=env, check=True, timeout=240)
+    got = np.load(out)
+    for i, (n, seed) in enumerate(zip(sizes, seeds)):
+        ocfg = oracle_config(fsb.FsbConfig(n_fish=n, seed=seed))
+        school = O.init(ocfg)
+        m, s, a = O.run(ocfg, school, 0, steps)
+        what = f"batch filter {setting} school {i} ({n} fish)"
+        gm = np.array([got[f"max{t}"][i] for t in range(steps)], np.float32)
+        assert np.array_equal(gm.view(np.uint32), m.view(np.uint32)), what
+        gs = np.array([got[f"sums{t}"][i] for t in range(steps)])
+        assert_sums_close(gs, s, a, what=what)
+        assert_columns_equal({k: got[f"{k}{i}"] for k in fsb.COLUMNS}, school, what)
