@@ -4,8 +4,11 @@ multiply-adds in any kernel are those inside the correctly rounded sqrtf
 v_div_fixup_f32) expansions, plus the swim displacements' explicit
 fma(S * 2^-23, r >> 8, -S), which rounds once exactly as S * v(r) does (its
 addend is the uniform -S, read from a scalar register, negated there or by the
-operand modifier); and no packed-FP32 instruction is
-emitted, in the single-school and the batch kernels alike."""
+operand modifier), and the deep kernels' look-ahead skip test fma(dx, dx,
+RN(dy * dy)), a bound on a move's length that feeds no fish's state (both
+multiplicands the same register, only in the deep kernels' plain-swim
+instances); and no packed-FP32 instruction is emitted, in the single-school and
+the batch kernels alike."""
 import re
 
 import pytest
@@ -42,20 +45,33 @@ def test_kernels_found(kernels):
 
 
 DRAW_FMA = r"\bv_fma_f32\s+v\d+,\s*v\d+,\s*v\d+,\s*-?s\d+"
+# the skip test's fma(dx, dx, q): the same register as both multiplicands
+SQUARE_FMA = r"\bv_fma_f32\s+v\d+,\s*(v\d+),\s*\1,\s*v\d+|\bv_fmac_f32_e32\s+v\d+,\s*(v\d+),\s*\2\b"
+
+
+def is_deep_plain_swim(name):
+    # fused_deep_kernel<KD, NT, 0u> and batch_deep_kernel<B, GPL, NT, KD, 0u>
+    return ("fused_deep_kernel" in name or "batch_deep_kernel" in name) and name.endswith(
+        "Lj0EEEvNS_10SchoolArgsENS_9FusedArgsE") or (
+        "batch_deep_kernel" in name and name.endswith("Lj0EEEvNS_9BatchArgsE"))
 
 
 def test_no_contraction_outside_sqrt_and_div(kernels):
-    draws_seen = 0
+    draws_seen = squares_seen = 0
     for name, body in kernels.items():
         fma = count(body, r"\bv_(fma|fmac|mac|mad)_f32|\bv_fma_mix")
         draws = count(body, DRAW_FMA)
+        squares = count(body, SQUARE_FMA)
         sqrt = count(body, r"\bv_sqrt_f32")
         div = count(body, r"\bv_div_fixup_f32")
-        assert fma - draws == 2 * sqrt + 5 * div, (
-            f"{name}: {fma} fused ops ({draws} draws) vs {sqrt} sqrt and {div} div expansions")
+        assert squares == 0 or is_deep_plain_swim(name), f"{name}: {squares} square fmas"
+        assert fma - draws - squares == 2 * sqrt + 5 * div, (
+            f"{name}: {fma} fused ops ({draws} draws, {squares} skip tests) vs {sqrt} sqrt "
+            f"and {div} div expansions")
         assert draws % 2 == 0, f"{name}: draws come in (dx, dy) pairs"
         draws_seen += draws
-    assert draws_seen > 0
+        squares_seen += squares
+    assert draws_seen > 0 and squares_seen > 0
 
 
 def test_no_packed_fp32(kernels):
