@@ -154,8 +154,9 @@ def persistent_bytes(variant: str, n: int, steps: int) -> int:
     """Algorithmic bytes of one persistent launch of `steps` iterations."""
     if variant == "regs":  # x, y, w read once, all five columns written once
         return n * (12 + 20)
-    if variant == "deep":  # prologue reads x, y; 24 B per superstep; the last adds prev, cur
-        return n * (8 + 24 * -(-steps // deep_depth(n)) + 8)
+    if variant == "deep":  # prologue reads x, y; 32 B per superstep (x, y, w, cur read and
+        # written; the first forms cur instead of reading it, the last also writes prev)
+        return n * (8 + 32 * -(-steps // deep_depth(n)))
     if variant == "lean":  # prologue reads x, y; sweeps 24 B; the last also writes prev, cur
         return n * (8 + 24 * steps + 8)
     return n * (20 + 32 * (steps - 1) + 24)  # prologue 20 B, sweeps 32 B, last sweep 24 B
@@ -182,10 +183,10 @@ def batch_bytes(variant: str, fish: int, steps: int, per_launch: int, launches: 
     `per_launch` (the last one shorter if it does not divide)."""
     if variant == "lean":  # prologue reads x, y; 24 B per iteration; the last sweep writes prev, cur
         return fish * (16 * launches + 24 * steps)
-    if variant == "deep":  # the same per launch; 24 B per superstep of BATCH_DEEP_DEPTH iterations
+    if variant == "deep":  # per launch as a single school's: prologue 8 B, 32 B per superstep
         full, rest = divmod(steps, per_launch)
         supersteps = full * -(-per_launch // BATCH_DEEP_DEPTH) + -(-rest // BATCH_DEEP_DEPTH)
-        return fish * (16 * launches + 24 * supersteps)
+        return fish * (8 * launches + 32 * supersteps)
     return fish * (44 * launches + 32 * (steps - launches))  # prologue 20 B, last sweep 24 B
 
 
@@ -211,7 +212,7 @@ def fused_vs_plain(n: int, steps: int, label: str):
             key, fused_variant(n))
         kernel_s = ms[fsb.FSB_KERNEL_FUSED] / 1e3
         nbytes = persistent_bytes(variant, n, steps)
-        per_step = {"lean": 24, "prev": 32, "regs": 32 / steps, "deep": 24 / deep_depth(n)}[variant]
+        per_step = {"lean": 24, "prev": 32, "regs": 32 / steps, "deep": 32 / deep_depth(n)}[variant]
         barriers_per_step = 1.0 / deep_depth(n) if variant == "deep" else 1.0
         out[key] = {"variant": variant, "value": n * steps / wall, "ms_per_step": wall / steps * 1e3,
                     "launches": int(counts[fsb.FSB_KERNEL_FUSED]),
@@ -534,7 +535,7 @@ def batched_form(n_schools: int, steps: int, probe_steps: int, baseline_schools:
         "variant": variant,
         "lane_sums": "binary64 accumulation of pairwise float32 group totals" if variant == "deep"
         else "compensated float32 (TwoSum) lanes",
-        "algorithmic_bytes_per_fish_step": {"lean": 24, "prev": 32, "deep": 24 / BATCH_DEEP_DEPTH}[variant],
+        "algorithmic_bytes_per_fish_step": {"lean": 24, "prev": 32, "deep": 32 / BATCH_DEEP_DEPTH}[variant],
         "kernel_achieved_GBs": bytes_total / (ms / 1e3) / 1e9,
         "kernel_hbm_frac": bytes_total / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
         "baseline_per_school_plain": {"schools": baseline_schools, "fish": base_fish,

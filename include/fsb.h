@@ -107,9 +107,10 @@ extern "C" {
                                  barrier: positions do not depend on weights, so the
                                  differences of the next iterations are formed before
                                  their maxima are known; each swim is computed twice,
-                                 24 B per fish per barrier.  8 iterations per barrier
-                                 (3 B per fish-iteration) for schools of up to 2^23
-                                 fish, 4 above (6 B per fish-iteration, in blocks that
+                                 32 B per fish per barrier (x, y, w and cur read and
+                                 written).  8 iterations per barrier (4 B per
+                                 fish-iteration) for schools of up to 2^23 fish, 4
+                                 above (8 B per fish-iteration, in blocks that
                                  keep three waves per SIMD: faster there on MI355X);
                                  the environment variable FSB_DEEP_DEPTH, read once,
                                  may force 2, 4 or 8.

@@ -460,7 +460,8 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs a) {
 // Deep batched kernel: KD iterations per grid barrier, as the single-school
 // deep kernel (positions do not depend on weights, so a superstep replays its
 // swims with the published maxima and swims the next superstep ahead for its
-// maxima; x, y, w are read and written once per superstep).  Per school the
+// maxima; x, y, w and the objective cur are read and written once per
+// superstep, cur formed from the positions only in a launch's first).  Per school the
 // maxima of iteration t live in slot t mod 3 KD of the max ring (written by
 // the previous superstep's look-ahead, read by this one, cleared by the next
 // one's combine), the tile partials of iteration t in slot t mod 2 KD.
@@ -666,8 +667,17 @@ void batch_deep_kernel(BatchArgs a) {
                         lane_of(W, f) = (uint32_t)f < nf ? a.w[4 * c4 + f] : 0.0f;
                     }
                 }
+                if (k0 == 0 && !redo_sweep) {
 #pragma unroll
-                for (int f = 0; f < 4; ++f) lane_of(C, f) = distance(lane_of(X, f), lane_of(Y, f));
+                    for (int f = 0; f < 4; ++f)
+                        lane_of(C, f) = distance(lane_of(X, f), lane_of(Y, f));
+                } else if (nf == 4) {  // stored by this launch's previous sweep (below)
+                    C = ldv<kNT>(a.cur, c4);
+                } else {
+#pragma unroll
+                    for (int f = 0; f < 4; ++f)
+                        lane_of(C, f) = (uint32_t)f < nf ? a.cur[4 * c4 + f] : 0.0f;
+                }
 #pragma unroll
                 for (int j = 0; j < KD; ++j) {
                     if ((uint32_t)j >= kd || redo_sweep) break;  // a redo sweep replays nothing
@@ -695,10 +705,8 @@ void batch_deep_kernel(BatchArgs a) {
                     stv<kNT>(a.x, c4, X);
                     stv<kNT>(a.y, c4, Y);
                     stv<kNT>(a.w, c4, W);
-                    if (last) {
-                        stv<kNT>(a.prev, c4, P);
-                        stv<kNT>(a.cur, c4, C);
-                    }
+                    stv<kNT>(a.cur, c4, C);
+                    if (last) stv<kNT>(a.prev, c4, P);
                 } else {
 #pragma unroll
                     for (int f = 0; f < 4; ++f) {
@@ -706,10 +714,8 @@ void batch_deep_kernel(BatchArgs a) {
                         a.x[4 * c4 + f] = lane_of(X, f);
                         a.y[4 * c4 + f] = lane_of(Y, f);
                         a.w[4 * c4 + f] = lane_of(W, f);
-                        if (last) {
-                            a.prev[4 * c4 + f] = lane_of(P, f);
-                            a.cur[4 * c4 + f] = lane_of(C, f);
-                        }
+                        a.cur[4 * c4 + f] = lane_of(C, f);
+                        if (last) a.prev[4 * c4 + f] = lane_of(P, f);
                     }
                 }
                 if (!last && filt) {

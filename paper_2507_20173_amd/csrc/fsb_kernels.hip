@@ -763,13 +763,16 @@ __global__ __launch_bounds__(kFusedBlock) void fused_lean_kernel(SchoolArgs a, F
 // depend on (seed, fish, t) only, and the greedy test on objectives only), so
 // the differences of KD iterations ahead can be formed before any of their
 // maxima is known.  A superstep of kd <= KD iterations s0 .. s0 + kd - 1
-// reads (x, y, w) once: it replays swims s0 .. s0 + kd - 1 from the stored
-// positions, feeding with the maxima M_s0 .. published by the previous
+// reads (x, y, w, cur) once: it replays swims s0 .. s0 + kd - 1 from the
+// stored positions, feeding with the maxima M_s0 .. published by the previous
 // barrier and adding each iteration's partial sums; then, from a copy of the
 // final positions, it swims the next superstep's iterations only for their
-// maxima; it writes (x, y, w) once.  One barrier reduces all those maxima.
-// Columns: 24 B per fish per superstep, 24 / KD per fish-iteration; each swim
-// is computed twice, as in the lean kernel.  Every operation of a fish is the
+// maxima; it writes (x, y, w, cur) once.  cur carries the objective of the
+// stored positions from one superstep to the next, which saves forming it
+// again (a square root per fish and superstep) for 8 B; the first superstep
+// of a launch forms it from the positions.  One barrier reduces all the
+// maxima.  Columns: 32 B per fish per superstep, 32 / KD per fish-iteration;
+// each swim is computed twice, as in the lean kernel.  Every operation of a fish is the
 // plain path's, in the same order, so the bits are the same.  Compensated
 // sums only; the host never picks it under the weighted rule.  The rule is a
 // template argument (kRule: 0 or kSwimGreedy), so the plain swim carries no
@@ -898,8 +901,12 @@ __global__ __launch_bounds__(kDeepBlockOf<KD>) void fused_deep_kernel(SchoolArgs
         for (uint64_t g = gbase; g < n4; g += stride) {
             float4 X = ldv<kNT>(a.x, g), Y = ldv<kNT>(a.y, g), W = ldv<kNT>(a.w, g);
             float4 C, P;
+            if (k0 == 0) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) lane_of(C, q) = distance(lane_of(X, q), lane_of(Y, q));
+                for (int q = 0; q < 4; ++q) lane_of(C, q) = distance(lane_of(X, q), lane_of(Y, q));
+            } else {
+                C = ldv<kNT>(a.cur, g);  // stored by the previous superstep (below)
+            }
 #pragma unroll
             for (int j = 0; j < KD; ++j) {
                 if ((uint32_t)j >= kd) break;
@@ -918,9 +925,9 @@ __global__ __launch_bounds__(kDeepBlockOf<KD>) void fused_deep_kernel(SchoolArgs
             stv<kNT>(a.x, g, X);
             stv<kNT>(a.y, g, Y);
             stv<kNT>(a.w, g, W);
+            stv<kNT>(a.cur, g, C);
             if (last) {
                 stv<kNT>(a.prev, g, P);
-                stv<kNT>(a.cur, g, C);
             } else if (filtered) {
                 // The plain swim's own operations; C[q] is the objective of
                 // the current position only while fresh[q] holds.

@@ -67,14 +67,14 @@ def test_persistent_bytes_accounting():
     assert bench.persistent_bytes("lean", n, 10) == n * (8 + 24 * 10 + 8)
     assert bench.persistent_bytes("prev", n, 10) == n * (20 + 32 * 9 + 24)
     assert bench.persistent_bytes("regs", n, 10) == n * 32
-    assert bench.persistent_bytes("deep", n, 16) == n * (8 + 24 * 2 + 8)
-    assert bench.persistent_bytes("deep", n, 17) == n * (8 + 24 * 3 + 8)
+    assert bench.persistent_bytes("deep", n, 16) == n * (8 + 32 * 2)
+    assert bench.persistent_bytes("deep", n, 17) == n * (8 + 32 * 3)
     big = (1 << 23) + 4  # above 2^23 fish the single-school deep kernel runs four per barrier
-    assert bench.persistent_bytes("deep", 1 << 23, 16) == (1 << 23) * (8 + 24 * 2 + 8)
-    assert bench.persistent_bytes("deep", big, 16) == big * (8 + 24 * 4 + 8)
+    assert bench.persistent_bytes("deep", 1 << 23, 16) == (1 << 23) * (8 + 32 * 2)
+    assert bench.persistent_bytes("deep", big, 16) == big * (8 + 32 * 4)
     assert bench.fused_variant(1 << 26) == "deep"
-    assert bench.batch_bytes("deep", n, 500, 1000, 1) == n * (16 + 24 * 63)
-    assert bench.batch_bytes("deep", n, 20, 8, 3) == n * (16 * 3 + 24 * 3)
+    assert bench.batch_bytes("deep", n, 500, 1000, 1) == n * (8 + 32 * 63)
+    assert bench.batch_bytes("deep", n, 20, 8, 3) == n * (8 * 3 + 32 * 3)
     assert bench.batch_bytes("lean", n, 500, 500, 1) == n * (16 + 24 * 500)
     assert bench.batch_bytes("prev", n, 10, 10, 1) == n * (20 + 32 * 9 + 24)
     f = bench.fused_variant
