@@ -33,10 +33,57 @@ BYTES_PER_FISH = {
 PROFILE_EVERY = 8
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2507_20173_amd", "csrc", "fsb_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plain_n16777216.json")
+# Vector-ALU instructions per fish-iteration of the deep kernels, from a
+# committed SQ_INSTS_VALU counter summary (like the traffic above).
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_deep_forms.json")
+# Nominal vector-ALU issue rate of MI355X in lane instructions per second:
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, i.e. one wave64 instruction per SIMD
+# every four cycles (dual issue can exceed it).
+VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9
+# The deep kernels a counter run of the persistent forms launches, by school:
+# `bench.py --forms fused,registers --fused-steps F` runs each school's timed
+# launch of F iterations in one of these instances.
+DEEP_COUNTER_KERNELS = {
+    "fused_deep_n67108864": ("fused_deep_kernel<4, true, 0u>", 1 << 26),
+    "fused_deep_n16777216": ("fused_deep_kernel<4, false, 0u>", 1 << 24),
+    "fused_deep_n2097152": ("fused_deep_kernel<8, false, 0u>", 1 << 21),
+}
+BATCH_DEEP_COUNTER_KERNEL = "batch_deep_kernel<256, 4, true, 8, 0u>"
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def valu_digest() -> str:
+    """Digest of the sources the deep kernels are built from."""
+    h = hashlib.sha256()
+    for name in ("fsb_kernels.hip", "fsb_batch.hip", "fsb_device.hpp", "fsb_sweep.hpp",
+                 "fsb_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2507_20173_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def valu_roofline(key: str, fish_iterations: float, kernel_s: float, path: str = VALU_FILE):
+    """The "alu" roofline of a deep form: its lane instructions (the committed
+    count per fish-iteration, if taken from the current sources) over its
+    event-timed kernel time, against the nominal issue rate."""
+    try:
+        with open(path) as fh:
+            v = json.load(fh)
+    except OSError:
+        return None
+    lane = v.get("lane_instructions_per_fish_iteration", {}).get(key)
+    if v.get("source_digest") != valu_digest() or lane is None or kernel_s <= 0:
+        return None
+    achieved = lane * fish_iterations / kernel_s
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANE_PEAK / 1e12,
+            "unit": "T lane-instructions/s", "frac": achieved / VALU_LANE_PEAK,
+            "lane_instructions_per_fish_iteration": lane,
+            "note": "SQ_INSTS_VALU per fish-iteration from " + os.path.relpath(path, ROOT) +
+                    "; peak = 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one wave64 VALU issue "
+                    "per SIMD per 4 cycles; dual issue can exceed it)"}
 
 
 def source_digest() -> str:
@@ -224,6 +271,7 @@ def fused_vs_plain(n: int, steps: int, label: str):
             out[key]["iterations_per_barrier"] = deep_depth(n)
             out[key]["lane_sums"] = ("binary64 accumulation of pairwise float32 group totals "
                                      "(not the compensated float32 lanes of the plain path)")
+            out[key]["roofline_alu"] = valu_roofline(f"fused_deep_n{n}", n * steps, kernel_s)
         if key == "fused" and steps >= 4:
             # per-iteration cost as the slope between a launch of steps/2 and one
             # of steps iterations (the launch and its prologue drop out)
@@ -538,6 +586,8 @@ def batched_form(n_schools: int, steps: int, probe_steps: int, baseline_schools:
         "algorithmic_bytes_per_fish_step": {"lean": 24, "prev": 32, "deep": 32 / BATCH_DEEP_DEPTH}[variant],
         "kernel_achieved_GBs": bytes_total / (ms / 1e3) / 1e9,
         "kernel_hbm_frac": bytes_total / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+        "roofline_alu": (valu_roofline("batch_deep_cfg5", total * steps, ms / 1e3)
+                         if variant == "deep" and n_schools == 4096 else None),
         "baseline_per_school_plain": {"schools": baseline_schools, "fish": base_fish,
                                       "value": base, "speedup_of_batched": value / base},
         "mean_max_delta_last_iteration": float(np.mean(mx)),
@@ -732,6 +782,31 @@ def ingest_counters(fetch_dir: str, write_dir: str, n_fish: int, out_path: str =
     return out
 
 
+def ingest_valu(fused_dir: str, batch_dir: str, fused_steps: int, batch_steps: int,
+                out_path: str = VALU_FILE) -> dict:
+    """Vector-ALU lane instructions per fish-iteration of the deep kernels from
+    two rocprofv3 --pmc SQ_INSTS_VALU runs: the persistent forms
+    (`--forms fused,registers --fused-steps fused_steps`) and the batched form
+    (`--forms batched --batch-steps batch_steps`).  Each kernel's timed launch
+    is its dispatch with the most instructions."""
+    from paper_2507_20173_amd.workloads import log_uniform_school_sizes
+    out = {"source_digest": valu_digest(), "fused_steps": fused_steps, "batch_steps": batch_steps,
+           "lane_instructions_per_fish_iteration": {}}
+    lanes = out["lane_instructions_per_fish_iteration"]
+    rows = _counter_rows(fused_dir, "SQ_INSTS_VALU")
+    for key, (name, n) in DEEP_COUNTER_KERNELS.items():
+        vals = [v for k, v in rows if name in k]
+        if vals:
+            lanes[key] = max(vals) * 64 / (n * fused_steps)
+    total = int(log_uniform_school_sizes(4096).sum())
+    vals = [v for k, v in _counter_rows(batch_dir, "SQ_INSTS_VALU") if BATCH_DEEP_COUNTER_KERNEL in k]
+    if vals:
+        lanes["batch_deep_cfg5"] = max(vals) * 64 / (total * batch_steps)
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -768,10 +843,20 @@ def main() -> int:
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the plain kernels' measured HBM traffic from two rocprofv3 "
                          "--pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
+    ap.add_argument("--ingest-valu", nargs=4,
+                    metavar=("FUSED_DIR", "BATCH_DIR", "FUSED_STEPS", "BATCH_STEPS"),
+                    help="write the deep kernels' VALU instructions per fish-iteration from "
+                         "two rocprofv3 --pmc SQ_INSTS_VALU runs and exit")
+    ap.add_argument("--valu-out", default=VALU_FILE,
+                    help="where --ingest-valu writes the instruction counts")
     args = ap.parse_args()
     if args.ingest_counters:
         print(json.dumps(ingest_counters(*args.ingest_counters, args.n_fish, args.traffic_out),
                          indent=1))
+        return 0
+    if args.ingest_valu:
+        fd, bd, fs, bs = args.ingest_valu
+        print(json.dumps(ingest_valu(fd, bd, int(fs), int(bs), args.valu_out), indent=1))
         return 0
     if args.gpus != 1:
         log(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "

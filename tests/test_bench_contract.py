@@ -1,7 +1,7 @@
 """bench.py's host logic: the one-GPU refusal, the counter ingestion that
-scales rocprofv3 FETCH_SIZE / WRITE_SIZE by a known-size copy, the digest
-that voids stale traffic figures, and (on a GPU) the shape of the JSON
-line."""
+scales rocprofv3 FETCH_SIZE / WRITE_SIZE by a known-size copy, the deep
+kernels' VALU instruction counts and their "alu" roofline, the digests that
+void stale figures, and (on a GPU) the shape of the JSON line."""
 import csv
 import json
 import os
@@ -60,6 +60,37 @@ def test_counter_ingestion_scales_by_the_copy(tmp_path):
     stale["source_digest"] = "0" * 16
     out.write_text(json.dumps(stale))
     assert bench.measured_traffic("swim_eval", n, str(out)) is None
+
+
+def test_valu_ingestion_and_roofline(tmp_path):
+    from paper_2507_20173_amd.workloads import log_uniform_school_sizes
+    n = 1 << 26
+    # the timed launch is each kernel's dispatch with the most instructions
+    fused = [("void fsb::fused_deep_kernel<4, true, 0u>(fsb::SchoolArgs, fsb::FusedArgs)", 100 * n * 20 / 64),
+             ("void fsb::fused_deep_kernel<4, true, 0u>(fsb::SchoolArgs, fsb::FusedArgs)", 1000.0),
+             ("void fsb::fused_deep_kernel<8, false, 0u>(fsb::SchoolArgs, fsb::FusedArgs)",
+              120 * (1 << 21) * 20 / 64)]
+    total = int(log_uniform_school_sizes(4096).sum())
+    batch = [("void fsb::batch_deep_kernel<256, 4, true, 8, 0u>(fsb::BatchArgs)", 110 * total * 16 / 64)]
+    _counter_csv(tmp_path / "f", "SQ_INSTS_VALU", fused)
+    _counter_csv(tmp_path / "b", "SQ_INSTS_VALU", batch)
+    out = tmp_path / "valu.json"
+    v = bench.ingest_valu(str(tmp_path / "f"), str(tmp_path / "b"), 20, 16, str(out))
+    lanes = v["lane_instructions_per_fish_iteration"]
+    assert lanes["fused_deep_n67108864"] == pytest.approx(100)
+    assert lanes["fused_deep_n2097152"] == pytest.approx(120)
+    assert lanes["batch_deep_cfg5"] == pytest.approx(110)
+    assert "fused_deep_n16777216" not in lanes
+    # 100 lane instructions per fish-iteration at the nominal rate
+    kernel_s = 100 * n * 10 / bench.VALU_LANE_PEAK
+    r = bench.valu_roofline("fused_deep_n67108864", n * 10, kernel_s, str(out))
+    assert r["bound"] == "alu" and r["frac"] == pytest.approx(1.0)
+    assert r["peak"] == pytest.approx(39.3216)
+    assert bench.valu_roofline("fused_deep_n16777216", n, 1.0, str(out)) is None
+    stale = json.loads(out.read_text())
+    stale["source_digest"] = "0" * 16
+    out.write_text(json.dumps(stale))
+    assert bench.valu_roofline("fused_deep_n67108864", n * 10, kernel_s, str(out)) is None
 
 
 def test_persistent_bytes_accounting():
