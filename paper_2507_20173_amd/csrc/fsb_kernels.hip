@@ -50,7 +50,7 @@ constexpr int kUnroll = 2;  // groups in flight per thread (persistent kernels)
 // swim block's max).
 constexpr uint32_t kSwimGridCap = 4096;
 constexpr uint32_t kFeedGridCap = 512;
-constexpr int kSwimUnroll = 2;
+constexpr int kSwimUnroll = 1;
 constexpr int kFeedUnroll = 1;
 
 __device__ __forceinline__ double* partial_slot(const SchoolArgs& a, uint32_t t, int k) {
