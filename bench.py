@@ -172,7 +172,7 @@ def run_form(n: int, steps: int, mode: int, warmup: int = 2, swim_rule: int = 0)
 REGS_MAX_FISH = 4 * 4 * 512 * 256 + 3
 
 
-DEEP_WIDE_FISH = 1 << 23  # above this the single-school deep kernel runs four iterations per barrier
+DEEP_WIDE_FISH = 5 << 20  # above this the single-school deep kernel runs four iterations per barrier
 BATCH_DEEP_DEPTH = 8  # iterations per grid barrier of the batched deep kernel
 
 

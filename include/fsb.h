@@ -109,7 +109,7 @@ extern "C" {
                                  their maxima are known; each swim is computed twice,
                                  32 B per fish per barrier (x, y, w and cur read and
                                  written).  8 iterations per barrier (4 B per
-                                 fish-iteration) for schools of up to 2^23 fish, 4
+                                 fish-iteration) for schools of up to 5 x 2^20 fish, 4
                                  above (8 B per fish-iteration, in blocks that
                                  keep three waves per SIMD: faster there on MI355X);
                                  the environment variable FSB_DEEP_DEPTH, read once,

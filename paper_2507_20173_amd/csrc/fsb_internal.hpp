@@ -176,8 +176,8 @@ uint32_t fused_grid(uint64_t n, uint32_t resident);
 // ~230 registers per lane, so that instance runs 512-thread blocks (two waves
 // per SIMD); four need ~150, so those instances run 768-thread blocks, three
 // waves per SIMD, which hide more latency but barrier twice as often: the
-// faster choice above ~2^23 fish, measured on MI355X.
-constexpr uint64_t kDeepWideFish = 1ull << 23;
+// faster choice above ~5 x 2^20 fish, measured on MI355X.
+constexpr uint64_t kDeepWideFish = 5ull << 20;
 uint32_t deep_depth(uint64_t n);
 // Threads per block of the deep kernel of a depth.
 inline uint32_t deep_block(uint32_t depth) { return depth == 8 ? 512u : 768u; }

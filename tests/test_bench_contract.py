@@ -100,8 +100,8 @@ def test_persistent_bytes_accounting():
     assert bench.persistent_bytes("regs", n, 10) == n * 32
     assert bench.persistent_bytes("deep", n, 16) == n * (8 + 32 * 2)
     assert bench.persistent_bytes("deep", n, 17) == n * (8 + 32 * 3)
-    big = (1 << 23) + 4  # above 2^23 fish the single-school deep kernel runs four per barrier
-    assert bench.persistent_bytes("deep", 1 << 23, 16) == (1 << 23) * (8 + 32 * 2)
+    big = (1 << 23) + 4  # above 5 x 2^20 fish the single-school deep kernel runs four per barrier
+    assert bench.persistent_bytes("deep", 5 << 20, 16) == (5 << 20) * (8 + 32 * 2)
     assert bench.persistent_bytes("deep", big, 16) == big * (8 + 32 * 4)
     assert bench.fused_variant(1 << 26) == "deep"
     assert bench.batch_bytes("deep", n, 500, 1000, 1) == n * (8 + 32 * 63)
@@ -179,15 +179,16 @@ def test_drift_report_stays_within_the_rounding_bound():
 
 
 def test_deep_depth_follows_the_library_rule(monkeypatch):
-    """Eight iterations per barrier up to 2^23 fish, four above, unless
+    """Eight iterations per barrier up to 5 x 2^20 fish, four above, unless
     FSB_DEEP_DEPTH says 2, 4 or 8 (anything else is ignored), as
     include/fsb.h documents for FSB_RUN_FUSED_DEEP."""
     monkeypatch.delenv("FSB_DEEP_DEPTH", raising=False)
-    assert bench.deep_depth(1000) == 8 and bench.deep_depth(1 << 23) == 8
-    assert bench.deep_depth((1 << 23) + 1) == 4 and bench.deep_depth(1 << 26) == 4
+    assert bench.deep_depth(1000) == 8 and bench.deep_depth(5 << 20) == 8
+    assert bench.deep_depth((5 << 20) + 1) == 4 and bench.deep_depth(1 << 23) == 4
+    assert bench.deep_depth(1 << 26) == 4
     monkeypatch.setenv("FSB_DEEP_DEPTH", "2")
     assert bench.deep_depth(1 << 26) == 2 and bench.deep_depth(1000) == 2
     monkeypatch.setenv("FSB_DEEP_DEPTH", "3")
     assert bench.deep_depth(1 << 26) == 4
     header = open(os.path.join(os.path.dirname(__file__), "..", "include", "fsb.h")).read()
-    assert "2^23" in header
+    assert "5 x 2^20" in header

@@ -122,7 +122,7 @@ def test_deep_cfg4_full_size_prefix(torch_cuda, O):
 @pytest.mark.parametrize("n,steps", [((1 << 23) + 5, 41), (10_007, 2000), ((1 << 21) + 1, 100)])
 def test_deep_long_launch_ring_wraps(torch_cuda, O, n, steps):
     """One FSB_RUN_FUSED launch of many iterations, every record and the final
-    columns against the oracle: above 2^23 fish four iterations per barrier
+    columns against the oracle: above 5 x 2^20 fish four iterations per barrier
     in 768-thread blocks (41 iterations: the slot-t-mod-16 partials ring wraps
     twice), below eight per barrier (2000 iterations on 10^4 fish, as in the
     benchmark's launch length)."""
@@ -131,8 +131,18 @@ def test_deep_long_launch_ring_wraps(torch_cuda, O, n, steps):
               [(steps, fsb.FSB_RUN_FUSED)], f"long launch n={n}")
 
 
+@pytest.mark.parametrize("n", [5 << 20, (5 << 20) + 3])
+def test_deep_depth_boundary(torch_cuda, O, n):
+    """The schools on either side of the depth boundary (eight iterations per
+    barrier up to 5 x 2^20 fish, four above), over two supersteps and a
+    ragged one, every record and the final columns against the oracle."""
+    announce(f"depth boundary n={n}")
+    check_run(O, fsb.FsbConfig(n_fish=n, seed=515, history_len=19), [(19, DEEP)],
+              f"depth boundary n={n}")
+
+
 def test_deep_wide_school_several_supersteps(torch_cuda, O):
-    """Above 2^23 fish the library runs four iterations per barrier in
+    """Above 5 x 2^20 fish the library runs four iterations per barrier in
     768-thread blocks: supersteps of 4, 4 and 1, then interleaved with plain."""
     n = (1 << 23) + 5
     announce(f"wide n={n}")

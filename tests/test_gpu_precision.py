@@ -59,7 +59,7 @@ def test_cfg3_full_size_compensated_vs_naive(torch_cuda):
     assert comp.max() < naive.max()
 
 
-@pytest.mark.parametrize("n", [1 << 23, 1 << 26], ids=["2^23-eight-deep", "2^26-four-deep"])
+@pytest.mark.parametrize("n", [1 << 22, 1 << 26], ids=["2^22-eight-deep", "2^26-four-deep"])
 def test_deep_kernel_sums_are_compensated_grade(torch_cuda, n):
     """The deep kernel's lane sums (pairwise float4 group totals accumulated in
     binary64, binary64 wave and block merges) keep every iteration's sums at
