@@ -15,6 +15,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -56,13 +57,9 @@ def log(*a):
 
 
 def valu_digest() -> str:
-    """Digest of the sources the deep kernels are built from."""
-    h = hashlib.sha256()
-    for name in ("fsb_kernels.hip", "fsb_batch.hip", "fsb_device.hpp", "fsb_sweep.hpp",
-                 "fsb_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2507_20173_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    """Digest of the code the deep kernels are built from."""
+    return code_digest(_csrc("fsb_kernels.hip", "fsb_batch.hip", "fsb_device.hpp",
+                             "fsb_sweep.hpp", "fsb_internal.hpp"))
 
 
 def valu_roofline(key: str, fish_iterations: float, kernel_s: float, path: str = VALU_FILE):
@@ -86,13 +83,29 @@ def valu_roofline(key: str, fish_iterations: float, kernel_s: float, path: str =
                     "per SIMD per 4 cycles; dual issue can exceed it)"}
 
 
-def source_digest() -> str:
-    """Digest of the sources the plain kernels are built from."""
+def code_digest(paths) -> str:
+    """Digest of the code in the given source files: comments, trailing blanks
+    and blank lines are left out, so that rewording a comment does not void
+    figures measured on the code."""
     h = hashlib.sha256()
-    for name in ("fsb_kernels.hip", "fsb_device.hpp", "fsb_sweep.hpp", "fsb_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2507_20173_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+    for path in paths:
+        with open(path) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update("\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip()).encode())
+        h.update(b"\0")
     return h.hexdigest()[:16]
+
+
+def _csrc(*names):
+    return [os.path.join(ROOT, "paper_2507_20173_amd", "csrc", n) for n in names]
+
+
+def source_digest() -> str:
+    """Digest of the code the plain kernels are built from."""
+    return code_digest(_csrc("fsb_kernels.hip", "fsb_device.hpp", "fsb_sweep.hpp",
+                             "fsb_internal.hpp"))
 
 
 def measured_traffic(kernel: str, n_fish: int, path: str = TRAFFIC_FILE):

@@ -23,10 +23,11 @@
 // folds its |diff| into one shared max word and its three terms into three
 // shared float32 sums with its own device-scope atomic, the way a critical
 // section entered once per fish serialises the update; no tree at all.
-// No kernel reads cur: a fish's objective is the distance of its position,
-// so it is recomputed from (x, y) with the same binary32 operations that
-// produced the stored value (the state after every iteration satisfies
-// cur == sqrtf(x*x + y*y)); cur is only written.
+// No kernel reads a cur it has not written in the same launch: a fish's
+// objective is the distance of its position, so it is recomputed from (x, y)
+// with the same binary32 operations that produced the stored value (the state
+// after every iteration satisfies cur == sqrtf(x*x + y*y)); only the deep
+// kernels read cur back, between their own supersteps.
 // Records are combined in a fixed order, so every sum is deterministic for a
 // given launch shape.  Each thread handles groups of four consecutive fish
 // (one float4 per column): two Philox calls, for fish pairs 2g and 2g+1.
@@ -292,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(SchoolArgs a, uint32_t 
 // Plain swim pass.
 // ---------------------------------------------------------------------------
 // Cache policy of the plain passes (chosen on the host from the footprint).
-// cur is write-only and always streamed.  kCached keeps x, y, prev and w in
+// cur is only written by these passes, and always streamed.  kCached keeps x, y, prev and w in
 // the last-level cache, kStreamW streams w too (touched by the feed pass
 // alone) so x, y, prev stay resident, and kStreamAll streams every column
 // once even those three cannot fit.

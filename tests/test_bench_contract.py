@@ -62,6 +62,16 @@ def test_counter_ingestion_scales_by_the_copy(tmp_path):
     assert bench.measured_traffic("swim_eval", n, str(out)) is None
 
 
+def test_code_digest_ignores_comments(tmp_path):
+    src = tmp_path / "k.hip"
+    src.write_text("int f(int a) {\n  return a + 1;  // one more\n}\n")
+    d0 = bench.code_digest([str(src)])
+    src.write_text("/* a kernel */\nint f(int a) {\n\n  return a + 1;   // plus one\n}\n")
+    assert bench.code_digest([str(src)]) == d0
+    src.write_text("int f(int a) {\n  return a + 2;  // one more\n}\n")
+    assert bench.code_digest([str(src)]) != d0
+
+
 def test_valu_ingestion_and_roofline(tmp_path):
     from paper_2507_20173_amd.workloads import log_uniform_school_sizes
     n = 1 << 26
