@@ -165,6 +165,14 @@ static void swim_drawn(const Config *cfg, Fish *f, uint64_t fish, uint64_t t)
     swim_fish(cfg, f, dx, dy);
 }
 
+/* One fish's weight update of eat(): its objective change over the school's
+ * maximum, kept within the weight limits (maxDiff > 0). */
+static void feed_fish(const Config *cfg, Fish *f, float maxDiff)
+{
+    float diff = f->prevObjective - f->currentObjective;
+    f->weight = clampf(f->weight + diff / maxDiff, cfg->weightMin, cfg->weightMax);
+}
+
 /* eat(): the school-wide max of |prevObjective - currentObjective|, then the
  * weight update normalised by it. */
 static float eat(const Config *cfg, Fish *school)
@@ -180,12 +188,8 @@ static float eat(const Config *cfg, Fish *school)
     }
     if (maxDiff > 0.0f) {
 #pragma omp parallel for schedule(static)
-        for (uint64_t i = 0; i < n; ++i) {
-            Fish *f = &school[i];
-            float diff = f->prevObjective - f->currentObjective;
-            f->weight = clampf(f->weight + diff / maxDiff, cfg->weightMin,
-                               cfg->weightMax);
-        }
+        for (uint64_t i = 0; i < n; ++i)
+            feed_fish(cfg, &school[i], maxDiff);
     }
     return maxDiff;
 }
@@ -277,6 +281,19 @@ int oracle_follow_fish(const Config *cfg, uint64_t fish, uint64_t t0,
         return -1;
     for (uint64_t t = t0; t < t1; ++t)
         swim_drawn(cfg, f, fish, t);
+    return 0;
+}
+
+int oracle_follow_fish_fed(const Config *cfg, uint64_t fish, uint64_t t0,
+                           uint64_t t1, const float *maxDiff, Fish *f)
+{
+    if (cfg->swimRule & ORACLE_SWIM_WEIGHTED)
+        return -1;
+    for (uint64_t t = t0; t < t1; ++t) {
+        swim_drawn(cfg, f, fish, t);
+        if (maxDiff[t - t0] > 0.0f)
+            feed_fish(cfg, f, maxDiff[t - t0]);
+    }
     return 0;
 }
 

@@ -129,6 +129,12 @@ void oracle_run(const Config *cfg, Fish *school, uint64_t t0, uint64_t nSteps,
  * at the start of t0. */
 int oracle_follow_fish(const Config *cfg, uint64_t fish, uint64_t t0,
                        uint64_t t1, Fish *f);
+/* The same fish with its weight fed as eat() feeds it (Sec. 2.3.2), given the
+ * school's maximum of every iteration, maxDiff[t1 - t0] (from a run of the
+ * whole school): a fish's weight depends on the rest of the school only
+ * through those maxima.  Returns -1 under the weighted rule, else 0. */
+int oracle_follow_fish_fed(const Config *cfg, uint64_t fish, uint64_t t0,
+                           uint64_t t1, const float *maxDiff, Fish *f);
 /* Exact-as-possible reference sums: each product of two binary32 values is
  * exact in binary64, summed with Neumaier's compensated summation. */
 void oracle_barycentre_sums(const Fish *school, uint64_t n, double sums[3],

@@ -106,6 +106,8 @@ class Oracle:
         lib.oracle_run.argtypes = [_P, _P, u64, u64, _P, _P, _P]
         lib.oracle_follow_fish.argtypes = [_P, u64, u64, u64, _P]
         lib.oracle_follow_fish.restype = ctypes.c_int
+        lib.oracle_follow_fish_fed.argtypes = [_P, u64, u64, u64, _P, _P]
+        lib.oracle_follow_fish_fed.restype = ctypes.c_int
         lib.oracle_barycentre_sums.argtypes = [_P, u64, _P, _P]
         lib.oracle_init_f64.argtypes = [_P, _P]
         lib.oracle_step_f64.argtypes = [_P, _P, u64, _P, _P]
@@ -188,6 +190,19 @@ class Oracle:
         f = np.array(state, dtype=FISH).reshape(1).copy()
         c = cfg.c()
         if self._lib.oracle_follow_fish(ctypes.byref(c), fish, t0, t1, _ptr(f)) != 0:
+            raise ValueError("under the weighted swim rule a fish cannot be followed alone")
+        return f[0]
+
+    def follow_fish_fed(self, cfg: Config, fish: int, t0: int, t1: int, state: np.ndarray,
+                        max_diff) -> np.ndarray:
+        """One fish's whole record after iterations t0..t1-1, its weight fed
+        with the given school maxima max_diff[t1 - t0] (eat(), Sec. 2.3.2)."""
+        f = np.array(state, dtype=FISH).reshape(1).copy()
+        m = np.ascontiguousarray(max_diff, dtype=np.float32)
+        if m.size != t1 - t0:
+            raise ValueError("one maximum per iteration")
+        c = cfg.c()
+        if self._lib.oracle_follow_fish_fed(ctypes.byref(c), fish, t0, t1, _ptr(m), _ptr(f)) != 0:
             raise ValueError("under the weighted swim rule a fish cannot be followed alone")
         return f[0]
 

@@ -550,11 +550,30 @@ def pin_f64_invariants(O):
             assert abs(got - ref) <= 1e-14 * np.abs(terms).sum(), f"f64 sums {got} vs {ref}"
 
 
+def pin_follow_fish_fed(O):
+    """One fish followed alone with the school's recorded maxima (eat(),
+    Sec. 2.3.2: a weight depends on the rest of the school only through the
+    maximum) ends with the record the whole school's run gives it, every
+    field, for every fish of a school, with the weight limits reached and
+    the zero-swim iteration (M = 0, weights kept) among them."""
+    for cfg, steps in ((Config(numFish=257, seed=31, weightMin=1.0, weightMax=1.3), 40),
+                       (Config(numFish=64, seed=5, swimStep=0.0), 3),
+                       (Config(numFish=129, seed=8, swimRule=1), 25)):
+        school = O.init(cfg)
+        start = school.copy()
+        m, _, _ = O.run(cfg, school, 0, steps)
+        for i in range(cfg.numFish):
+            f = O.follow_fish_fed(cfg, i, 0, steps, start[i], m)
+            for k in school.dtype.names:
+                assert np.float32(f[k]).view(np.uint32) == np.float32(school[i][k]).view(np.uint32), \
+                    f"fish {i} {k} of {cfg}"
+
+
 ALL_PINS = (pin_philox_matches_aten, pin_fish_word_layout, pin_unit_map_exhaustive,
             pin_philox_statistics, pin_worked_examples, pin_zero_swim,
             pin_uniform_weights_mean, pin_symmetric_school_exact, pin_init_stream,
             pin_swim_stream, pin_invariants, pin_exact_sums, pin_composition, pin_swim_rules,
-            pin_init_f64, pin_step_f64_drawn, pin_f64_invariants)
+            pin_init_f64, pin_step_f64_drawn, pin_f64_invariants, pin_follow_fish_fed)
 
 
 def run_all(O) -> list[str]:

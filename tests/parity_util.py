@@ -58,3 +58,21 @@ def assert_sums_close(got_sums, ref_sums, ref_abs, tol: float = REL_TOL, what: s
     err = sum_errors(got_sums, ref_sums, ref_abs)
     assert (err <= tol).all(), f"{what} sums {got_sums} vs {ref_sums}: errors {err}"
     return err
+
+
+def assert_sampled_fish(O, ocfg: Config, start: dict, got: dict, max_delta, sample,
+                        what: str = "") -> None:
+    """Every field of the sampled fish bit for bit against the oracle
+    following each fish alone from its starting record (start: columns at the
+    run's first iteration), fed with the run's recorded maxima (max_delta,
+    one per iteration): at sizes where the whole-school oracle would take
+    minutes, the fish's own arithmetic is still checked exactly."""
+    steps = len(max_delta)
+    for i in sample:
+        rec = np.zeros(1, FISH)
+        for k, f in FIELD_OF.items():
+            rec[f] = start[k][i]
+        f = O.follow_fish_fed(ocfg, int(i), 0, steps, rec[0], max_delta)
+        for k, fld in FIELD_OF.items():
+            g, e = np.float32(got[k][i]), np.float32(f[fld])
+            assert g.view(np.uint32) == e.view(np.uint32), f"{what} fish {i} {k}: {g!r} vs {e!r}"

@@ -11,7 +11,7 @@ import pytest
 import paper_2507_20173_amd as fsb
 from oracle.oracle import default
 from paper_2507_20173_amd.workloads import log_uniform_school_sizes, packed_starts, school_seeds
-from parity_util import assert_columns_equal, assert_sums_close, oracle_config
+from parity_util import assert_columns_equal, assert_sampled_fish, assert_sums_close, oracle_config
 
 pytestmark = pytest.mark.gpu
 DEEP = fsb.FSB_RUN_FUSED_DEEP
@@ -156,6 +156,41 @@ def test_deep_cfg5_full_shape(torch_cuda, O):
     check_against_oracle(O, b, steps, common,
                          schools=list(order[:4]) + list(order[2048:2050]) + [order[-1]],
                          what="cfg5 deep")
+    b.close()
+
+
+def test_deep_cfg5_full_length_sampled(torch_cuda, O):
+    """The batched benchmark run as it is timed: the 4096-school shape
+    (6.07e8 fish), 500 iterations in one graph launch at the tuning the
+    autotuner picks for it.  Every school's every maximum within the swim's
+    reach; in the largest, the median and the smallest schools, sampled fish
+    every field bit for bit against the oracle following each fish alone,
+    fed with that school's recorded maxima."""
+    import math
+    sizes = log_uniform_school_sizes(4096)
+    seeds = school_seeds(4096)
+    steps = 500
+    announce(f"cfg5 full length: {int(sizes.sum())} fish, {steps} iterations, one launch")
+    common = fsb.FsbConfig(n_fish=0, history_len=steps)
+    b = fsb.Batch(common, sizes, seeds)
+    order = np.argsort(sizes)
+    chosen = [int(order[-1]), int(order[-2]), int(order[2048]), int(order[0])]
+    start = {s: b.school_state(s) for s in chosen}
+    b.run(steps, fsb.tuning(256, 16, 1000, variant=DEEP, schedule=fsb.FSB_SCHED_DYNAMIC,
+                            chunk_tiles=4))
+    hist = [b.history(t) for t in range(steps)]
+    M = np.stack([h["max_delta"] for h in hist])  # [steps, schools]
+    assert (M > 0).all() and (M <= 0.1 * math.sqrt(2) + 1e-4).all()
+    assert all(np.array_equal(h["step_lo"], np.full(b.n, t)) for t, h in enumerate(hist))
+    rng = np.random.default_rng(5)
+    for s in chosen:
+        n = int(sizes[s])
+        got = b.school_state(s)
+        cfg = fsb.FsbConfig(n_fish=n, seed=int(seeds[s]))
+        sample = np.unique(np.concatenate([np.arange(min(n, 5)), n - 1 - np.arange(min(n, 5)),
+                                           rng.integers(0, n, 40)]))
+        assert_sampled_fish(O, oracle_config(cfg), start[s], got, M[:, s], sample,
+                            f"cfg5 full length school {s} ({n} fish)")
     b.close()
 
 

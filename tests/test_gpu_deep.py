@@ -9,7 +9,7 @@ import pytest
 
 import paper_2507_20173_amd as fsb
 from oracle.oracle import default
-from parity_util import assert_columns_equal, assert_sums_close, oracle_config
+from parity_util import assert_columns_equal, assert_sampled_fish, assert_sums_close, oracle_config
 
 pytestmark = pytest.mark.gpu
 DEEP = fsb.FSB_RUN_FUSED_DEEP
@@ -129,6 +129,34 @@ def test_deep_long_launch_ring_wraps(torch_cuda, O, n, steps):
     announce(f"long launch n={n} steps={steps}")
     check_run(O, fsb.FsbConfig(n_fish=n, seed=2024 + steps, history_len=steps),
               [(steps, fsb.FSB_RUN_FUSED)], f"long launch n={n}")
+
+
+def test_cfg4_full_length_sampled(torch_cuda, O):
+    """The persistent benchmark run as it is timed: N = 2^26, 2000 iterations
+    in one FSB_RUN_FUSED launch.  Sampled fish (the first and last groups and
+    random ones) every field bit for bit against the oracle following each
+    fish alone, fed with the run's recorded maxima; every maximum within the
+    swim's reach, the last one the largest |prev - cur| of the final columns,
+    and cur the distance of every final position."""
+    import math
+    n, steps = 1 << 26, 2000
+    announce(f"cfg4 full length N={n} T={steps}")
+    cfg = fsb.FsbConfig(n_fish=n, seed=0, history_len=steps)
+    sch = fsb.School(cfg)
+    start = {k: v.cpu().numpy() for k, v in sch.cols.items()}
+    sch.run(steps, fsb.FSB_RUN_FUSED)
+    got = sch.state()
+    h = sch.history(0, steps)
+    sch.close()
+    assert np.array_equal(h["step_lo"], np.arange(steps))
+    M = h["max_delta"]
+    assert (M > 0).all() and (M <= cfg.swim_step * math.sqrt(2) + 1e-4).all()
+    assert np.abs(got["prev"] - got["cur"]).max() == M[-1]
+    assert np.array_equal(got["cur"], np.sqrt(got["x"] * got["x"] + got["y"] * got["y"]))
+    assert (got["w"] >= cfg.w_min).all() and (got["w"] <= cfg.w_max).all()
+    rng = np.random.default_rng(2026)
+    sample = np.unique(np.concatenate([np.arange(8), n - 1 - np.arange(8), rng.integers(0, n, 112)]))
+    assert_sampled_fish(O, oracle_config(cfg), start, got, M, sample, "cfg4 full length")
 
 
 @pytest.mark.parametrize("n", [5 << 20, (5 << 20) + 3])

@@ -12,8 +12,8 @@ import pytest
 
 import oracle_pins
 import paper_2507_20173_amd as fsb
-from oracle.oracle import FISH, default
-from parity_util import (FIELD_OF, assert_columns_equal, assert_sums_close, columns_of,
+from oracle.oracle import default
+from parity_util import (assert_columns_equal, assert_sampled_fish, assert_sums_close, columns_of,
                          oracle_config)
 
 pytestmark = pytest.mark.gpu
@@ -110,8 +110,11 @@ def test_cfg2_full_size_prefix(torch_cuda, O):
 
 def test_cfg2_full_length_sampled(torch_cuda, O):
     """N = 2^24, 1000 iterations (the full benchmark run): swimming does not
-    depend on weights or other fish, so the oracle follows sampled fish one
-    by one; weights and maxima are checked through invariants."""
+    depend on weights or other fish, and a weight depends on the rest of the
+    school only through each iteration's maximum, so the oracle follows
+    sampled fish one by one, fed with the run's recorded maxima: every field
+    bit for bit.  The maxima themselves are checked through invariants (and
+    bit for bit against the whole-school oracle at smaller sizes)."""
     n, steps = 1 << 24, 1000
     announce(f"cfg2 N={n} T={steps} sampled")
     cfg = fsb.FsbConfig(n_fish=n, seed=0, history_len=steps)
@@ -120,17 +123,11 @@ def test_cfg2_full_length_sampled(torch_cuda, O):
     start = {k: v.cpu().numpy() for k, v in sch.cols.items()}
     sch.run(steps)
     got = sch.state()
+    hist = sch.history(0, steps)
     rng = np.random.default_rng(99)
     sample = np.unique(np.concatenate([[0, 1, 2, 3, n - 4, n - 3, n - 2, n - 1],
-                                       rng.integers(0, n, 56)]))
-    for i in sample:
-        rec = np.zeros(1, FISH)
-        for k, f in FIELD_OF.items():
-            rec[f] = start[k][i]
-        f = O.follow_fish(ocfg, int(i), 0, steps, rec[0])
-        for k in ("x", "y", "prev", "cur"):
-            assert got[k][i] == f[FIELD_OF[k]], f"fish {i} {k}"
-    hist = sch.history(0, steps)
+                                       rng.integers(0, n, 248)]))
+    assert_sampled_fish(O, ocfg, start, got, hist["max_delta"], sample, "cfg2 full length")
     assert (hist["max_delta"] > 0).all()
     assert (hist["max_delta"] <= cfg.swim_step * math.sqrt(2) + 1e-4).all()
     w = got["w"]

@@ -49,10 +49,10 @@ MUTANTS = [
     ("weighted_one_axis", "        dy = dy * mobility;\n    }\n    float x", "    }\n    float x"),
     ("signed_max", "float mag = fabsf(diff);", "float mag = diff;"),
     ("no_zero_guard", "if (maxDiff > 0.0f) {", "{"),
-    ("feed_sign_flip", "float diff = f->prevObjective - f->currentObjective;\n            f->weight",
-     "float diff = f->currentObjective - f->prevObjective;\n            f->weight"),
+    ("feed_sign_flip", "float diff = f->prevObjective - f->currentObjective;\n    f->weight = clampf(",
+     "float diff = f->currentObjective - f->prevObjective;\n    f->weight = clampf("),
     ("feed_not_normalised", "f->weight + diff / maxDiff", "f->weight + diff"),
-    ("no_weight_clamp", "f->weight = clampf(f->weight + diff / maxDiff, cfg->weightMin,\n                               cfg->weightMax);",
+    ("no_weight_clamp", "f->weight = clampf(f->weight + diff / maxDiff, cfg->weightMin, cfg->weightMax);",
      "f->weight = f->weight + diff / maxDiff;"),
     ("sums_before_feeding", "    float m = eat(cfg, school);\n    if (maxDiff)\n        *maxDiff = m;\n    if (sums || absSums)\n        oracle_barycentre_sums(school, cfg->numFish, sums, absSums);",
      "    if (sums || absSums)\n        oracle_barycentre_sums(school, cfg->numFish, sums, absSums);\n    float m = eat(cfg, school);\n    if (maxDiff)\n        *maxDiff = m;"),
@@ -64,6 +64,10 @@ MUTANTS = [
      "oracle_fish_words(cfg->seed, i, 0u, ORACLE_DOMAIN_INIT, &a, &b);\n        f->weight = lo + (hi - lo) * oracle_unit(a);"),
     ("init_prev_zero", "        f->prevObjective = f->currentObjective;\n    }\n}\n\n/* Move",
      "        f->prevObjective = 0.0f;\n    }\n}\n\n/* Move"),
+    # one fish followed with the school's maxima
+    ("fed_follow_wrong_max", "feed_fish(cfg, f, maxDiff[t - t0]);", "feed_fish(cfg, f, maxDiff[t1 - 1 - t]);"),
+    ("fed_follow_feeds_before_swim", "        swim_drawn(cfg, f, fish, t);\n        if (maxDiff[t - t0] > 0.0f)\n            feed_fish(cfg, f, maxDiff[t - t0]);",
+     "        if (maxDiff[t - t0] > 0.0f)\n            feed_fish(cfg, f, maxDiff[t - t0]);\n        swim_drawn(cfg, f, fish, t);"),
     # the binary64 drift variant
     ("init_f64_sign", "f->x = H * (2.0 * unit_f64(a) - 1.0);", "f->x = H * (1.0 - 2.0 * unit_f64(a));"),
     ("init_f64_same_word", "f->y = H * (2.0 * unit_f64(b) - 1.0);", "f->y = H * (2.0 * unit_f64(a) - 1.0);"),
