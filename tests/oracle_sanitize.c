@@ -69,6 +69,12 @@ static void school_case(uint64_t n, uint32_t rule)
     Fish f = b[n - 1];
     int rc = oracle_follow_fish(&c, n - 1, steps, steps + 3, &f);
     CHECK(rc == ((rule & ORACLE_SWIM_WEIGHTED) ? -1 : 0));
+    /* the last fish followed alone from its start, fed with the run's maxima */
+    Fish g;
+    oracle_init(&c, b);
+    g = b[n - 1];
+    rc = oracle_follow_fish_fed(&c, n - 1, 0, steps, m, &g);
+    CHECK(rc == ((rule & ORACLE_SWIM_WEIGHTED) ? -1 : 0));
     oracle_init_f64(&c, d);
     double md, sd[3];
     for (uint64_t t = 0; t < 3; ++t) oracle_step_f64(&c, d, t, &md, sd);
