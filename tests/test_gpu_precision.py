@@ -6,7 +6,7 @@ import pytest
 
 import paper_2507_20173_amd as fsb
 from oracle.oracle import default
-from parity_util import assert_columns_equal, oracle_config, sum_errors
+from parity_util import assert_columns_equal, assert_sampled_fish, oracle_config, sum_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -57,6 +57,39 @@ def test_cfg3_full_size_compensated_vs_naive(torch_cuda):
               f"naive {naive[t].max():.3e}", flush=True)
     assert (comp <= 1e-6).all(), comp
     assert comp.max() < naive.max()
+
+
+def test_cfg3_full_length_sampled(torch_cuda):
+    """The precision form as the benchmark times it: N = 2^27, 200 iterations
+    of per-iteration launches, compensated sums.  Sampled fish every field
+    bit for bit against the oracle following each fish alone with the run's
+    recorded maxima; the last iteration's three sums within the 1e-6 gate of
+    binary64 sums of the final columns (the per-fish products are exact in
+    binary64; numpy's pairwise sum adds at most ~27 roundings of 2^-53)."""
+    n, steps = 1 << 27, 200
+    print(f"[precision] full length N={n} steps={steps}", flush=True)
+    O = default()
+    cfg = fsb.FsbConfig(n_fish=n, seed=0, history_len=steps)
+    sch = fsb.School(cfg)
+    rng = np.random.default_rng(27)
+    sample = np.unique(np.concatenate([np.arange(4), n - 1 - np.arange(4), rng.integers(0, n, 56)]))
+    idx = torch_cuda.from_numpy(sample).to("cuda")
+    start = {k: v[idx].cpu().numpy() for k, v in sch.cols.items()}
+    sch.run(steps)
+    h = sch.history(0, steps)
+    got = sch.state()
+    sch.close()
+    local = {k: dict(zip(sample.tolist(), v)) for k, v in start.items()}
+    picked = {k: dict(zip(sample.tolist(), v[sample])) for k, v in got.items()}
+    assert_sampled_fish(O, oracle_config(cfg), local, picked, h["max_delta"], sample.tolist(),
+                        "cfg3 full length")
+    w = got["w"].astype(np.float64)
+    terms = [w, w * got["x"], w * got["y"]]
+    ref = [t.sum() for t in terms]
+    den = [np.abs(t).sum() for t in terms]
+    err = sum_errors([h["sum_w"][-1], h["sum_wx"][-1], h["sum_wy"][-1]], ref, den)
+    print(f"[precision] full length last iteration errors {err}", flush=True)
+    assert (err <= 1e-6).all(), err
 
 
 @pytest.mark.parametrize("n", [1 << 22, 1 << 26], ids=["2^22-eight-deep", "2^26-four-deep"])
