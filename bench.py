@@ -3,9 +3,11 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
 Workload: one school of N = 2^24 fish (x, y uniform in the 200x200 pond,
-weights in [1, 2], seed 0), advanced by per-iteration fsb_step launches (two
-streaming kernels per iteration).  A "step" is one FSB iteration over the
-whole school: swim, objective, max |diff|, feeding and barycentre sums.
+weights in [1, 2], seed 0), advanced by per-iteration launches
+(FSB_RUN_PLAIN: the swim pass of the first iteration, then one pipelined pass
+per iteration that feeds the previous iteration and swims this one, then the
+closing feed pass).  A "step" is one FSB iteration over the whole school:
+swim, objective, max |diff|, feeding and barycentre sums.
 `value` is fish-updates/s = N * K / wall time of K iterations, with the
 school resident in HBM.  Prints ONE JSON line on stdout.
 """
@@ -26,8 +28,32 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per fish of each plain kernel (float32 columns).
 BYTES_PER_FISH = {
     "swim_eval": 8 + 16,   # reads x, y; writes x, y, prev, cur
-    "feed_bary": 16 + 4,   # reads prev, w, x, y; writes w
+    "feed_bary": 16 + 4,   # reads prev, w, x, y; writes w (+4: cur, closing a pipelined run)
+    "feed_swim": 16 + 16,  # reads x, y, w, prev; writes x, y, w, prev
 }
+SPLIT_BYTES_PER_FISH_STEP = BYTES_PER_FISH["swim_eval"] + BYTES_PER_FISH["feed_bary"]
+
+
+def plain_launches(steps: int, split: bool) -> dict:
+    """Launches of each plain kernel in a run of `steps` iterations."""
+    if split or steps < 2:
+        return {"swim_eval": steps, "feed_bary": steps}
+    return {"swim_eval": 1, "feed_swim": steps - 1, "feed_bary": 1}
+
+
+def plain_kernel_bytes(kernel: str, split: bool) -> int:
+    """Bytes per fish of one launch of a plain kernel (the feed pass that
+    closes a pipelined run also writes cur)."""
+    return BYTES_PER_FISH[kernel] + (4 if kernel == "feed_bary" and not split else 0)
+
+
+def plain_bytes(n: int, steps: int, split: bool = False) -> int:
+    """Algorithmic bytes of a plain run of `steps` iterations: 44 B per
+    fish-iteration in two passes, or pipelined 24 B (first swim) + 32 B per
+    further iteration + 24 B (closing feed, cur included)."""
+    split = split or steps < 2
+    return n * sum(c * plain_kernel_bytes(k, split)
+                   for k, c in plain_launches(steps, split).items())
 # Every PROFILE_EVERY-th launch of each kernel is timed by HIP events inside
 # the timed region (the plain passes' launches record them themselves; the
 # persistent launches are bracketed by them).
@@ -122,36 +148,49 @@ def measured_traffic(kernel: str, n_fish: int, path: str = TRAFFIC_FILE):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def plain_run(n: int, steps: int, warmup: int):
+def plain_run(n: int, steps: int, warmup: int, split: bool = False):
+    """Wall time of `steps` plain iterations (FSB_RUN_PLAIN, or fsb_step's two
+    passes with split), and each kernel's event-timed duration and rate."""
     import torch
 
     import paper_2507_20173_amd as fsb
 
+    mode = fsb.FSB_RUN_PLAIN_SPLIT if split else fsb.FSB_RUN_PLAIN
     cfg = fsb.FsbConfig(n_fish=n, seed=0, history_len=1)
     sch = fsb.School(cfg)
-    sch.run(warmup)
+    sch.run(warmup, mode)
     sch.sync()
     fsb.fsb_profile_enable(sch.h, PROFILE_EVERY)
     fsb.fsb_kernel_times(sch.h)  # reset counters
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sch.run(steps)
+    sch.run(steps, mode)
     sch.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     counts, ms = fsb.fsb_kernel_times(sch.h)
     xy, sums = sch.barycentre()
     sch.close()
+    kinds = {"swim_eval": fsb.FSB_KERNEL_SWIM_EVAL, "feed_bary": fsb.FSB_KERNEL_FEED_BARY,
+             "feed_swim": fsb.FSB_KERNEL_FEED_SWIM}
     kernels = {}
-    for name, kind in (("swim_eval", fsb.FSB_KERNEL_SWIM_EVAL),
-                       ("feed_bary", fsb.FSB_KERNEL_FEED_BARY)):
-        c = int(counts[kind])
-        avg_s = ms[kind] / 1e3 / max(c, 1)
-        nbytes = BYTES_PER_FISH[name] * n
-        kernels[name] = {"launches": c, "avg_us": avg_s * 1e6,
+    for name, launches in plain_launches(steps, split).items():
+        c = int(counts[kinds[name]])
+        avg_s = ms[kinds[name]] / 1e3 / max(c, 1)
+        nbytes = plain_kernel_bytes(name, split or steps < 2) * n
+        kernels[name] = {"launches": launches, "timed_launches": c, "avg_us": avg_s * 1e6,
+                         "share_of_kernel_time": avg_s * launches,
                          "algorithmic_bytes_per_launch": nbytes,
                          "achieved_GBs": nbytes / avg_s / 1e9}
+    total = sum(k["share_of_kernel_time"] for k in kernels.values())
+    for k in kernels.values():
+        k["share_of_kernel_time"] /= total
     return wall, kernels, xy
+
+
+def dominant(kernels: dict) -> str:
+    """The kernel that takes most of a run's kernel time."""
+    return max(kernels, key=lambda k: kernels[k]["share_of_kernel_time"])
 
 
 def run_form(n: int, steps: int, mode: int, warmup: int = 2, swim_rule: int = 0):
@@ -290,11 +329,16 @@ def fused_vs_plain(n: int, steps: int, label: str):
             # of steps iterations (the launch and its prologue drop out)
             half, _, _ = run_form(n, steps // 2, mode)
             out[key]["slope_ms_per_step"] = (wall - half) / (steps - steps // 2) * 1e3
-    wp, cp, mp = run_form(n, steps, fsb.FSB_RUN_PLAIN)
-    out["plain"] = {"value": n * steps / wp, "ms_per_step": wp / steps * 1e3,
-                    "algorithmic_bytes_per_fish_step": sum(BYTES_PER_FISH.values()),
-                    "hbm_frac": sum(BYTES_PER_FISH.values()) * n * steps / wp / 1e9 / HBM_PEAK_GBS}
+    for key, split in (("plain", False), ("plain_split", True)):
+        wp, _, _ = run_form(n, steps, fsb.FSB_RUN_PLAIN_SPLIT if split else fsb.FSB_RUN_PLAIN)
+        nb = plain_bytes(n, steps, split)
+        out[key] = {"value": n * steps / wp, "ms_per_step": wp / steps * 1e3,
+                    "algorithmic_bytes_per_fish_step": nb / (n * steps),
+                    "hbm_frac": nb / wp / 1e9 / HBM_PEAK_GBS}
+    out["plain"]["launches"] = "pipelined: one per iteration (FSB_RUN_PLAIN)"
+    out["plain_split"]["launches"] = "two per iteration (fsb_step, FSB_RUN_PLAIN_SPLIT)"
     out["fused_speedup"] = out["fused"]["value"] / out["plain"]["value"]
+    out["fused_speedup_vs_split"] = out["fused"]["value"] / out["plain_split"]["value"]
     return out
 
 
@@ -426,7 +470,7 @@ def ablation_form(sizes, checked_steps: int, budget_s: float = 0.5):
     modes = (("tree_compensated", fsb.FSB_REDUCE_COMPENSATED),
              ("tree_f32_block_atomics", fsb.FSB_REDUCE_NAIVE_F32),
              ("critical_f32_fish_atomics", fsb.FSB_REDUCE_CRITICAL_F32))
-    out = {"workload": "construct ablation: one school, per-iteration launches, seed 0; "
+    out = {"workload": "construct ablation: one school, fsb_step's two passes per iteration, seed 0; "
                        "the three reductions of the school max and the barycentre sums",
            "error_definition": "max over the first iterations of |got - ref| / sum|terms| "
                                "(sum w, sum w*x, sum w*y); ref = binary64 sums of the columns"}
@@ -445,7 +489,8 @@ def ablation_form(sizes, checked_steps: int, budget_s: float = 0.5):
             fsb.fsb_kernel_times(sch.h)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            sch.run(steps)
+            # every mode on fsb_step's two passes (the critical one has no other)
+            sch.run(steps, fsb.FSB_RUN_PLAIN_SPLIT)
             sch.sync()
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
@@ -571,7 +616,7 @@ def batched_form(n_schools: int, steps: int, probe_steps: int, baseline_schools:
                                                                                 "prev")
     bytes_total = batch_bytes(variant, total, steps, K, launches)
 
-    # baseline: the first schools one by one, fsb_step per iteration
+    # baseline: the first schools one by one, one launch per iteration (FSB_RUN_PLAIN)
     base_fish, base_wall = 0, 0.0
     for i in range(baseline_schools):
         sch = fsb.School(fsb.FsbConfig(n_fish=int(sizes[i]), seed=int(seeds[i])))
@@ -760,6 +805,16 @@ def _counter_rows(directory: str, counter: str):
     return rows
 
 
+def plain_kernel_names(n: int) -> dict:
+    """The instances a default-configuration run launches for a school of n
+    fish (cache policy by footprint, as the library picks it): fsb_step's
+    swim and feed passes, and FSB_RUN_PLAIN's pipelined pass."""
+    pol = 0 if 16 * n <= INFINITY_CACHE_MIB << 20 else 1 if 12 * n <= INFINITY_CACHE_MIB << 20 else 2
+    return {"swim_eval": f"swim_eval_kernel<false, {pol}, false>",
+            "feed_bary": f"feed_bary_kernel<0, {pol}, false>",
+            "feed_swim": f"feed_swim_kernel<false, {pol}>"}
+
+
 def ingest_counters(fetch_dir: str, write_dir: str, n_fish: int, out_path: str = TRAFFIC_FILE) -> dict:
     """Per-launch HBM bytes of the plain kernels from a FETCH_SIZE run and a
     WRITE_SIZE run (KiB per dispatch), each scaled by what the same counter
@@ -777,13 +832,13 @@ def ingest_counters(fetch_dir: str, write_dir: str, n_fish: int, out_path: str =
             raise SystemExit(f"no calibration copy dispatches with {counter} in {d}")
         known_kib = COPY_REPS * COPY_FLOATS * 4 / 1024
         scale[counter] = known_kib / sum(copy)
-        for name in ("swim_eval_kernel", "feed_bary_kernel"):
+        for key, name in plain_kernel_names(n_fish).items():
             vals = [v for k, v in rows if name in k]
             if vals:
-                per.setdefault(name, {})[counter] = statistics.mean(vals)
+                per.setdefault(key, {})[counter] = statistics.mean(vals)
     out["copy_scale"] = scale
-    for name, key in (("swim_eval_kernel", "swim_eval"), ("feed_bary_kernel", "feed_bary")):
-        c = per.get(name, {})
+    for key in plain_kernel_names(n_fish):
+        c = per.get(key, {})
         if "FETCH_SIZE" in c and "WRITE_SIZE" in c:
             rd = c["FETCH_SIZE"] * scale["FETCH_SIZE"] * 1024
             wr = c["WRITE_SIZE"] * scale["WRITE_SIZE"] * 1024
@@ -886,7 +941,7 @@ def main() -> int:
         calibrate_copy()
     wall, kernels, xy = plain_run(n, args.steps, args.warmup)
     value = n * args.steps / wall
-    dom = max(kernels, key=lambda k: kernels[k]["avg_us"])
+    dom = dominant(kernels)
     dk = kernels[dom]
     traffic = measured_traffic(dom, n)
     residency = cache_residency(n)
@@ -904,8 +959,9 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"plain FSB, one school: N=2^{n.bit_length() - 1} fish, "
-                               f"{args.steps} iterations, per-iteration fsb_step launches "
-                               "(swim pass + feed pass)",
+                               f"{args.steps} iterations, one kernel launch per iteration "
+                               "(FSB_RUN_PLAIN: the feed of iteration t-1 pipelined into the "
+                               "swim of t; a swim pass first, a feed pass last)",
                    "n_fish": n, "iterations": args.steps, "seed": 0, "mode": "plain",
                    "infinity_cache": residency},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk["achieved_GBs"],
@@ -918,25 +974,35 @@ def main() -> int:
                              "it: see roofline_hbm_resident for the same kernels from HBM"
                      if residency["live_columns_fit"] else "columns exceed the Infinity Cache"},
         "kernels": kernels,
-        "hbm_frac_whole_step": (sum(BYTES_PER_FISH.values()) * n * args.steps / wall / 1e9)
-        / HBM_PEAK_GBS,
+        "algorithmic_bytes_per_fish_step": plain_bytes(n, args.steps) / (n * args.steps),
+        "hbm_frac_whole_step": plain_bytes(n, args.steps) / wall / 1e9 / HBM_PEAK_GBS,
     }
+    # the same iterations as fsb_step's two passes (44 B per fish-iteration)
+    wall_s, kernels_s, _ = plain_run(n, args.steps, args.warmup, split=True)
+    line["plain_split"] = {
+        "value": n * args.steps / wall_s, "ms_per_step": wall_s / args.steps * 1e3,
+        "algorithmic_bytes_per_fish_step": SPLIT_BYTES_PER_FISH_STEP,
+        "hbm_frac_whole_step": plain_bytes(n, args.steps, True) / wall_s / 1e9 / HBM_PEAK_GBS,
+        "kernels": kernels_s, "pipelined_speedup": value / (n * args.steps / wall_s)}
     if args.hbm_companion_fish:
         # the same passes on a school whose columns cannot stay in the 256 MiB
         # Infinity Cache: every byte comes from HBM
         n_hbm = args.hbm_companion_fish
         hbm_steps = min(args.steps, 200)
         wall_h, kernels_h, _ = plain_run(n_hbm, hbm_steps, min(args.warmup, 5))
-        dom_h = max(kernels_h, key=lambda k: kernels_h[k]["avg_us"])
+        dom_h = dominant(kernels_h)
+        wall_hs, kernels_hs, _ = plain_run(n_hbm, hbm_steps, min(args.warmup, 5), split=True)
         line["roofline_hbm_resident"] = {
             "bound": "hbm", "kernel": dom_h, "n_fish": n_hbm, "iterations": hbm_steps,
             "achieved": kernels_h[dom_h]["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": kernels_h[dom_h]["achieved_GBs"] / HBM_PEAK_GBS,
-            "swim_frac": kernels_h["swim_eval"]["achieved_GBs"] / HBM_PEAK_GBS,
-            "feed_frac": kernels_h["feed_bary"]["achieved_GBs"] / HBM_PEAK_GBS,
-            "whole_step_frac": sum(BYTES_PER_FISH.values()) * n_hbm * hbm_steps / wall_h / 1e9
-            / HBM_PEAK_GBS,
+            "whole_step_frac": plain_bytes(n_hbm, hbm_steps) / wall_h / 1e9 / HBM_PEAK_GBS,
             "ms_per_step": wall_h / hbm_steps * 1e3, "kernels": kernels_h,
+            "split": {"swim_frac": kernels_hs["swim_eval"]["achieved_GBs"] / HBM_PEAK_GBS,
+                      "feed_frac": kernels_hs["feed_bary"]["achieved_GBs"] / HBM_PEAK_GBS,
+                      "whole_step_frac": plain_bytes(n_hbm, hbm_steps, True) / wall_hs / 1e9
+                      / HBM_PEAK_GBS,
+                      "ms_per_step": wall_hs / hbm_steps * 1e3, "kernels": kernels_hs},
             "infinity_cache": cache_residency(n_hbm)}
     forms = set() if args.plain_only else set(args.forms.split(","))
     line["forms"] = {}

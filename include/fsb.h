@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define FSB_ABI_VERSION 1
+#define FSB_ABI_VERSION 2
 
 /* Return codes. */
 #define FSB_OK 0
@@ -91,7 +91,13 @@ extern "C" {
                                 w_init_lo > 0 */
 
 /* fsb_run modes. */
-#define FSB_RUN_PLAIN 0u      /* one fsb_step (two kernels) per iteration */
+#define FSB_RUN_PLAIN 0u      /* one launch per iteration: for n_steps >= 2 the swim
+                                 pass of the first iteration, then one pipelined pass per
+                                 further iteration t that feeds t - 1 and swims t (x, y,
+                                 w, prev read and written once: 32 B per fish-iteration,
+                                 cur left unwritten), then the feed pass of the last
+                                 iteration, which also writes cur.  n_steps = 1 and
+                                 FSB_REDUCE_CRITICAL_F32 take FSB_RUN_PLAIN_SPLIT */
 #define FSB_RUN_FUSED 1u      /* one persistent launch; the library picks a variant below:
                                  deep whenever it can run, else registers for a school
                                  they hold, else store-prev or lean by footprint */
@@ -116,6 +122,8 @@ extern "C" {
                                  may force 2, 4 or 8.
                                  FSB_ERR_UNSUPPORTED under the weighted swim rule or a
                                  reduce_mode other than FSB_REDUCE_COMPENSATED */
+#define FSB_RUN_PLAIN_SPLIT 6u /* fsb_step n_steps times: two kernels per iteration
+                                  (swim pass 24 B per fish, feed pass 20 B) */
 
 typedef struct fsb_config {
     uint64_t n_fish;      /* fish in the school, >= 1 */
@@ -231,8 +239,10 @@ int fsb_step(fsb_school *h);
 
 /* n_steps iterations of the simulation loop (Sec. 2.1.3: the total
  * iteration count is a Config parameter; each iteration swims every fish,
- * Sec. 2.1.2, then runs eat(), Sec. 2.3.2).  FSB_RUN_PLAIN issues fsb_step
- * n_steps times;
+ * Sec. 2.1.2, then runs eat(), Sec. 2.3.2).  FSB_RUN_PLAIN_SPLIT issues
+ * fsb_step n_steps times; FSB_RUN_PLAIN launches one kernel per iteration,
+ * the feed of each iteration fused into the swim of the next (the columns are
+ * complete once the run's last kernel has finished, as for every mode);
  * the FSB_RUN_FUSED* modes run them in one persistent launch with a grid
  * barrier per iteration (per 4 or 8 iterations for FSB_RUN_FUSED_DEEP).  All give
  * bit-identical columns and maxima (the sums agree to
@@ -412,7 +422,8 @@ int fsb_run_static(const fsb_config *cfg, fsb_state state, uint64_t t,
 #define FSB_KERNEL_FEED_BARY 1 /* plain pass 2: feeding, barycentre sums */
 #define FSB_KERNEL_FUSED 2     /* persistent multi-iteration kernel */
 #define FSB_KERNEL_INIT 3
-#define FSB_KERNEL_KINDS 4
+#define FSB_KERNEL_FEED_SWIM 4 /* FSB_RUN_PLAIN's pipelined pass: feed of t - 1, swim of t */
+#define FSB_KERNEL_KINDS 5
 int fsb_profile_enable(fsb_school *h, int every);
 int fsb_kernel_times(fsb_school *h, uint64_t counts[FSB_KERNEL_KINDS],
                      double ms[FSB_KERNEL_KINDS]);

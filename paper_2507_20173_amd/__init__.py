@@ -13,11 +13,11 @@ import dataclasses
 import numpy as np
 
 from . import _lib
-from ._lib import (FSB_KERNEL_FEED_BARY, FSB_KERNEL_FUSED, FSB_KERNEL_INIT,  # noqa: F401
-                   FSB_KERNEL_KINDS, FSB_KERNEL_SWIM_EVAL, FSB_REDUCE_COMPENSATED,
+from ._lib import (FSB_KERNEL_FEED_BARY, FSB_KERNEL_FEED_SWIM, FSB_KERNEL_FUSED,  # noqa: F401
+                   FSB_KERNEL_INIT, FSB_KERNEL_KINDS, FSB_KERNEL_SWIM_EVAL, FSB_REDUCE_COMPENSATED,
                    FSB_REDUCE_CRITICAL_F32, FSB_REDUCE_NAIVE_F32, FSB_RUN_FUSED,
                    FSB_RUN_FUSED_DEEP, FSB_RUN_FUSED_LEAN, FSB_RUN_FUSED_PREV,
-                   FSB_RUN_FUSED_REGS, FSB_RUN_PLAIN,
+                   FSB_RUN_FUSED_REGS, FSB_RUN_PLAIN, FSB_RUN_PLAIN_SPLIT,
                    FSB_SCHED_DYNAMIC, FSB_SCHED_GUIDED, FSB_SCHED_STATIC, FSB_SWIM_GREEDY,
                    FSB_SWIM_WEIGHTED,
                    FsbError, check, lib)

@@ -32,12 +32,14 @@ FSB_RUN_FUSED_PREV = 2
 FSB_RUN_FUSED_LEAN = 3
 FSB_RUN_FUSED_REGS = 4
 FSB_RUN_FUSED_DEEP = 5
+FSB_RUN_PLAIN_SPLIT = 6
 
 FSB_KERNEL_SWIM_EVAL = 0
 FSB_KERNEL_FEED_BARY = 1
 FSB_KERNEL_FUSED = 2
 FSB_KERNEL_INIT = 3
-FSB_KERNEL_KINDS = 4
+FSB_KERNEL_FEED_SWIM = 4
+FSB_KERNEL_KINDS = 5
 
 
 class fsb_config(ctypes.Structure):

@@ -173,6 +173,7 @@ int do_step(fsb_school* h, const float* dx, const float* dy) {
     if (rc) return rc;
     h->pending = false;
     const uint32_t fgrid = feed_grid(h->cfg.n_fish);
+    s.combine = 0u;  // the swim pass wrote the pending record
     rc = timed_by_launch(h, FSB_KERNEL_FEED_BARY, "feed pass launch",
                          [&](hipEvent_t e0, hipEvent_t e1) {
                              return launch_feed_bary(h->args, s, fgrid, h->stream, e0, e1);
@@ -183,6 +184,70 @@ int do_step(fsb_school* h, const float* dx, const float* dy) {
     h->pending_grid = fgrid;
     h->t += 1;
     h->has_result = true;
+    return FSB_OK;
+}
+
+// FSB_RUN_PLAIN over n_steps >= 2 iterations, one launch per iteration: the
+// swim pass of the first, then for each next iteration t the pipelined pass
+// (feed of t - 1, swim of t), then the feed pass of the last, which also
+// stores cur.  Every launch first writes the record its predecessor left
+// pending.  The critical ablation keeps fsb_step's two passes.
+int run_plain(fsb_school* h, uint64_t n_steps) {
+    if (n_steps < 2 || h->cfg.reduce_mode == FSB_REDUCE_CRITICAL_F32) {
+        for (uint64_t k = 0; k < n_steps; ++k) {
+            int rc = do_step(h, nullptr, nullptr);
+            if (rc) return rc;
+        }
+        return FSB_OK;
+    }
+    const uint64_t n = h->cfg.n_fish;
+    StepArgs s{};
+    s.naive = h->cfg.reduce_mode != FSB_REDUCE_COMPENSATED;
+    auto pending_into = [&](StepArgs& a) {
+        a.combine = h->pending ? 1u : 0u;
+        a.prev_t = h->pending_t;
+        a.prev_grid = h->pending_grid;
+    };
+    const uint64_t t0 = h->t;
+    s.t = (uint32_t)t0;
+    s.swim_grid = plain_grid(n);
+    pending_into(s);
+    int rc = timed_by_launch(h, FSB_KERNEL_SWIM_EVAL, "swim pass launch",
+                             [&](hipEvent_t e0, hipEvent_t e1) {
+                                 return launch_swim_eval(h->args, s, h->stream, e0, e1);
+                             });
+    if (rc) return rc;
+    h->pending = false;
+    h->has_result = true;
+    uint32_t swum_by = s.swim_grid;  // grid whose block maxima the next launch reads
+    const uint32_t pgrid = pipe_grid(n);
+    for (uint64_t k = 1; k < n_steps; ++k) {
+        s.t = (uint32_t)(t0 + k);
+        s.swim_grid = swum_by;
+        pending_into(s);
+        rc = timed_by_launch(h, FSB_KERNEL_FEED_SWIM, "pipelined pass launch",
+                             [&](hipEvent_t e0, hipEvent_t e1) {
+                                 return launch_feed_swim(h->args, s, pgrid, h->stream, e0, e1);
+                             });
+        if (rc) return rc;
+        h->pending = true;
+        h->pending_t = (uint32_t)(t0 + k - 1);
+        h->pending_grid = pgrid;
+        swum_by = pgrid;
+    }
+    s.t = (uint32_t)(t0 + n_steps - 1);
+    s.swim_grid = swum_by;
+    pending_into(s);
+    const uint32_t fgrid = feed_grid(n);
+    rc = timed_by_launch(h, FSB_KERNEL_FEED_BARY, "feed pass launch",
+                         [&](hipEvent_t e0, hipEvent_t e1) {
+                             return launch_feed_bary(h->args, s, fgrid, h->stream, e0, e1, true);
+                         });
+    if (rc) return rc;
+    h->pending = true;
+    h->pending_t = s.t;
+    h->pending_grid = fgrid;
+    h->t = t0 + n_steps;
     return FSB_OK;
 }
 
@@ -341,9 +406,10 @@ int fsb_step_displaced(fsb_school* h, const float* dx, const float* dy) {
 
 int fsb_run(fsb_school* h, uint64_t n_steps, uint32_t mode) {
     if (!h) return fail(FSB_ERR_INVALID_ARG, "handle is NULL");
-    if (mode > FSB_RUN_FUSED_DEEP) return fail(FSB_ERR_INVALID_ARG, "unknown run mode");
+    if (mode > FSB_RUN_PLAIN_SPLIT) return fail(FSB_ERR_INVALID_ARG, "unknown run mode");
     if (n_steps > kStepLimit - h->t) return fail(FSB_ERR_INVALID_ARG, "iteration index would pass 2^32");
-    if (mode != FSB_RUN_PLAIN) return run_fused(h, n_steps, mode);
+    if (mode == FSB_RUN_PLAIN) return run_plain(h, n_steps);
+    if (mode != FSB_RUN_PLAIN_SPLIT) return run_fused(h, n_steps, mode);
     for (uint64_t k = 0; k < n_steps; ++k) {
         int rc = do_step(h, nullptr, nullptr);
         if (rc) return rc;
@@ -451,7 +517,7 @@ int fsb_run_static(const fsb_config* cfg, fsb_state state, uint64_t t, uint64_t 
     if (!aligned(records, alignof(fsb_record)))
         return fail(FSB_ERR_INVALID_ARG, "records is not 8-byte aligned");
     if (status && !aligned(status, 4)) return fail(FSB_ERR_INVALID_ARG, "status is not 4-byte aligned");
-    if (mode > FSB_RUN_FUSED_DEEP) return fail(FSB_ERR_INVALID_ARG, "unknown run mode");
+    if (mode > FSB_RUN_PLAIN_SPLIT) return fail(FSB_ERR_INVALID_ARG, "unknown run mode");
     if (t >= kStepLimit || n_steps > kStepLimit - t)
         return fail(FSB_ERR_INVALID_ARG, "iterations must stay below 2^32");
     if (kStaticLayout.total > kStaticScratchBytes)  // the layout is fixed; checked at compile time

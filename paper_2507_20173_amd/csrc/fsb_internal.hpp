@@ -53,7 +53,7 @@ constexpr uint32_t kSyncWords = kSyncSlots + 2 * kMaxDepth * kMaxBarrierBlocks;
 static_assert(2 * kMaxDepth <= kLineWords, "the publish words fit one line");
 
 // Workspace of one school:
-//   [Ctrl][history ring][block maxima u32 x kMaxGrid]
+//   [Ctrl][history ring][block maxima u32 x kMaxGrid x 2 (slot t & 1)]
 //   [block partials f64 x 3 x kMaxGrid x 2 (slot t & 1)][barrier sync area]
 //   [deep kernel's block partials f64 x 3 x kMaxBarrierBlocks x 2 kMaxDepth
 //    (slot t mod 2 kMaxDepth)]
@@ -69,7 +69,7 @@ constexpr Layout school_layout(uint32_t history_len) {
     L.ctrl = 0;
     L.hist = align_up(L.ctrl + sizeof(Ctrl), kAlign);
     L.blockmax = align_up(L.hist + (size_t)history_len * sizeof(fsb_record), kAlign);
-    L.partials = align_up(L.blockmax + kMaxGrid * sizeof(uint32_t), kAlign);
+    L.partials = align_up(L.blockmax + 2 * (size_t)kMaxGrid * sizeof(uint32_t), kAlign);
     L.sync = align_up(L.partials + 2 * 3 * (size_t)kMaxGrid * sizeof(double), kAlign);
     L.deep = align_up(L.sync + kSyncWords * sizeof(uint32_t), kAlign);
     L.total = align_up(L.deep + (size_t)kDeepSlots * 3 * kMaxBarrierBlocks * sizeof(double),
@@ -102,7 +102,8 @@ struct SchoolArgs {
     Ctrl *ctrl;
     fsb_record *hist;
     uint32_t hist_len;
-    uint32_t *blockmax;   // [kMaxGrid] per-block max |diff| bits of the swim pass
+    uint32_t *blockmax;   // [2][kMaxGrid] per-block max |diff| bits of the swim of iteration t,
+                          // slot t & 1
     double *partials;     // [2][3][kMaxGrid] per-block binary64 sums
     uint32_t *sync;       // [kSyncWords] persistent-kernel barrier words
     double *deep;         // [kDeepSlots][3][kMaxBarrierBlocks] the deep kernel's partials
@@ -111,7 +112,8 @@ struct SchoolArgs {
 // Step-specific arguments of the plain passes.
 struct StepArgs {
     uint32_t t;           // iteration index (low 32 bits; host keeps t < 2^32)
-    uint32_t swim_grid;   // blocks of the swim pass (feed pass reads that many maxima)
+    uint32_t swim_grid;   // blocks of the launch that swam the iteration being fed (the feed
+                          // reads that many maxima); the swim pass's own grid when it launches
     uint32_t combine;     // swim pass block 0 first writes the pending record
     uint32_t prev_t;      // iteration whose record is pending
     uint32_t prev_grid;   // blocks that produced its partials
@@ -155,13 +157,20 @@ float look_theta(uint64_t n);
 // status of the launch.
 uint32_t plain_grid(uint64_t n);  // swim pass (and init)
 uint32_t feed_grid(uint64_t n);   // feed pass
+uint32_t pipe_grid(uint64_t n);   // pipelined pass (feed of t - 1 and swim of t)
 hipError_t launch_reset(const SchoolArgs& a, hipStream_t stream);
 hipError_t launch_init(const SchoolArgs& a, float wlo, float whi, hipStream_t stream);
 // The plain passes; with a start and a stop event the launch records them
 // itself, around the kernel's own execution.
 hipError_t launch_swim_eval(const SchoolArgs& a, const StepArgs& s, hipStream_t stream,
                             hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+// The feed pass; write_cur also stores each fish's objective in cur (the
+// closing pass of a pipelined run, whose passes leave cur unwritten).
 hipError_t launch_feed_bary(const SchoolArgs& a, const StepArgs& s, uint32_t grid,
+                            hipStream_t stream, hipEvent_t start = nullptr,
+                            hipEvent_t stop = nullptr, bool write_cur = false);
+// The pipelined pass: feeds iteration s.t - 1 and swims iteration s.t.
+hipError_t launch_feed_swim(const SchoolArgs& a, const StepArgs& s, uint32_t grid,
                             hipStream_t stream, hipEvent_t start = nullptr,
                             hipEvent_t stop = nullptr);
 hipError_t launch_combine(const SchoolArgs& a, uint32_t t, uint32_t grid, uint32_t naive,

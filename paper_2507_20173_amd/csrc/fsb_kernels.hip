@@ -11,6 +11,17 @@
 //     accumulates sum w, sum w*x, sum w*y per lane in compensated float32,
 //     merges lanes with TwoSum and waves in binary64: one binary64 partial
 //     per block.
+// Pipelined plain iterations (a run of n >= 2 iterations, one launch each):
+//   swim pass of the first iteration, then for each next iteration t
+//   feed-swim pass (reads x, y, w, prev; writes x, y, w, prev; 32 B/fish)
+//     every block reduces the previous launch's block maxima to M_{t-1},
+//     feeds each fish with it, adds the fed weight and the position to
+//     iteration t-1's sums, then swims the fish for iteration t: prev_t is
+//     the objective of the position it swims from (cur of t-1, recomputed),
+//     so cur is not stored; each block stores its max |diff| of t.
+//   and the feed pass of the last iteration, which also writes cur.
+//   Block maxima and partials sit in slot t & 1, so a launch reads the
+//   previous launch's while it writes its own.
 // Persistent iteration (one cooperative launch for many iterations, one grid
 // barrier per iteration; 32 B/fish per iteration):
 //   prologue   swim t0 from (x, y), keep (x, y, prev), block max -> M_t0
@@ -51,11 +62,22 @@ constexpr int kUnroll = 2;  // groups in flight per thread (persistent kernels)
 // swim block's max).
 constexpr uint32_t kSwimGridCap = 4096;
 constexpr uint32_t kFeedGridCap = 512;
+// The pipelined pass runs the feed pass's grid: each iteration's sums then
+// come from the same lanes in the same order whichever pass feeds it, so a
+// pipelined run's records equal fsb_step's bit for bit.  It is also its
+// fastest grid (measured at N = 2^24 and 2^26: 256 blocks 27% and 17%
+// slower, 768 3% and 2%, 1024-4096 6-11%).
+constexpr uint32_t kPipeGridCap = kFeedGridCap;
 constexpr int kSwimUnroll = 1;
 constexpr int kFeedUnroll = 1;
 
 __device__ __forceinline__ double* partial_slot(const SchoolArgs& a, uint32_t t, int k) {
     return a.partials + ((size_t)(t & 1u) * 3 + k) * kMaxGrid;
+}
+
+// Per-block max |diff| bits of the swim of iteration t.
+__device__ __forceinline__ uint32_t* blockmax_slot(const SchoolArgs& a, uint32_t t) {
+    return a.blockmax + (size_t)(t & 1u) * kMaxGrid;
 }
 
 // The deep kernel's partials of iteration t: slot t mod kDeepSlots.
@@ -376,7 +398,7 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
     }
     if constexpr (!kCritical) {
         const uint32_t m = block_max(best);
-        if (threadIdx.x == 0) a.blockmax[blockIdx.x] = m;
+        if (threadIdx.x == 0) blockmax_slot(a, s.t)[blockIdx.x] = m;
     }
 }
 
@@ -387,40 +409,42 @@ __global__ __launch_bounds__(kBlock) void swim_eval_kernel(SchoolArgs a, StepArg
 // atomic per block, or critical (one atomic per fish, max and sums).
 constexpr int kRedCompensated = 0, kRedNaive = 1, kRedCritical = 2;
 
-template <int kRed, int kPolicy>
+// M of iteration t: the max of the `count` block maxima its swim stored (every
+// thread of the block gets it).  Four maxima per load, all loads of a thread
+// issued before any is used.
+__device__ __forceinline__ uint32_t school_max(const SchoolArgs& a, uint32_t t, uint32_t count) {
+    const uint32_t* bm = blockmax_slot(a, t);
+    const uint32_t n_vec = count / 4;
+    const uint4* bm4 = reinterpret_cast<const uint4*>(bm);
+    constexpr uint32_t kPer = kMaxGrid / 4 / kBlock;  // vector loads per thread, at most
+    uint4 v[kPer];
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+        const uint32_t i = threadIdx.x + j * kBlock;
+        v[j] = i < n_vec ? bm4[i] : make_uint4(0u, 0u, 0u, 0u);
+    }
+    uint32_t mb = 0u;
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) mb = max(mb, max(max(v[j].x, v[j].y), max(v[j].z, v[j].w)));
+    for (uint32_t b = 4 * n_vec + threadIdx.x; b < count; b += kBlock) mb = max(mb, bm[b]);
+    return block_max(mb);
+}
+
+// kWriteCur: also store each fish's objective in cur (the closing pass of a
+// pipelined run).  With s.combine, block 0 first writes the pending record.
+template <int kRed, int kPolicy, bool kWriteCur>
 __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArgs s) {
     constexpr bool NT = kPolicy == kStreamAll;
     constexpr bool NTW = kPolicy != kCached;
     constexpr bool kNaive = kRed != kRedCompensated;
-    __shared__ uint32_t M_bits;
-    // M = max over the swim pass's block maxima (critical mode: the shared word).
-    uint32_t mb = 0u;
-    if constexpr (kRed == kRedCritical) {
-        mb = a.ctrl->crit_max[s.t & 1u];
-    } else {
-        // every block reads the swim pass's block maxima: four per load, all
-        // loads of a thread issued before any is used
-        const uint32_t n_vec = s.swim_grid / 4;
-        const uint4* bm4 = reinterpret_cast<const uint4*>(a.blockmax);
-        constexpr uint32_t kPer = kMaxGrid / 4 / kBlock;  // vector loads per thread, at most
-        uint4 v[kPer];
-#pragma unroll
-        for (uint32_t j = 0; j < kPer; ++j) {
-            const uint32_t i = threadIdx.x + j * kBlock;
-            v[j] = i < n_vec ? bm4[i] : make_uint4(0u, 0u, 0u, 0u);
-        }
-#pragma unroll
-        for (uint32_t j = 0; j < kPer; ++j) mb = max(mb, max(max(v[j].x, v[j].y), max(v[j].z, v[j].w)));
-        for (uint32_t b = 4 * n_vec + threadIdx.x; b < s.swim_grid; b += kBlock)
-            mb = max(mb, a.blockmax[b]);
-        mb = block_max(mb);
-    }
-    if (threadIdx.x == 0) {
-        M_bits = mb;
-        if (blockIdx.x == 0) a.ctrl->last_max = mb;
-    }
-    __syncthreads();
-    const float M = __uint_as_float(M_bits);
+    if (s.combine && blockIdx.x == 0)
+        combine_block(a, s.prev_t, s.prev_grid, s.naive, a.ctrl->last_max);
+    // M = max over the swim's block maxima (critical mode: the shared word).
+    uint32_t mb;
+    if constexpr (kRed == kRedCritical) mb = a.ctrl->crit_max[s.t & 1u];
+    else mb = school_max(a, s.t, s.swim_grid);
+    if (threadIdx.x == 0 && blockIdx.x == 0) a.ctrl->last_max = mb;
+    const float M = __uint_as_float(mb);
 
     const float wmin = a.wmin, wmax = a.wmax;
     LaneSums<kNaive> ls;
@@ -455,29 +479,106 @@ __global__ __launch_bounds__(kBlock) void feed_bary_kernel(SchoolArgs a, StepArg
         for (int u = 0; u < kFeedUnroll; ++u) {
             const uint64_t g = g0 + u * stride;
             if (g >= n4) break;
-            float4 nw;
+            float4 nw, C;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const float c = distance(lane_of(X[u], k), lane_of(Y[u], k));
-                const float diff = lane_of(P[u], k) - c;
+                lane_of(C, k) = distance(lane_of(X[u], k), lane_of(Y[u], k));
+                const float diff = lane_of(P[u], k) - lane_of(C, k);
                 lane_of(nw, k) = feed(lane_of(W[u], k), diff, M, wmin, wmax);
                 if constexpr (kRed == kRedCritical) add(lane_of(nw, k), lane_of(X[u], k), lane_of(Y[u], k));
             }
             if constexpr (kRed != kRedCritical) ls.add4(nw, X[u], Y[u]);
             stv<NTW>(a.w, g, nw);
+            if constexpr (kWriteCur) stv<true>(a.cur, g, C);
         }
     }
     if (blockIdx.x == gridDim.x - 1) {
         const uint64_t i = 4 * n4 + threadIdx.x;
         if (i < a.n) {
             const float x = a.x[i], y = a.y[i];
-            const float diff = a.prev[i] - distance(x, y);
-            const float nw = feed(a.w[i], diff, M, wmin, wmax);
+            const float c = distance(x, y);
+            const float nw = feed(a.w[i], a.prev[i] - c, M, wmin, wmax);
             a.w[i] = nw;
+            if constexpr (kWriteCur) a.cur[i] = c;
             add(nw, x, y);
         }
     }
     if constexpr (kRed != kRedCritical) block_sums<kNaive>(a, ls, s.t);
+}
+
+// ---------------------------------------------------------------------------
+// Pipelined pass: the feed of iteration t - 1 and the swim of iteration t.
+// ---------------------------------------------------------------------------
+// Within a run, the feed of t - 1 and the swim of t touch each fish one after
+// the other, so one launch does both and the columns are read and written
+// once per iteration (x, y, w, prev: 32 B per fish) instead of twice.  Every
+// operation of a fish is the plain passes', in their order: the objective of
+// the position (cur of t - 1), the feed with M_{t-1}, the fed weight and the
+// position into iteration t-1's sums, then the swim of t from that position
+// (the weighted rule sees the fed weight, as the swim pass reads it).  The
+// objective swum from is prev_t; the new one is only compared with it, and
+// the run's closing feed pass stores cur from the final positions.
+template <bool kNaive, int kPolicy>
+__global__ __launch_bounds__(kBlock) void feed_swim_kernel(SchoolArgs a, StepArgs s) {
+    constexpr bool NT = kPolicy == kStreamAll;
+    constexpr bool NTW = kPolicy != kCached;
+    const uint32_t tf = s.t - 1u;  // iteration fed
+    if (s.combine && blockIdx.x == 0)
+        combine_block(a, s.prev_t, s.prev_grid, s.naive, a.ctrl->last_max);
+    const uint32_t mb = school_max(a, tf, s.swim_grid);
+    if (threadIdx.x == 0 && blockIdx.x == 0) a.ctrl->last_max = mb;
+    const float M = __uint_as_float(mb);
+
+    const float H = a.H, wmin = a.wmin, wmax = a.wmax;
+    const SwimRule rule{a.rule, a.wmin};
+    LaneSums<kNaive> ls;
+    uint32_t best = 0u;
+    const uint64_t n4 = a.n >> 2;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g < n4; g += stride) {
+        float4 X = ldv<NT>(a.x, g), Y = ldv<NT>(a.y, g);
+        float4 W = ldv<NTW>(a.w, g), P = ldv<NT>(a.prev, g);
+        float dx[4], dy[4];
+        group_draws(a.S, a.k0, a.k1, g, s.t, dx, dy);
+        float4 C, nw;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            lane_of(C, k) = distance(lane_of(X, k), lane_of(Y, k));
+            lane_of(nw, k) = feed(lane_of(W, k), lane_of(P, k) - lane_of(C, k), M, wmin, wmax);
+        }
+        ls.add4(nw, X, Y);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float nc = swim(rule, lane_of(X, k), lane_of(Y, k), dx[k], dy[k], H,
+                                  lane_of(C, k), lane_of(nw, k));
+            best = max(best, mag_bits(lane_of(C, k) - nc));
+        }
+        stv<NT>(a.x, g, X);
+        stv<NT>(a.y, g, Y);
+        stv<NTW>(a.w, g, nw);
+        stv<NT>(a.prev, g, C);
+    }
+    if (blockIdx.x == gridDim.x - 1) {
+        const uint64_t i = 4 * n4 + threadIdx.x;
+        if (i < a.n) {
+            float x = a.x[i], y = a.y[i];
+            const float c = distance(x, y);
+            const float nw = feed(a.w[i], a.prev[i] - c, M, wmin, wmax);
+            ls.add(nw, x, y);
+            float dx, dy;
+            fish_draw(a.S, a.k0, a.k1, i, s.t, dx, dy);
+            const float nc = swim(rule, x, y, dx, dy, H, c, nw);
+            best = max(best, mag_bits(c - nc));
+            a.x[i] = x;
+            a.y[i] = y;
+            a.w[i] = nw;
+            a.prev[i] = c;
+        }
+    }
+    block_sums<kNaive>(a, ls, tf);
+    __syncthreads();  // block_max's staging words were read by school_max
+    const uint32_t m = block_max(best);
+    if (threadIdx.x == 0) blockmax_slot(a, s.t)[blockIdx.x] = m;
 }
 
 // ---------------------------------------------------------------------------
@@ -1228,6 +1329,7 @@ static uint32_t capped_grid(uint64_t n, uint32_t cap) {
 
 uint32_t plain_grid(uint64_t n) { return capped_grid(n, kSwimGridCap); }
 uint32_t feed_grid(uint64_t n) { return capped_grid(n, kFeedGridCap); }
+uint32_t pipe_grid(uint64_t n) { return capped_grid(n, kPipeGridCap); }
 
 hipError_t launch_reset(const SchoolArgs& a, hipStream_t stream) {
     hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, stream, a.ctrl);
@@ -1261,12 +1363,24 @@ const void* swim_fn(int pol) {
     }
 }
 
-template <int kRed>
+template <int kRed, bool kWriteCur>
 const void* feed_fn(int pol) {
     switch (pol) {
-        case kCached: return reinterpret_cast<const void*>(feed_bary_kernel<kRed, kCached>);
-        case kStreamW: return reinterpret_cast<const void*>(feed_bary_kernel<kRed, kStreamW>);
-        default: return reinterpret_cast<const void*>(feed_bary_kernel<kRed, kStreamAll>);
+        case kCached:
+            return reinterpret_cast<const void*>(feed_bary_kernel<kRed, kCached, kWriteCur>);
+        case kStreamW:
+            return reinterpret_cast<const void*>(feed_bary_kernel<kRed, kStreamW, kWriteCur>);
+        default:
+            return reinterpret_cast<const void*>(feed_bary_kernel<kRed, kStreamAll, kWriteCur>);
+    }
+}
+
+template <bool kNaive>
+const void* feed_swim_fn(int pol) {
+    switch (pol) {
+        case kCached: return reinterpret_cast<const void*>(feed_swim_kernel<kNaive, kCached>);
+        case kStreamW: return reinterpret_cast<const void*>(feed_swim_kernel<kNaive, kStreamW>);
+        default: return reinterpret_cast<const void*>(feed_swim_kernel<kNaive, kStreamAll>);
     }
 }
 
@@ -1292,11 +1406,23 @@ hipError_t launch_swim_eval(const SchoolArgs& a, const StepArgs& s, hipStream_t 
 }
 
 hipError_t launch_feed_bary(const SchoolArgs& a, const StepArgs& s, uint32_t grid,
-                            hipStream_t stream, hipEvent_t start, hipEvent_t stop) {
+                            hipStream_t stream, hipEvent_t start, hipEvent_t stop,
+                            bool write_cur) {
     const int pol = plain_policy(a.n);
-    const void* fn = s.critical ? feed_fn<kRedCritical>(pol)
-                     : s.naive  ? feed_fn<kRedNaive>(pol)
-                                : feed_fn<kRedCompensated>(pol);
+    if (s.critical && write_cur) return hipErrorInvalidValue;  // critical runs never pipeline
+    const void* fn = s.critical ? feed_fn<kRedCritical, false>(pol)
+                     : s.naive  ? (write_cur ? feed_fn<kRedNaive, true>(pol)
+                                             : feed_fn<kRedNaive, false>(pol))
+                                : (write_cur ? feed_fn<kRedCompensated, true>(pol)
+                                             : feed_fn<kRedCompensated, false>(pol));
+    return launch_plain(fn, grid, a, s, stream, start, stop);
+}
+
+hipError_t launch_feed_swim(const SchoolArgs& a, const StepArgs& s, uint32_t grid,
+                            hipStream_t stream, hipEvent_t start, hipEvent_t stop) {
+    if (s.critical || s.dx || s.t == 0) return hipErrorInvalidValue;
+    const int pol = plain_policy(a.n);
+    const void* fn = s.naive ? feed_swim_fn<true>(pol) : feed_swim_fn<false>(pol);
     return launch_plain(fn, grid, a, s, stream, start, stop);
 }
 

@@ -55,9 +55,23 @@ def test_binding_covers_every_declared_symbol():
     assert set(declared()) <= set(_lib.PROTOTYPES)
 
 
+def test_binding_constants_match_the_header():
+    with open(HEADER) as fh:
+        text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+    consts = {m.group(1): int(m.group(2).strip("()").rstrip("u"), 0)
+              for m in re.finditer(r"^#define (FSB_\w+) (\(?-?\w+\)?)\s*$", text, re.M)
+              if not m.group(1).endswith("_H")}
+    assert "FSB_RUN_PLAIN_SPLIT" in consts and "FSB_KERNEL_FEED_SWIM" in consts
+    for name, value in consts.items():
+        if name == "FSB_ABI_VERSION":
+            assert _lib.lib().fsb_abi_version() == value
+        else:
+            assert getattr(_lib, name) == value, name
+
+
 def test_abi_version_and_strerror():
     lib = _lib.lib()
-    assert lib.fsb_abi_version() == 1
+    assert lib.fsb_abi_version() == 2
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.fsb_strerror(code)
     assert lib.fsb_strerror(-99) == b"unknown error code"
@@ -253,7 +267,7 @@ def test_run_static_rejects_before_any_hip_call(case):
     elif case == "misaligned_status":
         kw["status"] = FAKE + (17 << 20) + 2
     elif case == "bad_mode":
-        kw["mode"] = 6
+        kw["mode"] = _lib.FSB_RUN_PLAIN_SPLIT + 1
     elif case == "t_limit":
         kw["t"] = 1 << 32
     elif case == "steps_limit":

@@ -40,17 +40,22 @@ def test_counter_ingestion_scales_by_the_copy(tmp_path):
     fetch = [("__amd_rocclr_copyBuffer", copy_kib / 2 / bench.COPY_REPS)] * bench.COPY_REPS
     fetch += [("__amd_rocclr_copyBuffer", 0.5)]
     fetch += [("void fsb::swim_eval_kernel<false, 0, false>(...)", 8 * n / 1024 / 2)] * 3
-    fetch += [("void fsb::feed_bary_kernel<0, 0>(...)", 16 * n / 1024 / 2)] * 3
+    fetch += [("void fsb::feed_bary_kernel<0, 0, false>(...)", 16 * n / 1024 / 2)] * 3
+    fetch += [("void fsb::feed_swim_kernel<false, 0>(...)", 16 * n / 1024 / 2)] * 5
+    # a pipelined run's closing feed pass (it also writes cur) is not the split pass
+    fetch += [("void fsb::feed_bary_kernel<0, 0, true>(...)", 99 * n / 1024)]
     write = [("__amd_rocclr_copyBuffer", copy_kib / bench.COPY_REPS)] * bench.COPY_REPS
     write += [("void fsb::swim_eval_kernel<false, 0, false>(...)", 16 * n / 1024)] * 3
-    write += [("void fsb::feed_bary_kernel<0, 0>(...)", 4 * n / 1024)] * 3
+    write += [("void fsb::feed_bary_kernel<0, 0, false>(...)", 4 * n / 1024)] * 3
+    write += [("void fsb::feed_swim_kernel<false, 0>(...)", 16 * n / 1024)] * 5
+    write += [("void fsb::feed_bary_kernel<0, 0, true>(...)", 99 * n / 1024)]
     _counter_csv(tmp_path / "f", "FETCH_SIZE", fetch)
     _counter_csv(tmp_path / "w", "WRITE_SIZE", write)
     out = tmp_path / "traffic.json"
     t = bench.ingest_counters(str(tmp_path / "f"), str(tmp_path / "w"), n, str(out))
     assert t["copy_scale"]["FETCH_SIZE"] == pytest.approx(2.0)
     assert t["copy_scale"]["WRITE_SIZE"] == pytest.approx(1.0)
-    for k, per_fish in (("swim_eval", 24), ("feed_bary", 20)):
+    for k, per_fish in (("swim_eval", 24), ("feed_bary", 20), ("feed_swim", 32)):
         assert t["kernels"][k]["bytes_per_launch"] == pytest.approx(per_fish * n)
         assert t["kernels"][k]["algorithmic_bytes_per_launch"] == per_fish * n
     assert json.loads(out.read_text())["source_digest"] == bench.source_digest()
@@ -121,7 +126,14 @@ def test_persistent_bytes_accounting():
     f = bench.fused_variant
     assert f(1 << 21, False) == "regs" and f((1 << 21) + 4, False) == "prev"
     assert f(1 << 24, False) == "lean" and f(1 << 26, False) == "lean"
-    assert sum(bench.BYTES_PER_FISH.values()) == 44
+    assert bench.SPLIT_BYTES_PER_FISH_STEP == 44
+    # pipelined: swim pass 24 B, 32 B per further iteration, closing feed pass 24 B (cur too)
+    assert bench.plain_bytes(n, 1000) == n * (24 + 32 * 999 + 24)
+    assert bench.plain_bytes(n, 1000, split=True) == n * 44 * 1000
+    assert bench.plain_bytes(n, 1) == n * 44  # one iteration is fsb_step's two passes
+    assert bench.plain_launches(10, False) == {"swim_eval": 1, "feed_swim": 9, "feed_bary": 1}
+    assert bench.plain_kernel_names(1 << 24)["feed_swim"] == "feed_swim_kernel<false, 0>"
+    assert bench.plain_kernel_names(1 << 26)["swim_eval"] == "swim_eval_kernel<false, 2, false>"
 
 
 def test_cache_residency_flags():
@@ -173,10 +185,14 @@ def test_json_line_contract():
     assert cb["single_thread"]["value"] > 0 and cb["host"]["usable_cpus"] >= 1
     assert d["config"]["infinity_cache"]["columns_MiB"] == 320
     assert "20 iterations" in d["config"]["workload"]
+    assert rl["kernel"] == "feed_swim"
+    assert d["kernels"]["feed_swim"]["launches"] == 19
+    assert d["plain_split"]["value"] > 0 and d["algorithmic_bytes_per_fish_step"] < 44
     assert rl["cache_assisted"] is True
     hr = d["roofline_hbm_resident"]
     assert hr["n_fish"] == 1 << 26 and not hr["infinity_cache"]["live_columns_fit"]
-    assert 0 < hr["swim_frac"] < 1 and 0 < hr["feed_frac"] < 1
+    assert hr["kernel"] == "feed_swim" and 0 < hr["frac"] < 1
+    assert 0 < hr["split"]["swim_frac"] < 1 and 0 < hr["split"]["feed_frac"] < 1
     dr = cb["drift_f64"]
     assert dr["max_position_drift"] <= dr["position_bound_last_iteration"]
 
