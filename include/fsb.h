@@ -245,10 +245,14 @@ int fsb_step(fsb_school *h);
  * complete once the run's last kernel has finished, as for every mode);
  * the FSB_RUN_FUSED* modes run them in one persistent launch with a grid
  * barrier per iteration (per 4 or 8 iterations for FSB_RUN_FUSED_DEEP).  All give
- * bit-identical columns and maxima (the sums agree to
- * rounding; each mode is deterministic).  Asynchronous; FSB_ERR_UNSUPPORTED
- * if the fused grid cannot be co-resident, for FSB_RUN_FUSED_REGS on a
- * school too large for it, or for a fused mode under FSB_REDUCE_CRITICAL_F32. */
+ * bit-identical columns and maxima (the sums agree to rounding and, for
+ * FSB_RUN_PLAIN and FSB_RUN_PLAIN_SPLIT, are bit-identical too; each mode is
+ * deterministic).  Asynchronous; FSB_ERR_UNSUPPORTED if the fused grid cannot
+ * be co-resident, for FSB_RUN_FUSED_REGS on a school too large for it, or for
+ * a fused mode under FSB_REDUCE_CRITICAL_F32.  If the runtime refuses a launch
+ * part-way (FSB_ERR_HIP), the launches already enqueued still run, t is not
+ * advanced and the columns may hold a state between two iterations: attach a
+ * saved state (fsb_attach) or initialise again before going on. */
 int fsb_run(fsb_school *h, uint64_t n_steps, uint32_t mode);
 
 /* Test hook: one iteration with the displacements dx[n_fish], dy[n_fish]
