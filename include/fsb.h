@@ -250,9 +250,10 @@ int fsb_step(fsb_school *h);
  * deterministic).  Asynchronous; FSB_ERR_UNSUPPORTED if the fused grid cannot
  * be co-resident, for FSB_RUN_FUSED_REGS on a school too large for it, or for
  * a fused mode under FSB_REDUCE_CRITICAL_F32.  If the runtime refuses a launch
- * part-way (FSB_ERR_HIP), the launches already enqueued still run, t is not
- * advanced and the columns may hold a state between two iterations: attach a
- * saved state (fsb_attach) or initialise again before going on. */
+ * part-way (FSB_ERR_HIP), the launches already enqueued still run, and the
+ * columns may hold a state between two iterations that the handle's t does
+ * not describe: attach a saved state (fsb_attach) or initialise again before
+ * going on. */
 int fsb_run(fsb_school *h, uint64_t n_steps, uint32_t mode);
 
 /* Test hook: one iteration with the displacements dx[n_fish], dy[n_fish]
