@@ -88,6 +88,39 @@ def valu_digest() -> str:
                              "fsb_sweep.hpp", "fsb_internal.hpp"))
 
 
+# Plain-VALU ceilings measured by the probe kernels at the start of the run
+# (None until then, or when there is no GPU).
+MEASURED_VALU = None
+
+
+def valu_ceiling(waves_per_simd: int = 8, reps: int = 3) -> dict:
+    """Measured plain-VALU ceilings: fsb_valu_probe's independent chains of
+    v_fma_f32 and of Philox4x32-10 calls (v_mad_u64_u32 + v_bitop3_b32) on
+    every SIMD, `waves_per_simd` waves each; the best of `reps` launches."""
+    import torch
+
+    import paper_2507_20173_amd as fsb
+
+    blocks = 256 * waves_per_simd
+    buf = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
+    out = {"unit": "T lane-instructions/s", "waves_per_simd": waves_per_simd,
+           "nominal": VALU_LANE_PEAK / 1e12}
+    for name, kind, iters in (("fma", fsb.FSB_PROBE_FMA, 4096),
+                              ("philox", fsb.FSB_PROBE_PHILOX, 512)):
+        fsb.fsb_valu_probe(kind, blocks, 64, buf)
+        best = 0.0
+        for _ in range(reps):
+            ms, lanes = fsb.fsb_valu_probe(kind, blocks, iters, buf)
+            best = max(best, lanes / (ms / 1e3))
+        out[name] = best / 1e12
+    out["ceiling"] = max(out["fma"], out["philox"])
+    out["note"] = ("single-issue chains of one instruction kind; under such load the clock "
+                   "runs near 2.0-2.1 GHz, not 2.4 (GRBM_GUI_ACTIVE cycles per ns), and "
+                   "kernels mixing kinds can exceed it by dual issue")
+    del buf
+    return out
+
+
 def valu_roofline(key: str, fish_iterations: float, kernel_s: float, path: str = VALU_FILE):
     """The "alu" roofline of a deep form: its lane instructions (the committed
     count per fish-iteration, if taken from the current sources) over its
@@ -101,8 +134,11 @@ def valu_roofline(key: str, fish_iterations: float, kernel_s: float, path: str =
     if v.get("source_digest") != valu_digest() or lane is None or kernel_s <= 0:
         return None
     achieved = lane * fish_iterations / kernel_s
+    measured = MEASURED_VALU["ceiling"] * 1e12 if MEASURED_VALU else None
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANE_PEAK / 1e12,
             "unit": "T lane-instructions/s", "frac": achieved / VALU_LANE_PEAK,
+            "measured_ceiling": measured / 1e12 if measured else None,
+            "frac_of_measured_ceiling": achieved / measured if measured else None,
             "lane_instructions_per_fish_iteration": lane,
             "note": "SQ_INSTS_VALU per fish-iteration from " + os.path.relpath(path, ROOT) +
                     "; peak = 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one wave64 VALU issue "
@@ -939,6 +975,8 @@ def main() -> int:
     n = args.n_fish
     if args.calibrate_copy:
         calibrate_copy()
+    global MEASURED_VALU
+    MEASURED_VALU = valu_ceiling()
     wall, kernels, xy = plain_run(n, args.steps, args.warmup)
     value = n * args.steps / wall
     dom = dominant(kernels)
@@ -974,6 +1012,7 @@ def main() -> int:
                              "it: see roofline_hbm_resident for the same kernels from HBM"
                      if residency["live_columns_fit"] else "columns exceed the Infinity Cache"},
         "kernels": kernels,
+        "valu_ceiling": MEASURED_VALU,
         "algorithmic_bytes_per_fish_step": plain_bytes(n, args.steps) / (n * args.steps),
         "hbm_frac_whole_step": plain_bytes(n, args.steps) / wall / 1e9 / HBM_PEAK_GBS,
     }

@@ -18,6 +18,7 @@ from ._lib import (FSB_KERNEL_FEED_BARY, FSB_KERNEL_FEED_SWIM, FSB_KERNEL_FUSED,
                    FSB_REDUCE_CRITICAL_F32, FSB_REDUCE_NAIVE_F32, FSB_RUN_FUSED,
                    FSB_RUN_FUSED_DEEP, FSB_RUN_FUSED_LEAN, FSB_RUN_FUSED_PREV,
                    FSB_RUN_FUSED_REGS, FSB_RUN_PLAIN, FSB_RUN_PLAIN_SPLIT,
+                   FSB_PROBE_FMA, FSB_PROBE_KINDS, FSB_PROBE_PHILOX,
                    FSB_SCHED_DYNAMIC, FSB_SCHED_GUIDED, FSB_SCHED_STATIC, FSB_SWIM_GREEDY,
                    FSB_SWIM_WEIGHTED,
                    FsbError, check, lib)
@@ -281,6 +282,19 @@ def fsb_eval_sqrt(inp, out, stream=None) -> None:
     assert inp.numel() == out.numel() and inp.is_contiguous() and out.is_contiguous()
     s = torch.cuda.current_stream().cuda_stream if stream is None else stream
     check(lib().fsb_eval_sqrt(_ptr(inp), _ptr(out), inp.numel(), s))
+
+
+def fsb_valu_probe(kind: int, blocks: int, iters: int, out, stream=None) -> tuple[float, int]:
+    """(milliseconds, lane instructions) of one VALU ceiling probe launch;
+    out: a device tensor of at least blocks x 256 4-byte words."""
+    import torch
+    assert out.is_contiguous() and out.element_size() * out.numel() >= blocks * 256 * 4
+    s = torch.cuda.current_stream().cuda_stream if stream is None else stream
+    ms = ctypes.c_double()
+    lanes = ctypes.c_uint64()
+    check(lib().fsb_valu_probe(kind, blocks, iters, _ptr(out), out.element_size() * out.numel(),
+                               s, ctypes.byref(ms), ctypes.byref(lanes)))
+    return ms.value, lanes.value
 
 
 def fsb_batch_profile_enable(b, every: int = 1) -> None:

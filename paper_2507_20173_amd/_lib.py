@@ -40,6 +40,9 @@ FSB_KERNEL_FUSED = 2
 FSB_KERNEL_INIT = 3
 FSB_KERNEL_FEED_SWIM = 4
 FSB_KERNEL_KINDS = 5
+FSB_PROBE_FMA = 0
+FSB_PROBE_PHILOX = 1
+FSB_PROBE_KINDS = 2
 
 
 class fsb_config(ctypes.Structure):
@@ -120,6 +123,8 @@ PROTOTYPES = {
     "fsb_batch_profile_enable": (_I, [_P, _I]),
     "fsb_barrier_probe": (_I, [_P, _U32, _U32, _DP, ctypes.POINTER(_U32)]),
     "fsb_eval_sqrt": (_I, [_P, _P, _U64, _P]),
+    "fsb_valu_probe": (_I, [_U32, _U32, _U32, _P, ctypes.c_size_t, _P, _DP,
+                           ctypes.POINTER(_U64)]),
     "fsb_batch_kernel_times": (_I, [_P, ctypes.POINTER(_U64), _DP]),
 }
 

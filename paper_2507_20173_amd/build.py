@@ -26,7 +26,7 @@ DEVICE = [f"--offload-arch={ARCH}", "-ffp-contract=off",
           "-fhip-fp32-correctly-rounded-divide-sqrt",
           "-fno-gpu-flush-denormals-to-zero", "-munsafe-fp-atomics",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["fsb_kernels.hip", "fsb_batch.hip", "fsb_api.cpp", "fsb_batch_api.cpp"]
+SOURCES = ["fsb_kernels.hip", "fsb_batch.hip", "fsb_probe.hip", "fsb_api.cpp", "fsb_batch_api.cpp"]
 
 
 def _run(cmd):

@@ -13,6 +13,7 @@
 #include "fsb.h"
 #include "fsb_host.hpp"
 #include "fsb_internal.hpp"
+#include "fsb_probe.hpp"
 
 using namespace fsb;
 
@@ -585,6 +586,37 @@ int fsb_barrier_probe(fsb_school* h, uint32_t grid, uint32_t n_barriers, double*
                     "hipMemcpyDtoH");
     }
     *out_us = ms * 1e3 / (double)n_barriers;
+    return FSB_OK;
+}
+
+int fsb_valu_probe(uint32_t kind, uint32_t blocks, uint32_t iters, void* out, size_t out_bytes,
+                   void* stream, double* out_ms, uint64_t* out_lane_instructions) {
+    // Vector instructions per lane and round of each probe kind (the assembly
+    // of the probe kernels is checked for exactly these).
+    static const uint64_t per_round[FSB_PROBE_KINDS] = {8, 80};
+    if (kind >= FSB_PROBE_KINDS) return fail(FSB_ERR_INVALID_ARG, "unknown probe kind");
+    if (blocks == 0 || iters == 0) return fail(FSB_ERR_INVALID_ARG, "blocks and iters must be >= 1");
+    if (!out || !out_ms || !out_lane_instructions) return fail(FSB_ERR_INVALID_ARG, "NULL argument");
+    if (!aligned(out, 4)) return fail(FSB_ERR_INVALID_ARG, "out is not 4-byte aligned");
+    if (out_bytes < (size_t)blocks * kProbeThreads * 4)
+        return fail(FSB_ERR_INVALID_ARG, "out must hold blocks x 256 words");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = FSB_OK;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = launch_valu_probe(kind, blocks, iters, out, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) rc = hip_fail(e, "VALU probe");
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    *out_ms = ms;
+    *out_lane_instructions = (uint64_t)blocks * kProbeThreads * iters * per_round[kind];
     return FSB_OK;
 }
 

@@ -278,3 +278,30 @@ def test_run_static_rejects_before_any_hip_call(case):
         st = cols(cur=0)
     assert run_static(c, st, **kw) == _lib.FSB_ERR_INVALID_ARG
     assert _lib.lib().fsb_last_error()
+
+
+@pytest.mark.parametrize("case", ["kind", "blocks", "iters", "null_out", "small_out",
+                                  "misaligned_out", "null_results"])
+def test_valu_probe_rejects_before_any_hip_call(case):
+    """Every argument check of fsb_valu_probe runs on the host first."""
+    lib = _lib.lib()
+    ms, lanes = ctypes.c_double(), ctypes.c_uint64()
+    args = dict(kind=0, blocks=2, iters=1, out=FAKE, out_bytes=2 * 256 * 4,
+                ms=ctypes.byref(ms), lanes=ctypes.byref(lanes))
+    if case == "kind":
+        args["kind"] = _lib.FSB_PROBE_KINDS
+    elif case == "blocks":
+        args["blocks"] = 0
+    elif case == "iters":
+        args["iters"] = 0
+    elif case == "null_out":
+        args["out"] = None
+    elif case == "small_out":
+        args["out_bytes"] = 2 * 256 * 4 - 1
+    elif case == "misaligned_out":
+        args["out"] = FAKE + 2
+    elif case == "null_results":
+        args["ms"] = None
+    rc = lib.fsb_valu_probe(args["kind"], args["blocks"], args["iters"], args["out"],
+                            args["out_bytes"], None, args["ms"], args["lanes"])
+    assert rc == _lib.FSB_ERR_INVALID_ARG

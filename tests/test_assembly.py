@@ -8,7 +8,8 @@ operand modifier), and the deep kernels' look-ahead skip test fma(dx, dx,
 RN(dy * dy)), a bound on a move's length that feeds no fish's state (both
 multiplicands the same register, only in the deep kernels' plain-swim
 instances); and no packed-FP32 instruction is emitted, in the single-school and
-the batch kernels alike."""
+the batch kernels alike.  The VALU ceiling probes issue exactly the
+instructions per round that the library's rate assumes."""
 import re
 
 import pytest
@@ -19,7 +20,7 @@ from paper_2507_20173_amd import build as fsb_build
 @pytest.fixture(scope="module")
 def kernels():
     bodies, name = {}, None
-    for source in ("fsb_kernels.hip", "fsb_batch.hip"):
+    for source in ("fsb_kernels.hip", "fsb_batch.hip", "fsb_probe.hip"):
         text = open(fsb_build.assembly(source)).read()
         for line in text.splitlines():
             m = re.match(r"^(_Z\w+):", line)
@@ -59,6 +60,8 @@ def is_deep_plain_swim(name):
 def test_no_contraction_outside_sqrt_and_div(kernels):
     draws_seen = squares_seen = 0
     for name, body in kernels.items():
+        if "valu_probe_fma_kernel" in name:
+            continue  # instrumentation: explicit fma chains, no fish state
         fma = count(body, r"\bv_(fma|fmac|mac|mad)_f32|\bv_fma_mix")
         draws = count(body, DRAW_FMA)
         squares = count(body, SQUARE_FMA)
@@ -114,3 +117,35 @@ def test_grid_barrier_waits_for_every_waves_stores(kernels):
         waits = len(re.findall(r"s_waitcnt vmcnt\(0\)[^\n]*\n(?:[^\n]*\n){0,2}?\s*s_barrier\b",
                                body))
         assert waits >= (1 if "regs" in name else 2), f"{name}: {waits} barriers after a wait"
+
+
+def loop_blocks(body):
+    """Instruction mnemonics of each basic block that branches back to itself."""
+    blocks, cur = {}, None
+    for line in body.splitlines():
+        m = re.match(r"^(\.LBB\w+):", line)
+        if m:
+            cur = m.group(1)
+            blocks[cur] = []
+            continue
+        t = line.strip()
+        if cur and t and not t.startswith((";", ".")):
+            blocks[cur].append(t)
+    return {b: [t.split()[0] for t in ins] for b, ins in blocks.items()
+            if any(t.split()[0].startswith(("s_cbranch", "s_branch")) and t.split()[-1] == b
+                   for t in ins)}
+
+
+@pytest.mark.parametrize("kernel,per_round", [
+    ("valu_probe_fma_kernel", {"v_fma_f32": 8}),
+    ("valu_probe_philox_kernel", {"v_mad_u64_u32": 40, "v_bitop3_b32": 40}),
+])
+def test_valu_probe_loops(kernels, kernel, per_round):
+    """The probe's loop holds the vector instructions fsb_valu_probe counts
+    (FSB_PROBE_FMA 8, FSB_PROBE_PHILOX 80 per round) and no others."""
+    (body,) = [b for n, b in kernels.items() if kernel in n]
+    loops = loop_blocks(body)
+    assert len(loops) == 1, loops
+    (ins,) = loops.values()
+    vector = [i for i in ins if i.startswith("v_")]
+    assert {k: vector.count(k) for k in set(vector)} == per_round

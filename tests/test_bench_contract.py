@@ -101,6 +101,13 @@ def test_valu_ingestion_and_roofline(tmp_path):
     r = bench.valu_roofline("fused_deep_n67108864", n * 10, kernel_s, str(out))
     assert r["bound"] == "alu" and r["frac"] == pytest.approx(1.0)
     assert r["peak"] == pytest.approx(39.3216)
+    assert r["measured_ceiling"] is None and r["frac_of_measured_ceiling"] is None
+    bench.MEASURED_VALU = {"ceiling": 39.3216 / 1.25}
+    try:
+        r = bench.valu_roofline("fused_deep_n67108864", n * 10, kernel_s, str(out))
+        assert r["frac_of_measured_ceiling"] == pytest.approx(1.25)
+    finally:
+        bench.MEASURED_VALU = None
     assert bench.valu_roofline("fused_deep_n16777216", n, 1.0, str(out)) is None
     stale = json.loads(out.read_text())
     stale["source_digest"] = "0" * 16
@@ -188,6 +195,8 @@ def test_json_line_contract():
     assert rl["kernel"] == "feed_swim"
     assert d["kernels"]["feed_swim"]["launches"] == 19
     assert d["plain_split"]["value"] > 0 and d["algorithmic_bytes_per_fish_step"] < 44
+    vc = d["valu_ceiling"]
+    assert 0 < vc["fma"] < 2 * vc["nominal"] and 0 < vc["philox"] < 2 * vc["nominal"]
     assert rl["cache_assisted"] is True
     hr = d["roofline_hbm_resident"]
     assert hr["n_fish"] == 1 << 26 and not hr["infinity_cache"]["live_columns_fit"]

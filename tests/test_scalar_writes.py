@@ -12,7 +12,7 @@ SCALAR_WRITES = re.compile(r"^\s*s_(store_|buffer_store|atomic_|buffer_atomic|sc
                            r"dcache_wb|dcache_discard)", re.M)
 
 
-@pytest.mark.parametrize("source", ["fsb_kernels.hip", "fsb_batch.hip"])
+@pytest.mark.parametrize("source", ["fsb_kernels.hip", "fsb_batch.hip", "fsb_probe.hip"])
 def test_no_scalar_memory_writes(source):
     text = open(fsb_build.assembly(source)).read()
     assert re.search(r"^_Z\w+:", text, re.M), f"no kernel found in the assembly of {source}"
