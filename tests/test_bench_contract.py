@@ -4,6 +4,7 @@ kernels' VALU instruction counts and their "alu" roofline, the digests that
 void stale figures, and (on a GPU) the shape of the JSON line."""
 import csv
 import json
+import re
 import os
 import subprocess
 import sys
@@ -227,3 +228,28 @@ def test_deep_depth_follows_the_library_rule(monkeypatch):
     assert bench.deep_depth(1 << 26) == 4
     header = open(os.path.join(os.path.dirname(__file__), "..", "include", "fsb.h")).read()
     assert "5 x 2^20" in header
+
+
+def test_counter_names_match_the_built_kernels():
+    """The instance names the counter ingestion looks for (plain kernels at
+    2^24 and 2^26, the deep kernels' counter keys) are kernels the library
+    really builds, as the profiler prints them (demangled)."""
+    import shutil
+
+    from paper_2507_20173_amd import build as fsb_build
+    filt = shutil.which("c++filt")
+    if filt is None:
+        pytest.skip("no c++filt")
+    symbols = []
+    for source in ("fsb_kernels.hip", "fsb_batch.hip"):
+        text = open(fsb_build.assembly(source)).read()
+        symbols += re.findall(r"^(_Z\w+):", text, re.M)
+    out = subprocess.run([filt], input="\n".join(symbols), capture_output=True, text=True,
+                         check=True).stdout
+    names = [ln.split("(")[0].replace("void fsb::", "") for ln in out.splitlines()]
+    wanted = list(bench.plain_kernel_names(1 << 24).values())
+    wanted += list(bench.plain_kernel_names(1 << 26).values())
+    wanted += [k for k, _ in bench.DEEP_COUNTER_KERNELS.values()]
+    wanted.append(bench.BATCH_DEEP_COUNTER_KERNEL)
+    for w in wanted:
+        assert w in names, w
