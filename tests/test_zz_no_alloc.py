@@ -46,8 +46,8 @@ def _check(cfg, t0, n_steps, mode, a, b):
         assert np.array_equal(b[k].cpu().numpy().view(np.uint32), st[k].view(np.uint32)), k
 
 
-@pytest.mark.parametrize("mode", [fsb.FSB_RUN_PLAIN, fsb.FSB_RUN_FUSED],
-                         ids=["plain", "persistent"])
+@pytest.mark.parametrize("mode", [fsb.FSB_RUN_PLAIN, fsb.FSB_RUN_PLAIN_SPLIT, fsb.FSB_RUN_FUSED],
+                         ids=["plain", "split", "persistent"])
 def test_static_matches_handle_two_calls(mode):
     print(f"\nfsb_run_static mode={mode}: call 1 n=1048579, call 2 n=4099", flush=True)
     # call 1: a larger school, several grid strides and a ragged tail
