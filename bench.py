@@ -121,6 +121,28 @@ def valu_ceiling(waves_per_simd: int = 8, reps: int = 3) -> dict:
     return out
 
 
+def sweep_ceiling(n: int, reps: int = 3) -> dict:
+    """The copy rate of the plain kernels' access pattern on a school of n
+    fish: fsb_sweep_probe reads and writes four columns of n floats in place
+    once (32 B per fish, the pipelined pass's traffic, without its arithmetic)
+    on the plain passes' grid, cached or streamed as the library's footprint
+    rule would take them; the best of `reps` launches."""
+    import torch
+
+    import paper_2507_20173_amd as fsb
+
+    cols = [torch.zeros(n, dtype=torch.float32, device="cuda") for _ in range(4)]
+    streamed = 16 * n > INFINITY_CACHE_MIB << 20
+    fsb.fsb_sweep_probe(cols, 0, streamed)
+    best = min(fsb.fsb_sweep_probe(cols, 0, streamed) for _ in range(reps))
+    del cols
+    torch.cuda.empty_cache()
+    return {"achieved_GBs": 32 * n / (best / 1e3) / 1e9, "n_fish": n, "streamed": streamed,
+            "note": "in-place read and write of four float32 columns, 512 blocks of 256 "
+                    "threads, one float4 group per thread per round: the pipelined pass's "
+                    "access pattern without its arithmetic"}
+
+
 def valu_roofline(key: str, fish_iterations: float, kernel_s: float, path: str = VALU_FILE):
     """The "alu" roofline of a deep form: its lane instructions (the committed
     count per fish-iteration, if taken from the current sources) over its
@@ -982,6 +1004,7 @@ def main() -> int:
     dom = dominant(kernels)
     dk = kernels[dom]
     traffic = measured_traffic(dom, n)
+    pattern = sweep_ceiling(n)
     residency = cache_residency(n)
     line = {
         "metric": "fish-updates/sec (N x steps/s) on 1 MI355X + % of HBM peak; fused vs plain",
@@ -1005,6 +1028,8 @@ def main() -> int:
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk["achieved_GBs"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dk["achieved_GBs"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "pattern_ceiling": pattern,
+                     "frac_of_pattern_ceiling": dk["achieved_GBs"] / pattern["achieved_GBs"],
                      "cache_assisted": residency["live_columns_fit"],
                      "note": "algorithmic bytes / event-timed duration; the reused columns fit "
                              "the 256 MiB Infinity Cache at this size, so part of the traffic "
@@ -1030,11 +1055,14 @@ def main() -> int:
         hbm_steps = min(args.steps, 200)
         wall_h, kernels_h, _ = plain_run(n_hbm, hbm_steps, min(args.warmup, 5))
         dom_h = dominant(kernels_h)
+        pattern_h = sweep_ceiling(n_hbm)
         wall_hs, kernels_hs, _ = plain_run(n_hbm, hbm_steps, min(args.warmup, 5), split=True)
         line["roofline_hbm_resident"] = {
             "bound": "hbm", "kernel": dom_h, "n_fish": n_hbm, "iterations": hbm_steps,
             "achieved": kernels_h[dom_h]["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": kernels_h[dom_h]["achieved_GBs"] / HBM_PEAK_GBS,
+            "pattern_ceiling": pattern_h,
+            "frac_of_pattern_ceiling": kernels_h[dom_h]["achieved_GBs"] / pattern_h["achieved_GBs"],
             "whole_step_frac": plain_bytes(n_hbm, hbm_steps) / wall_h / 1e9 / HBM_PEAK_GBS,
             "ms_per_step": wall_h / hbm_steps * 1e3, "kernels": kernels_h,
             "split": {"swim_frac": kernels_hs["swim_eval"]["achieved_GBs"] / HBM_PEAK_GBS,

@@ -476,6 +476,19 @@ int fsb_eval_sqrt(const float *in, float *out, uint64_t n, void *stream);
 int fsb_valu_probe(uint32_t kind, uint32_t blocks, uint32_t iters, void *out, size_t out_bytes,
                    void *stream, double *out_ms, uint64_t *out_lane_instructions);
 
+/* Streaming probe (instrumentation; the copy rate of the plain kernels' own
+ * access pattern, against which their bandwidth is judged): the four device
+ * columns cols[0..3] of n floats each (n a positive multiple of 4, each
+ * 16-byte aligned) are read and written in place once, as float4 groups, one
+ * group per thread per round on `grid` blocks of 256 threads (0: 512, the
+ * plain passes' grid), every float gaining 1.0f: 32 B per group of four
+ * elements, the pipelined pass's traffic.  streamed != 0 makes every access
+ * non-temporal.  Synchronises the stream; *out_ms gets the launch's duration
+ * by HIP events.  FSB_ERR_INVALID_ARG for NULL or misaligned pointers or a
+ * bad n. */
+int fsb_sweep_probe(float *cols[4], uint64_t n, uint32_t grid, uint32_t streamed, void *stream,
+                    double *out_ms);
+
 #ifdef __cplusplus
 }
 #endif

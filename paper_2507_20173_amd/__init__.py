@@ -297,6 +297,20 @@ def fsb_valu_probe(kind: int, blocks: int, iters: int, out, stream=None) -> tupl
     return ms.value, lanes.value
 
 
+def fsb_sweep_probe(cols, grid: int = 0, streamed: bool = False, stream=None) -> float:
+    """Milliseconds of one streaming probe launch over four equal float32
+    device tensors (read and written in place; each element gains 1)."""
+    import torch
+    assert len(cols) == 4 and all(c.dtype == torch.float32 and c.is_contiguous() for c in cols)
+    n = cols[0].numel()
+    assert all(c.numel() == n for c in cols)
+    s = torch.cuda.current_stream().cuda_stream if stream is None else stream
+    arr = (ctypes.c_void_p * 4)(*[_ptr(c) for c in cols])
+    ms = ctypes.c_double()
+    check(lib().fsb_sweep_probe(arr, n, grid, int(streamed), s, ctypes.byref(ms)))
+    return ms.value
+
+
 def fsb_batch_profile_enable(b, every: int = 1) -> None:
     """Time every `every`-th launch (0 = off)."""
     check(lib().fsb_batch_profile_enable(b, int(every)))

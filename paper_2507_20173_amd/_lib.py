@@ -125,6 +125,7 @@ PROTOTYPES = {
     "fsb_eval_sqrt": (_I, [_P, _P, _U64, _P]),
     "fsb_valu_probe": (_I, [_U32, _U32, _U32, _P, ctypes.c_size_t, _P, _DP,
                            ctypes.POINTER(_U64)]),
+    "fsb_sweep_probe": (_I, [ctypes.POINTER(_P), _U64, _U32, _U32, _P, _DP]),
     "fsb_batch_kernel_times": (_I, [_P, ctypes.POINTER(_U64), _DP]),
 }
 

@@ -620,6 +620,34 @@ int fsb_valu_probe(uint32_t kind, uint32_t blocks, uint32_t iters, void* out, si
     return FSB_OK;
 }
 
+int fsb_sweep_probe(float* cols[4], uint64_t n, uint32_t grid, uint32_t streamed, void* stream,
+                    double* out_ms) {
+    if (!cols || !out_ms) return fail(FSB_ERR_INVALID_ARG, "NULL argument");
+    if (n == 0 || n % 4) return fail(FSB_ERR_INVALID_ARG, "n must be a positive multiple of 4");
+    for (int k = 0; k < 4; ++k) {
+        if (!cols[k]) return fail(FSB_ERR_INVALID_ARG, "NULL column");
+        if (!aligned(cols[k], 16)) return fail(FSB_ERR_INVALID_ARG, "columns must be 16-byte aligned");
+    }
+    if (grid == 0) grid = 512;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = FSB_OK;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = launch_sweep_probe(cols, n, grid, streamed != 0, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) rc = hip_fail(e, "sweep probe");
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    *out_ms = ms;
+    return FSB_OK;
+}
+
 int fsb_eval_sqrt(const float* in, float* out, uint64_t n, void* stream) {
     if (n == 0) return FSB_OK;
     if (!in || !out) return fail(FSB_ERR_INVALID_ARG, "NULL array");

@@ -1,6 +1,6 @@
 // fsb_probe.hip -- instrumentation kernels that measure the chip rather than
 // the method: the plain-VALU ceiling the VALU-bound persistent kernels are
-// compared with.  Kept out of the kernels' own translation unit, so that the
+// compared with, and the streaming rate of the plain kernels' access pattern.  Kept out of the kernels' own translation unit, so that the
 // measured kernels' code (and the digests that key their counter summaries)
 // does not change with it.
 #include "fsb_device.hpp"
@@ -22,6 +22,24 @@ namespace fsb {
 constexpr uint32_t kProbeFma = 0, kProbePhilox = 1;
 constexpr int kProbeCounters = 2;
 constexpr int kBlock = kProbeThreads;
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+template <bool kNT>
+__device__ __forceinline__ float4 ldv4(const float* p, uint64_t g) {
+    const v4f* q = reinterpret_cast<const v4f*>(p) + g;
+    v4f v;
+    if constexpr (kNT) v = __builtin_nontemporal_load(q); else v = *q;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+template <bool kNT>
+__device__ __forceinline__ void stv4(float* p, uint64_t g, float4 v) {
+    v4f* q = reinterpret_cast<v4f*>(p) + g;
+    const v4f w = {v.x, v.y, v.z, v.w};
+    if constexpr (kNT) __builtin_nontemporal_store(w, q); else *q = w;
+}
+__device__ __forceinline__ float4 plus1(float4 v) {
+    return make_float4(v.x + 1.0f, v.y + 1.0f, v.z + 1.0f, v.w + 1.0f);
+}
 
 __global__ __launch_bounds__(kBlock) void valu_probe_fma_kernel(float* out, uint32_t iters,
                                                                  float b, float c) {
@@ -53,6 +71,38 @@ __global__ __launch_bounds__(kBlock) void valu_probe_philox_kernel(uint32_t* out
 #pragma unroll
     for (int j = 0; j < kProbeCounters; ++j) acc ^= w[j].r0 ^ w[j].r1 ^ w[j].r2 ^ w[j].r3;
     out[(size_t)blockIdx.x * kBlock + threadIdx.x] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Streaming probe (instrumentation): the plain kernels' access pattern without
+// their arithmetic.  Four float32 columns of n floats are read and written in
+// place as float4 groups, one group per thread per round, grid-stride (each
+// float gains 1.0f, so nothing is dead): 32 B per group of four fish, as the
+// pipelined pass moves.  kNT streams every access past the caches.
+// ---------------------------------------------------------------------------
+template <bool kNT>
+__global__ __launch_bounds__(kBlock) void sweep_probe_kernel(float* c0, float* c1, float* c2,
+                                                              float* c3, uint64_t n4) {
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g < n4; g += stride) {
+        float4 a = ldv4<kNT>(c0, g), b = ldv4<kNT>(c1, g), c = ldv4<kNT>(c2, g), d = ldv4<kNT>(c3, g);
+        stv4<kNT>(c0, g, plus1(a));
+        stv4<kNT>(c1, g, plus1(b));
+        stv4<kNT>(c2, g, plus1(c));
+        stv4<kNT>(c3, g, plus1(d));
+    }
+}
+
+hipError_t launch_sweep_probe(float* const cols[4], uint64_t n, uint32_t grid, bool streamed,
+                              hipStream_t stream) {
+    const uint64_t n4 = n / 4;
+    if (streamed)
+        hipLaunchKernelGGL(sweep_probe_kernel<true>, dim3(grid), dim3(kBlock), 0, stream, cols[0],
+                           cols[1], cols[2], cols[3], n4);
+    else
+        hipLaunchKernelGGL(sweep_probe_kernel<false>, dim3(grid), dim3(kBlock), 0, stream, cols[0],
+                           cols[1], cols[2], cols[3], n4);
+    return hipGetLastError();
 }
 
 hipError_t launch_valu_probe(uint32_t kind, uint32_t blocks, uint32_t iters, void* out,

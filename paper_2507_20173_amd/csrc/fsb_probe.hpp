@@ -12,5 +12,10 @@ namespace fsb {
 constexpr uint32_t kProbeThreads = 256;
 hipError_t launch_valu_probe(uint32_t kind, uint32_t blocks, uint32_t iters, void* out,
                              hipStream_t stream);
+// Streaming probe (instrumentation): four columns of n floats (n a multiple
+// of 4, 16-byte aligned) read and written in place once, on `grid` blocks of
+// 256 threads; streamed: non-temporal accesses.
+hipError_t launch_sweep_probe(float* const cols[4], uint64_t n, uint32_t grid, bool streamed,
+                              hipStream_t stream);
 
 }  // namespace fsb

@@ -305,3 +305,24 @@ def test_valu_probe_rejects_before_any_hip_call(case):
     rc = lib.fsb_valu_probe(args["kind"], args["blocks"], args["iters"], args["out"],
                             args["out_bytes"], None, args["ms"], args["lanes"])
     assert rc == _lib.FSB_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("case", ["null_cols", "null_col", "misaligned", "n_zero", "n_ragged",
+                                  "null_ms"])
+def test_sweep_probe_rejects_before_any_hip_call(case):
+    lib = _lib.lib()
+    ms = ctypes.c_double()
+    ptrs = [FAKE + k * (1 << 20) for k in range(4)]
+    n, out = 1024, ctypes.byref(ms)
+    if case == "null_col":
+        ptrs[2] = 0
+    elif case == "misaligned":
+        ptrs[1] += 4
+    elif case == "n_zero":
+        n = 0
+    elif case == "n_ragged":
+        n = 1026
+    elif case == "null_ms":
+        out = None
+    cols = None if case == "null_cols" else (ctypes.c_void_p * 4)(*ptrs)
+    assert lib.fsb_sweep_probe(cols, n, 0, 0, None, out) == _lib.FSB_ERR_INVALID_ARG

@@ -196,10 +196,14 @@ def test_json_line_contract():
     assert rl["kernel"] == "feed_swim"
     assert d["kernels"]["feed_swim"]["launches"] == 19
     assert d["plain_split"]["value"] > 0 and d["algorithmic_bytes_per_fish_step"] < 44
+    pc = rl["pattern_ceiling"]
+    assert 0 < pc["achieved_GBs"] < 2 * 8000 and 0 < rl["frac_of_pattern_ceiling"] < 1.5
+    assert not pc["streamed"]
     vc = d["valu_ceiling"]
     assert 0 < vc["fma"] < 2 * vc["nominal"] and 0 < vc["philox"] < 2 * vc["nominal"]
     assert rl["cache_assisted"] is True
     hr = d["roofline_hbm_resident"]
+    assert hr["pattern_ceiling"]["streamed"] and 0 < hr["frac_of_pattern_ceiling"] < 1.5
     assert hr["n_fish"] == 1 << 26 and not hr["infinity_cache"]["live_columns_fit"]
     assert hr["kernel"] == "feed_swim" and 0 < hr["frac"] < 1
     assert 0 < hr["split"]["swim_frac"] < 1 and 0 < hr["split"]["feed_frac"] < 1

@@ -1,6 +1,9 @@
-"""The VALU ceiling probe: its chains compute what they claim (checked against
-closed forms and the oracle's Philox), and the rates it reports are those of
-a chip that issues at most a few vector instructions per SIMD and cycle."""
+"""The instrumentation probes.  The VALU ceiling probe: its chains compute
+what they claim (checked against closed forms and the oracle's Philox), and
+the rates it reports are those of a chip that issues at most a few vector
+instructions per SIMD and cycle.  The streaming probe: every element of its
+four columns is read and written once per launch, and its rate is below the
+memory's peak."""
 import numpy as np
 import pytest
 
@@ -76,3 +79,16 @@ def test_probe_rejects_bad_arguments(torch_cuda):
     for kind, blocks, iters in ((2, 1, 1), (0, 0, 1), (0, 1, 0)):
         with pytest.raises(fsb.FsbError):
             fsb.fsb_valu_probe(kind, blocks, iters, out)
+
+
+@pytest.mark.parametrize("n,streamed", [(4096, False), ((1 << 22) + 4, True), (1 << 24, False)])
+def test_sweep_probe_touches_every_element_once(torch_cuda, n, streamed):
+    torch = torch_cuda
+    cols = [torch.full((n,), float(k), dtype=torch.float32, device="cuda") for k in range(4)]
+    ms = fsb.fsb_sweep_probe(cols, 0, streamed)
+    ms += fsb.fsb_sweep_probe(cols, 0, streamed)
+    for k, c in enumerate(cols):
+        assert torch.equal(c, torch.full_like(c, k + 2.0)), k
+    rate = 2 * 32 * n / (ms / 1e3) / 1e9
+    print(f"[probe] sweep n={n} streamed={streamed}: {rate:.0f} GB/s", flush=True)
+    assert ms > 0 and (n < 1 << 20 or rate < 2 * 8000)
