@@ -95,8 +95,9 @@ MEASURED_VALU = None
 
 def valu_ceiling(waves_per_simd: int = 8, reps: int = 3) -> dict:
     """Measured plain-VALU ceilings: fsb_valu_probe's independent chains of
-    v_fma_f32 and of Philox4x32-10 calls (v_mad_u64_u32 + v_bitop3_b32) on
-    every SIMD, `waves_per_simd` waves each; the best of `reps` launches."""
+    v_fma_f32, of Philox4x32-10 calls (v_mad_u64_u32 + v_bitop3_b32) and of
+    both mixed, on every SIMD, `waves_per_simd` waves each; the best of `reps`
+    launches."""
     import torch
 
     import paper_2507_20173_amd as fsb
@@ -106,14 +107,15 @@ def valu_ceiling(waves_per_simd: int = 8, reps: int = 3) -> dict:
     out = {"unit": "T lane-instructions/s", "waves_per_simd": waves_per_simd,
            "nominal": VALU_LANE_PEAK / 1e12}
     for name, kind, iters in (("fma", fsb.FSB_PROBE_FMA, 4096),
-                              ("philox", fsb.FSB_PROBE_PHILOX, 512)):
+                              ("philox", fsb.FSB_PROBE_PHILOX, 512),
+                              ("mixed", fsb.FSB_PROBE_MIXED, 512)):
         fsb.fsb_valu_probe(kind, blocks, 64, buf)
         best = 0.0
         for _ in range(reps):
             ms, lanes = fsb.fsb_valu_probe(kind, blocks, iters, buf)
             best = max(best, lanes / (ms / 1e3))
         out[name] = best / 1e12
-    out["ceiling"] = max(out["fma"], out["philox"])
+    out["ceiling"] = max(out["fma"], out["philox"], out["mixed"])
     out["note"] = ("single-issue chains of one instruction kind; under such load the clock "
                    "runs near 2.0-2.1 GHz, not 2.4 (GRBM_GUI_ACTIVE cycles per ns), and "
                    "kernels mixing kinds can exceed it by dual issue")

@@ -464,7 +464,8 @@ int fsb_eval_sqrt(const float *in, float *out, uint64_t n, void *stream);
  * vector instruction (FSB_PROBE_FMA: 8 v_fma_f32 per round; FSB_PROBE_PHILOX:
  * one Philox4x32-10 call, as the kernels draw them, on each of 2 counters,
  * 2 v_mad_u64_u32 and 2 v_bitop3_b32 per Philox round, 80 per round of the
- * probe).  out: device memory of at least
+ * probe; FSB_PROBE_MIXED: one Philox call and 40 v_fma_f32, the integer and
+ * float mix of the kernels' swims, 80 per round).  out: device memory of at least
  * blocks x 256 x 4 bytes, overwritten with one word per lane (keeps the
  * chains live).  Synchronises the stream; *out_ms gets the launch's duration
  * by HIP events and *out_lane_instructions the lane instructions it issued
@@ -472,7 +473,8 @@ int fsb_eval_sqrt(const float *in, float *out, uint64_t n, void *stream);
  * kind, zero blocks or iters, NULL or misaligned pointers, or out too small. */
 #define FSB_PROBE_FMA 0u
 #define FSB_PROBE_PHILOX 1u
-#define FSB_PROBE_KINDS 2u
+#define FSB_PROBE_MIXED 2u
+#define FSB_PROBE_KINDS 3u
 int fsb_valu_probe(uint32_t kind, uint32_t blocks, uint32_t iters, void *out, size_t out_bytes,
                    void *stream, double *out_ms, uint64_t *out_lane_instructions);
 

@@ -18,7 +18,7 @@ from ._lib import (FSB_KERNEL_FEED_BARY, FSB_KERNEL_FEED_SWIM, FSB_KERNEL_FUSED,
                    FSB_REDUCE_CRITICAL_F32, FSB_REDUCE_NAIVE_F32, FSB_RUN_FUSED,
                    FSB_RUN_FUSED_DEEP, FSB_RUN_FUSED_LEAN, FSB_RUN_FUSED_PREV,
                    FSB_RUN_FUSED_REGS, FSB_RUN_PLAIN, FSB_RUN_PLAIN_SPLIT,
-                   FSB_PROBE_FMA, FSB_PROBE_KINDS, FSB_PROBE_PHILOX,
+                   FSB_PROBE_FMA, FSB_PROBE_KINDS, FSB_PROBE_MIXED, FSB_PROBE_PHILOX,
                    FSB_SCHED_DYNAMIC, FSB_SCHED_GUIDED, FSB_SCHED_STATIC, FSB_SWIM_GREEDY,
                    FSB_SWIM_WEIGHTED,
                    FsbError, check, lib)

@@ -42,7 +42,8 @@ FSB_KERNEL_FEED_SWIM = 4
 FSB_KERNEL_KINDS = 5
 FSB_PROBE_FMA = 0
 FSB_PROBE_PHILOX = 1
-FSB_PROBE_KINDS = 2
+FSB_PROBE_MIXED = 2
+FSB_PROBE_KINDS = 3
 
 
 class fsb_config(ctypes.Structure):

@@ -593,7 +593,7 @@ int fsb_valu_probe(uint32_t kind, uint32_t blocks, uint32_t iters, void* out, si
                    void* stream, double* out_ms, uint64_t* out_lane_instructions) {
     // Vector instructions per lane and round of each probe kind (the assembly
     // of the probe kernels is checked for exactly these).
-    static const uint64_t per_round[FSB_PROBE_KINDS] = {8, 80};
+    static const uint64_t per_round[FSB_PROBE_KINDS] = {8, 80, 80};
     if (kind >= FSB_PROBE_KINDS) return fail(FSB_ERR_INVALID_ARG, "unknown probe kind");
     if (blocks == 0 || iters == 0) return fail(FSB_ERR_INVALID_ARG, "blocks and iters must be >= 1");
     if (!out || !out_ms || !out_lane_instructions) return fail(FSB_ERR_INVALID_ARG, "NULL argument");

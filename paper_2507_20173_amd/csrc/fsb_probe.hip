@@ -18,8 +18,10 @@ namespace fsb {
 //                 counters fed back as the next counter: per call and round
 //                 2 v_mad_u64_u32 and 2 v_bitop3_b32 (the key schedule is
 //                 uniform and stays on the scalar unit)
+//   kProbeMixed   80: one Philox4x32-10 call (40) and 40 v_fma_f32 (8 chains,
+//                 5 each), the integer and float mix of the kernels' swims
 // ---------------------------------------------------------------------------
-constexpr uint32_t kProbeFma = 0, kProbePhilox = 1;
+constexpr uint32_t kProbeFma = 0, kProbePhilox = 1, kProbeMixed = 2;
 constexpr int kProbeCounters = 2;
 constexpr int kBlock = kProbeThreads;
 
@@ -73,6 +75,26 @@ __global__ __launch_bounds__(kBlock) void valu_probe_philox_kernel(uint32_t* out
     out[(size_t)blockIdx.x * kBlock + threadIdx.x] = acc;
 }
 
+__global__ __launch_bounds__(kBlock) void valu_probe_mixed_kernel(uint32_t* out, uint32_t iters,
+                                                                   uint32_t k0, uint32_t k1,
+                                                                   float b, float c) {
+    Words w = {blockIdx.x * kBlock + threadIdx.x, 7u, iters, 0u};
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (float)(threadIdx.x + j);
+    for (uint32_t i = 0; i < iters; ++i) {
+        w = philox4x32_10(w.r0, w.r1, w.r2, w.r3, k0, k1);
+#pragma unroll
+        for (int r = 0; r < 5; ++r)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = __builtin_fmaf(v[j], b, c);
+    }
+    float acc = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc += v[j];
+    out[(size_t)blockIdx.x * kBlock + threadIdx.x] = w.r0 ^ w.r1 ^ w.r2 ^ w.r3 ^ __float_as_uint(acc);
+}
+
 // ---------------------------------------------------------------------------
 // Streaming probe (instrumentation): the plain kernels' access pattern without
 // their arithmetic.  Four float32 columns of n floats are read and written in
@@ -113,6 +135,9 @@ hipError_t launch_valu_probe(uint32_t kind, uint32_t blocks, uint32_t iters, voi
     else if (kind == kProbePhilox)
         hipLaunchKernelGGL(valu_probe_philox_kernel, dim3(blocks), dim3(kBlock), 0, stream,
                            static_cast<uint32_t*>(out), iters, 0x12345678u, 0x9ABCDEF0u);
+    else if (kind == kProbeMixed)
+        hipLaunchKernelGGL(valu_probe_mixed_kernel, dim3(blocks), dim3(kBlock), 0, stream,
+                           static_cast<uint32_t*>(out), iters, 0x12345678u, 0x9ABCDEF0u, 1.0f, 0.0f);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -60,7 +60,7 @@ def is_deep_plain_swim(name):
 def test_no_contraction_outside_sqrt_and_div(kernels):
     draws_seen = squares_seen = 0
     for name, body in kernels.items():
-        if "valu_probe_fma_kernel" in name:
+        if "valu_probe_fma_kernel" in name or "valu_probe_mixed_kernel" in name:
             continue  # instrumentation: explicit fma chains, no fish state
         fma = count(body, r"\bv_(fma|fmac|mac|mad)_f32|\bv_fma_mix")
         draws = count(body, DRAW_FMA)
@@ -139,10 +139,12 @@ def loop_blocks(body):
 @pytest.mark.parametrize("kernel,per_round", [
     ("valu_probe_fma_kernel", {"v_fma_f32": 8}),
     ("valu_probe_philox_kernel", {"v_mad_u64_u32": 40, "v_bitop3_b32": 40}),
+    ("valu_probe_mixed_kernel", {"v_mad_u64_u32": 20, "v_bitop3_b32": 20, "v_fma_f32": 40}),
 ])
 def test_valu_probe_loops(kernels, kernel, per_round):
     """The probe's loop holds the vector instructions fsb_valu_probe counts
-    (FSB_PROBE_FMA 8, FSB_PROBE_PHILOX 80 per round) and no others."""
+    (FSB_PROBE_FMA 8, FSB_PROBE_PHILOX and FSB_PROBE_MIXED 80 per round) and no
+    others."""
     (body,) = [b for n, b in kernels.items() if kernel in n]
     loops = loop_blocks(body)
     assert len(loops) == 1, loops

@@ -201,6 +201,8 @@ def test_json_line_contract():
     assert not pc["streamed"]
     vc = d["valu_ceiling"]
     assert 0 < vc["fma"] < 2 * vc["nominal"] and 0 < vc["philox"] < 2 * vc["nominal"]
+    assert 0 < vc["mixed"] < 2 * vc["nominal"]
+    assert vc["ceiling"] == max(vc["fma"], vc["philox"], vc["mixed"])
     assert rl["cache_assisted"] is True
     hr = d["roofline_hbm_resident"]
     assert hr["pattern_ceiling"]["streamed"] and 0 < hr["frac_of_pattern_ceiling"] < 1.5

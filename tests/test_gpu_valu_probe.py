@@ -55,7 +55,28 @@ def test_philox_chains_match_the_oracle(torch_cuda):
     assert np.array_equal(out.cpu().numpy().view(np.uint32), acc)
 
 
-@pytest.mark.parametrize("kind", [0, 1], ids=["fma", "philox"])
+def test_mixed_chains_match_the_oracle(torch_cuda):
+    """One Philox call per round from counter (lane, 7, iters, 0), beside fma
+    chains that keep their start values; the two folded into one word."""
+    torch = torch_cuda
+    blocks, iters = 2, 5
+    out = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
+    ms, lanes = fsb.fsb_valu_probe(fsb.FSB_PROBE_MIXED, blocks, iters, out)
+    assert lanes == blocks * 256 * iters * 80
+    O = default()
+    n = blocks * 256
+    keys = np.tile(np.array([0x12345678, 0x9ABCDEF0], np.uint32), (n, 1))
+    c = np.stack([np.arange(n, dtype=np.uint32), np.full(n, 7, np.uint32),
+                  np.full(n, iters, np.uint32), np.zeros(n, np.uint32)], 1)
+    for _ in range(iters):
+        c = O.philox(c, keys)
+    tid = np.arange(n) % 256
+    acc = (8 * tid + 28).astype(np.float32).view(np.uint32)
+    want = c[:, 0] ^ c[:, 1] ^ c[:, 2] ^ c[:, 3] ^ acc
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), want)
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2], ids=["fma", "philox", "mixed"])
 def test_rates_are_plausible(torch_cuda, kind):
     """From one wave per SIMD to eight: the rate rises with the waves and stays
     below twice the nominal issue rate (no lane can retire two instructions
@@ -76,7 +97,7 @@ def test_rates_are_plausible(torch_cuda, kind):
 def test_probe_rejects_bad_arguments(torch_cuda):
     torch = torch_cuda
     out = torch.empty(256, dtype=torch.float32, device="cuda")
-    for kind, blocks, iters in ((2, 1, 1), (0, 0, 1), (0, 1, 0)):
+    for kind, blocks, iters in ((3, 1, 1), (0, 0, 1), (0, 1, 0)):
         with pytest.raises(fsb.FsbError):
             fsb.fsb_valu_probe(kind, blocks, iters, out)
 
