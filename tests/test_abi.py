@@ -117,9 +117,14 @@ def test_bad_config_rejected(bad):
     dict(pond_half=2.0 ** 63), dict(pond_half=2.0 ** -126), dict(swim_step=2.0 ** -103),
     dict(w_min=-(2.0 ** 24), w_max=2.0 ** 24, w_init_lo=-(2.0 ** 24), w_init_hi=2.0 ** 24)])
 def test_edge_configs_accepted(edge):
+    # a failing call first: its message is the thread's last error, which a
+    # later success leaves in place ("the last failing call")
+    assert ws_bytes(cfg(history_len=0))[0] == _lib.FSB_ERR_INVALID_ARG
+    before = _lib.lib().fsb_last_error()
+    assert before
     rc, _ = ws_bytes(cfg(**edge))
     assert rc == 0
-    assert _lib.lib().fsb_last_error()
+    assert _lib.lib().fsb_last_error() == before
 
 
 FAKE = 1 << 40  # an aligned address that is never dereferenced
