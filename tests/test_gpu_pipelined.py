@@ -199,3 +199,24 @@ def test_cfg2_pipelined_prefix(torch_cuda, O):
     sch = fsb.School(cfg)
     check_run(O, sch, ocfg, school, 0, steps, what="cfg2 pipelined")
     sch.close()
+
+
+def test_pipelined_record_ring_wraps(torch_cuda, O):
+    """A ring of 3 records over 17 pipelined iterations: each record lands in
+    slot t mod 3 one launch late, and the last three are the oracle's."""
+    announce("record ring of 3")
+    n = 20_003
+    cfg = fsb.FsbConfig(n_fish=n, seed=41, history_len=3)
+    ocfg = oracle_config(cfg)
+    school = O.init(ocfg)
+    m, s, a = O.run(ocfg, school, 0, 17)
+    sch = fsb.School(cfg)
+    sch.run(17)
+    h = sch.history(14, 3)
+    assert np.array_equal(h["step_lo"], np.arange(14, 17))
+    assert np.array_equal(h["max_delta"], m[14:])
+    assert_sums_close(history_sums(h), s[14:], a[14:], what="ring")
+    with pytest.raises(fsb.FsbError):
+        sch.history(13, 1)
+    assert_columns_equal(sch.state(), school, "ring")
+    sch.close()
